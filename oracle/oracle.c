@@ -1,0 +1,526 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the ensemble ODE/SDE hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written for readability against
+ * the paper, not for speed: one trajectory at a time, textbook formulas, no
+ * blocking or fusion.  Trajectories are independent, so an OpenMP loop over
+ * them is the only concession to run time.
+ *
+ * Paper passages followed:
+ *   - ODE problem statement: section 3.1, eq. 1.
+ *   - Explicit Runge-Kutta step with tableau {A, b, c}: section 3.1, eqs. 2-3.
+ *   - Embedded estimate, scaled error q and accept rule q < 1, PI step-size
+ *     control h_new = eta q_{n-1}^{beta2} q_n^{beta1} h: section 3.1, eq. 4.
+ *   - Tsitouras 5(4) pair (GPUTsit5): section 5.2.1.
+ *   - Rosenbrock s-stage method: section 3.2.1, eqs. 5-8; 4th-order stiffly
+ *     stable variant (GPURodas4): section 5.2.1; LU of W per system:
+ *     section 5.1.3, eq. 16.
+ *   - SDE definition dX = a dt + b dW, dW ~ N(0, dt): section 3.3, eq. 11;
+ *     Euler-Maruyama (GPUEM): section 5.2.2.
+ *   - Models: appendix (Lorenz, Robertson, linear SDE).
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NMAX 4
+
+/* ------------------------------------------------------------------------ */
+/* Systems                                                                   */
+/* ------------------------------------------------------------------------ */
+
+int orc_dims(int sys, int *n, int *m) {
+  switch (sys) {
+  case ORC_LINEAR: *n = 3; *m = 9; return 0;
+  case ORC_LORENZ: *n = 3; *m = 3; return 0;
+  case ORC_ROBERTSON: *n = 3; *m = 3; return 0;
+  case ORC_GBM4: *n = 4; *m = 2; return 0;
+  }
+  return -1;
+}
+
+/* Appendix, Lorenz problem: dy1 = sigma (y2 - y1), dy2 = rho y1 - y2 - y1 y3,
+ * dy3 = y1 y2 - beta y3 (the paper writes beta as gamma).
+ * Appendix, Robertson: dy1 = -k1 y1 + k3 y2 y3, dy2 = k1 y1 - k3 y2 y3 - k2 y2^2,
+ * dy3 = k2 y2^2, with (k1, k2, k3) = (0.04, 3e7, 1e4) at the printed rates.
+ * GBM drift (appendix, linear SDE): a(X) = mu X per component.              */
+int orc_rhs(int sys, const double *p, const double *u, double *du) {
+  switch (sys) {
+  case ORC_LINEAR:
+    for (int i = 0; i < 3; i++)
+      du[i] = p[3 * i + 0] * u[0] + p[3 * i + 1] * u[1] + p[3 * i + 2] * u[2];
+    return 0;
+  case ORC_LORENZ: {
+    double sigma = p[0], rho = p[1], beta = p[2];
+    du[0] = sigma * (u[1] - u[0]);
+    du[1] = rho * u[0] - u[1] - u[0] * u[2];
+    du[2] = u[0] * u[1] - beta * u[2];
+    return 0;
+  }
+  case ORC_ROBERTSON: {
+    double k1 = p[0], k2 = p[1], k3 = p[2];
+    du[0] = -k1 * u[0] + k3 * u[1] * u[2];
+    du[1] = k1 * u[0] - k3 * u[1] * u[2] - k2 * u[1] * u[1];
+    du[2] = k2 * u[1] * u[1];
+    return 0;
+  }
+  case ORC_GBM4:
+    for (int i = 0; i < 4; i++) du[i] = p[0] * u[i];
+    return 0;
+  }
+  return -1;
+}
+
+/* J[i][j] = d f_i / d u_j, written out by hand from orc_rhs. */
+int orc_jac(int sys, const double *p, const double *u, double *J) {
+  switch (sys) {
+  case ORC_LINEAR:
+    for (int i = 0; i < 9; i++) J[i] = p[i];
+    return 0;
+  case ORC_LORENZ: {
+    double sigma = p[0], rho = p[1], beta = p[2];
+    J[0] = -sigma;        J[1] = sigma;  J[2] = 0.0;
+    J[3] = rho - u[2];    J[4] = -1.0;   J[5] = -u[0];
+    J[6] = u[1];          J[7] = u[0];   J[8] = -beta;
+    return 0;
+  }
+  case ORC_ROBERTSON: {
+    double k1 = p[0], k2 = p[1], k3 = p[2];
+    J[0] = -k1; J[1] = k3 * u[2];                   J[2] = k3 * u[1];
+    J[3] = k1;  J[4] = -k3 * u[2] - 2.0 * k2 * u[1]; J[5] = -k3 * u[1];
+    J[6] = 0.0; J[7] = 2.0 * k2 * u[1];             J[8] = 0.0;
+    return 0;
+  }
+  case ORC_GBM4:
+    memset(J, 0, 16 * sizeof(double));
+    for (int i = 0; i < 4; i++) J[5 * i] = p[0];
+    return 0;
+  }
+  return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tableaus, written from the primary publications the paper cites.         */
+/* ------------------------------------------------------------------------ */
+
+/* Tsitouras (2011), "Runge-Kutta pairs of order 5(4) satisfying only the first
+ * column simplifying assumption": 7 stages, FSAL (row 7 of A equals b).
+ * TS_BT holds b - bhat, the weights of the embedded error estimate.         */
+static const double TS_C[7] = {0.0, 0.161, 0.327, 0.9, 0.9800255409045097,
+                               1.0, 1.0};
+static const double TS_A[7][7] = {
+    {0, 0, 0, 0, 0, 0, 0},
+    {0.161, 0, 0, 0, 0, 0, 0},
+    {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0, 0},
+    {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0, 0},
+    {5.325864828439257, -11.748883564062828, 7.4955393428898365,
+     -0.09249506636175525, 0, 0, 0},
+    {5.86145544294642, -12.92096931784711, 8.159367898576159,
+     -0.071584973281401, -0.028269050394068383, 0, 0},
+    {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742,
+     -3.290069515436081, 2.324710524099774, 0}};
+static const double TS_BT[7] = {
+    -0.00178001105222577714, -0.0008164344596567469, 0.007880878010261995,
+    -0.1447110071732629,     0.5823571654525552,     -0.45808210592918697,
+    0.015151515151515152};
+
+/* RODAS4 of Hairer & Wanner, "Solving ODEs II", section IV.7, in the
+ * transformed variables U_i = sum_j gamma_ij k_j, for which one stage reads
+ *   (I/(gamma h) - J) U_i = f(u + sum_{j<i} a_ij U_j) + sum_{j<i} (C_ij / h) U_j.
+ * Solution u + sum m_j U_j, embedded u + sum mhat_j U_j.  Stiffly accurate:
+ * the 6th stage point is the embedded solution and U_6 is the error.       */
+static const double RO_GAMMA = 0.25;
+static const double RO_A[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.544, 0, 0, 0, 0, 0},
+    {0.9466785280815826, 0.2557011698983284, 0, 0, 0, 0},
+    {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087,
+     -0.6878860361058950, 0, 0},
+    {1.221224509226641, 6.019134481288629, 12.53708332932087,
+     -0.6878860361058950, 1.0, 0}};
+static const double RO_C[6][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {-5.6688, 0, 0, 0, 0, 0},
+    {-2.430093356833875, -0.2063599157091915, 0, 0, 0, 0},
+    {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0, 0},
+    {7.496443313967647, -10.24680431464352, -33.99990352819905,
+     11.70890893206160, 0, 0},
+    {8.083246795921522, -7.981132988064893, -31.52159432874371,
+     16.31930543123136, -6.058818238834054, 0}};
+static const double RO_M[6] = {1.221224509226641, 6.019134481288629,
+                               12.53708332932087, -0.6878860361058950, 1.0,
+                               1.0};
+static const double RO_MHAT[6] = {1.221224509226641, 6.019134481288629,
+                                  12.53708332932087, -0.6878860361058950, 1.0,
+                                  0.0};
+
+void orc_tsit5_tableau(double c[7], double a[49], double b[7],
+                       double btilde[7]) {
+  for (int i = 0; i < 7; i++) {
+    c[i] = TS_C[i];
+    b[i] = TS_A[6][i];
+    btilde[i] = TS_BT[i];
+    for (int j = 0; j < 7; j++) a[7 * i + j] = TS_A[i][j];
+  }
+}
+
+void orc_rodas4_tableau(double *gamma, double a[36], double C[36],
+                        double m[6], double mhat[6]) {
+  *gamma = RO_GAMMA;
+  for (int i = 0; i < 6; i++) {
+    m[i] = RO_M[i];
+    mhat[i] = RO_MHAT[i];
+    for (int j = 0; j < 6; j++) {
+      a[6 * i + j] = RO_A[i][j];
+      C[6 * i + j] = RO_C[i][j];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One step of each method.  All systems are autonomous.                     */
+/* ------------------------------------------------------------------------ */
+
+/* Explicit RK step (eqs. 2-3) with the Tsit5 tableau.  k1 = f(u) on entry
+ * (first-same-as-last).  Writes unew, the error vector err = h sum btilde_j k_j
+ * (= unew - uhat) and k7 = f(unew).                                          */
+static void tsit5_step(int sys, const double *p, int n, const double *u,
+                       const double *k1, double h, double *unew, double *err,
+                       double *k7) {
+  double k[7][NMAX], y[NMAX];
+  for (int c = 0; c < n; c++) k[0][c] = k1[c];
+  for (int i = 1; i < 7; i++) {
+    for (int c = 0; c < n; c++) {
+      double s = 0.0;
+      for (int j = 0; j < i; j++) s += TS_A[i][j] * k[j][c];
+      y[c] = u[c] + h * s;
+    }
+    orc_rhs(sys, p, y, k[i]);
+  }
+  for (int c = 0; c < n; c++) {
+    double s = 0.0;
+    for (int j = 0; j < 7; j++) s += TS_BT[j] * k[j][c];
+    unew[c] = y[c]; /* stage-7 point = u + h sum b_j k_j */
+    err[c] = h * s;
+    k7[c] = k[6][c];
+  }
+}
+
+/* LU factorisation with partial pivoting of the n x n row-major matrix W. */
+static void lu_factor(int n, double *W, int *piv) {
+  for (int k = 0; k < n; k++) {
+    int pr = k;
+    for (int i = k + 1; i < n; i++)
+      if (fabs(W[i * n + k]) > fabs(W[pr * n + k])) pr = i;
+    piv[k] = pr;
+    if (pr != k)
+      for (int j = 0; j < n; j++) {
+        double t = W[k * n + j];
+        W[k * n + j] = W[pr * n + j];
+        W[pr * n + j] = t;
+      }
+    for (int i = k + 1; i < n; i++) {
+      W[i * n + k] /= W[k * n + k];
+      for (int j = k + 1; j < n; j++) W[i * n + j] -= W[i * n + k] * W[k * n + j];
+    }
+  }
+}
+
+/* Solve (LU) x = b in place, applying the recorded row swaps first. */
+static void lu_solve(int n, const double *LU, const int *piv, double *x) {
+  for (int k = 0; k < n; k++)
+    if (piv[k] != k) {
+      double t = x[k];
+      x[k] = x[piv[k]];
+      x[piv[k]] = t;
+    }
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < i; j++) x[i] -= LU[i * n + j] * x[j];
+  for (int i = n - 1; i >= 0; i--) {
+    for (int j = i + 1; j < n; j++) x[i] -= LU[i * n + j] * x[j];
+    x[i] /= LU[i * n + i];
+  }
+}
+
+/* Rosenbrock step (eqs. 5-8) in the transformed form stated above the
+ * tableau: one Jacobian, one LU of W = I/(gamma h) - J, six solves.        */
+static void rodas4_step(int sys, const double *p, int n, const double *u,
+                        double h, double *unew, double *err) {
+  double J[NMAX * NMAX], W[NMAX * NMAX], U[6][NMAX], y[NMAX], fy[NMAX];
+  int piv[NMAX];
+  orc_jac(sys, p, u, J);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++)
+      W[i * n + j] = (i == j ? 1.0 / (RO_GAMMA * h) : 0.0) - J[i * n + j];
+  lu_factor(n, W, piv);
+  for (int i = 0; i < 6; i++) {
+    for (int c = 0; c < n; c++) {
+      double s = 0.0;
+      for (int j = 0; j < i; j++) s += RO_A[i][j] * U[j][c];
+      y[c] = u[c] + s;
+    }
+    orc_rhs(sys, p, y, fy);
+    for (int c = 0; c < n; c++) {
+      double s = 0.0;
+      for (int j = 0; j < i; j++) s += RO_C[i][j] / h * U[j][c];
+      U[i][c] = fy[c] + s;
+    }
+    lu_solve(n, W, piv, U[i]);
+  }
+  for (int c = 0; c < n; c++) {
+    double s = 0.0, e = 0.0;
+    for (int j = 0; j < 6; j++) {
+      s += RO_M[j] * U[j][c];
+      e += (RO_M[j] - RO_MHAT[j]) * U[j][c];
+    }
+    unew[c] = u[c] + s;
+    err[c] = e;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive driver                                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Scaled error proportion q of eq. 4, taking the norm as the root mean square
+ * over the n components (Hairer, Norsett & Wanner I, section II.4).        */
+static double error_q(int n, const double *err, const double *u,
+                      const double *unew, double atol, double rtol) {
+  double s = 0.0;
+  for (int c = 0; c < n; c++) {
+    double sc = atol + rtol * fmax(fabs(u[c]), fabs(unew[c]));
+    double r = err[c] / sc;
+    s += r * r;
+  }
+  return sqrt(s / n);
+}
+
+static double rms_scaled(int n, const double *v, const double *sc) {
+  double s = 0.0;
+  for (int c = 0; c < n; c++) s += (v[c] / sc[c]) * (v[c] / sc[c]);
+  return sqrt(s / n);
+}
+
+/* Starting step of Hairer, Norsett & Wanner I, section II.4 (two f calls),
+ * capped by the interval length.  p is the order of the method.            */
+static double initial_step(int sys, const double *pp, int n, const double *u0,
+                           const double *f0, double atol, double rtol, int p,
+                           double hmax) {
+  double sc[NMAX], u1[NMAX], f1[NMAX], df[NMAX];
+  for (int c = 0; c < n; c++) sc[c] = atol + rtol * fabs(u0[c]);
+  double d0 = rms_scaled(n, u0, sc), d1 = rms_scaled(n, f0, sc);
+  double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+  h0 = fmin(h0, hmax);
+  for (int c = 0; c < n; c++) u1[c] = u0[c] + h0 * f0[c];
+  orc_rhs(sys, pp, u1, f1);
+  for (int c = 0; c < n; c++) df[c] = f1[c] - f0[c];
+  double d2 = rms_scaled(n, df, sc) / h0;
+  double dm = fmax(d1, d2);
+  double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
+                            : pow(0.01 / dm, 1.0 / (p + 1));
+  return fmin(fmin(100.0 * h0, h1), hmax);
+}
+
+/* PI controller constants (section 3.1 names eta, beta1, beta2 without
+ * values; taken from Hairer & Wanner's presentation of Gustafsson's PI
+ * controller with k = embedded order + 1).                                 */
+#define PI_ETA 0.9
+#define PI_FMIN 0.2
+#define PI_FMAX 10.0
+#define PI_QFLOOR 1e-4
+
+static void solve_one(int sys, int alg, int n, const double *p,
+                      const double *u0, double t0, double tf, double atol,
+                      double rtol, const double *theta, int n_save,
+                      double *outcol /* [n_save][n] */, int *status,
+                      int64_t *nacc, int64_t *nrej, double h0,
+                      int64_t maxiters) {
+  const double kexp = (alg == ORC_TSIT5) ? 5.0 : 4.0;
+  double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX];
+  double hmax = tf - t0;
+  int j = 0;
+  int64_t acc = 0, rej = 0;
+  *status = ORC_OK;
+  for (int c = 0; c < n; c++) u[c] = u0[c];
+  double t = t0;
+  /* save points that coincide with t0 (only when tf == t0) */
+  while (j < n_save && t0 + theta[j] * (tf - t0) <= t) {
+    for (int c = 0; c < n; c++) outcol[j * n + c] = u[c];
+    j++;
+  }
+  orc_rhs(sys, p, u, k1);
+  double h = h0;
+  if (j < n_save && !(h0 > 0.0))
+    h = initial_step(sys, p, n, u, k1, atol, rtol, alg == ORC_TSIT5 ? 5 : 4,
+                     hmax);
+  h = fmin(h, hmax);
+  double qold = PI_QFLOOR;
+  while (j < n_save) {
+    if (acc + rej >= maxiters) { *status = ORC_MAXITERS; break; }
+    double ts = t0 + theta[j] * (tf - t0);
+    double rem = ts - t;
+    int clamped = (h >= rem);
+    double he = clamped ? rem : h;
+    if (alg == ORC_TSIT5)
+      tsit5_step(sys, p, n, u, k1, he, unew, err, k7);
+    else
+      rodas4_step(sys, p, n, u, he, unew, err);
+    double q = error_q(n, err, u, unew, atol, rtol);
+    if (!isfinite(q)) { *status = ORC_NONFINITE; break; }
+    if (q <= 1.0) {
+      acc++;
+      t = clamped ? ts : t + he;
+      for (int c = 0; c < n; c++) u[c] = unew[c];
+      if (alg == ORC_TSIT5)
+        for (int c = 0; c < n; c++) k1[c] = k7[c];
+      double fac = PI_ETA * pow(fmax(q, 1e-10), -0.7 / kexp) *
+                   pow(qold, 0.4 / kexp);
+      fac = fmin(PI_FMAX, fmax(PI_FMIN, fac));
+      qold = fmax(q, PI_QFLOOR);
+      double hn = he * fac;
+      if (clamped) hn = fmax(hn, h); /* keep the proposal made before the clamp */
+      h = fmin(hn, hmax);
+      while (j < n_save && t0 + theta[j] * (tf - t0) <= t) {
+        for (int c = 0; c < n; c++) outcol[j * n + c] = u[c];
+        j++;
+      }
+    } else {
+      rej++;
+      double fac = fmax(PI_FMIN, PI_ETA * pow(q, -1.0 / kexp));
+      h = he * fac;
+    }
+    if (!(h > 16.0 * DBL_EPSILON * fabs(t))) { *status = ORC_DTMIN; break; }
+  }
+  /* trajectories that stopped early report NaN at the unreached save times */
+  for (; j < n_save; j++)
+    for (int c = 0; c < n; c++) outcol[j * n + c] = NAN;
+  *nacc = acc;
+  *nrej = rej;
+}
+
+int orc_solve(int sys, int alg, int64_t N, const double *params,
+              const double *u0, const double *tspan, double atol,
+              double rtol, const double *theta, int n_save, double *out,
+              int *status, int64_t *naccept, int64_t *nreject, double h0,
+              int64_t maxiters, int nthreads) {
+  int n, m;
+  if (orc_dims(sys, &n, &m) != 0 || sys == ORC_GBM4) return -1;
+  if (alg != ORC_TSIT5 && alg != ORC_RODAS4) return -1;
+  if (N < 0 || n_save < 1 || !params || !u0 || !tspan || !theta || !out)
+    return -1;
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
+  for (int64_t i = 0; i < N; i++) {
+    double p[16], uu[NMAX], col[64 * NMAX];
+    for (int r = 0; r < m; r++) p[r] = params[r * N + i];
+    for (int c = 0; c < n; c++) uu[c] = u0[c * N + i];
+    int st;
+    int64_t a, rj;
+    double *colp = (n_save <= 64) ? col : (double *)malloc(sizeof(double) * n_save * n);
+    solve_one(sys, alg, n, p, uu, tspan[i], tspan[N + i], atol, rtol, theta,
+              n_save, colp, &st, &a, &rj, h0, maxiters);
+    for (int s = 0; s < n_save; s++)
+      for (int c = 0; c < n; c++) out[((int64_t)s * n + c) * N + i] = colp[s * n + c];
+    if (colp != col) free(colp);
+    if (status) status[i] = st;
+    if (naccept) naccept[i] = a;
+    if (nreject) nreject[i] = rj;
+  }
+  return 0;
+}
+
+int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,
+              int n_steps, double *u_out, double *uhat_out) {
+  int n, m;
+  if (orc_dims(sys, &n, &m) != 0) return -1;
+  double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX];
+  for (int c = 0; c < n; c++) u[c] = u0[c];
+  orc_rhs(sys, p, u, k1);
+  for (int s = 0; s < n_steps; s++) {
+    if (alg == ORC_TSIT5)
+      tsit5_step(sys, p, n, u, k1, h, unew, err, k7);
+    else
+      rodas4_step(sys, p, n, u, h, unew, err);
+    if (s == n_steps - 1)
+      for (int c = 0; c < n; c++) uhat_out[c] = unew[c] - err[c];
+    for (int c = 0; c < n; c++) u[c] = unew[c];
+    if (alg == ORC_TSIT5)
+      for (int c = 0; c < n; c++) k1[c] = k7[c];
+  }
+  for (int c = 0; c < n; c++) u_out[c] = u[c];
+  if (n_steps == 0)
+    for (int c = 0; c < n; c++) uhat_out[c] = u[c];
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, Box-Muller and Euler-Maruyama                              */
+/* ------------------------------------------------------------------------ */
+
+/* Salmon, Moraes, Dror & Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+ * (SC'11): Philox4x32 round = two 32x32->64 multiplies and a permutation
+ * with key XOR; Weyl key schedule; 10 rounds.                               */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2],
+                       uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; r++) {
+    uint64_t p0 = (uint64_t)M0 * x0, p1 = (uint64_t)M1 * x2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+    x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Top 23 bits of x mapped to the midpoints (2k + 1) 2^-24, k < 2^23: exact in
+ * single precision, strictly inside (0, 1).                                 */
+double orc_uniform(uint32_t x) {
+  return (double)(2u * (x >> 9) + 1u) * 0x1p-24;
+}
+
+/* Box-Muller: z0 = r cos(2 pi v), z1 = r sin(2 pi v), r = sqrt(-2 ln u). */
+void orc_box_muller(uint32_t x0, uint32_t x1, double *z0, double *z1) {
+  const double two_pi = 6.283185307179586476925287;
+  double u = orc_uniform(x0), v = orc_uniform(x1);
+  double r = sqrt(-2.0 * log(u));
+  *z0 = r * cos(two_pi * v);
+  *z1 = r * sin(two_pi * v);
+}
+
+int orc_em(int sys, int64_t N, const double *params, const double *u0,
+           double dt, int n_steps, uint64_t seed, double *out, int nthreads) {
+  if (sys != ORC_GBM4 || N < 0 || n_steps < 0 || !(dt > 0.0)) return -1;
+  if (nthreads < 1) nthreads = 1;
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const double sqdt = sqrt(dt);
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+  for (int64_t i = 0; i < N; i++) {
+    double mu = params[i], sigma = params[N + i];
+    double X[4];
+    for (int c = 0; c < 4; c++) X[c] = u0[c * N + i];
+    for (int s = 0; s < n_steps; s++) {
+      uint32_t ctr[4] = {(uint32_t)s, (uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u};
+      uint32_t r[4];
+      double z[4];
+      orc_philox4x32_10(ctr, key, r);
+      orc_box_muller(r[0], r[1], &z[0], &z[1]);
+      orc_box_muller(r[2], r[3], &z[2], &z[3]);
+      for (int c = 0; c < 4; c++) {
+        double dW = sqdt * z[c];
+        X[c] = X[c] + mu * X[c] * dt + sigma * X[c] * dW;
+      }
+    }
+    for (int c = 0; c < 4; c++) out[c * N + i] = X[c];
+  }
+  return 0;
+}

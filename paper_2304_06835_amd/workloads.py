@@ -1,0 +1,121 @@
+"""Seeded synthetic ensembles (inputs only; no integration arithmetic here).
+
+Both the GPU path and the CPU oracle are fed from these generators, so that
+they see bit-identical inputs.  Every draw uses numpy's PCG64 with a fixed
+seed.  Arrays follow the library's structure-of-arrays layout: a quantity
+with r rows per trajectory is a C-contiguous [r][N] array (column j of the
+paper's U / P matrices, section 5.1.1, is trajectory j).
+
+Workloads (the paper's models, appendix, with per-trajectory draws):
+  lorenz_fp64   Lorenz, sigma=10, beta=8/3, rho ~ U[0,21], u0=(1,0,0),
+                t in [0,1], Tsit5 atol=rtol=1e-8, final state saved; N=8192.
+  lorenz_fp32   Lorenz, rho ~ U[0,28], u0=(1,0,0)+N(0,0.01^2) per component,
+                t in [0,1], Tsit5 atol=rtol=1e-6, 16 evenly spaced saves
+                (theta_j = (j+1)/16); N=2^24.
+  robertson     Robertson kinetics, (k1,k2,k3) = (0.04, 3e7, 1e4) each scaled
+                by exp(U[ln 0.5, ln 2]), u0=(1,0,0), t0=0, tf = exp(U[0, ln 1e5]),
+                Rodas4 rtol=1e-6 atol=1e-8, h0=1e-4, final state; N=2^20.
+  gbm           4 independent GBM components, mu ~ U[-0.5,0.5],
+                sigma ~ U[0.05,0.5], u0=1, Euler-Maruyama dt=1/256 on [0,1];
+                N=2^22; Philox key 4.
+  surrogate     (rho, u0) draws from lorenz_fp32's distribution: training set
+                2^20 (seed 5), validation 2^16 (seed 6), queries 2^24 (seed 7),
+                audit sample seed 8.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEEDS = {"lorenz_fp64": 1, "lorenz_fp32": 2, "robertson": 3, "gbm": 4,
+         "surr_train": 5, "surr_val": 6, "surr_query": 7, "surr_audit": 8}
+
+FULL_N = {"lorenz_fp64": 8192, "lorenz_fp32": 1 << 24, "robertson": 1 << 20,
+          "gbm": 1 << 22}
+
+
+@dataclass
+class Ensemble:
+    name: str
+    system: str            # "lorenz" | "robertson" | "gbm4" | "linear"
+    alg: str               # "tsit5" | "rodas4" | "em"
+    params: np.ndarray     # [m][N]
+    u0: np.ndarray         # [n][N]
+    tspan: np.ndarray      # [2][N] float64 (t0 row, tf row)
+    theta: np.ndarray      # [n_save] float64, save fractions in (0, 1]
+    abstol: float = 0.0
+    reltol: float = 0.0
+    h0: float = 0.0        # 0: starting-step heuristic
+    dt: float = 0.0        # fixed-step algorithms
+    n_steps: int = 0
+    seed: int = 0          # Philox key for SDEs
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.u0.shape[1]
+
+
+def _rows(*rows, dtype):
+    return np.ascontiguousarray(np.stack(rows), dtype=dtype)
+
+
+def lorenz_fp64(N: int = FULL_N["lorenz_fp64"], seed: int = SEEDS["lorenz_fp64"]):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = rng.uniform(0.0, 21.0, N)
+    params = _rows(np.full(N, 10.0), rho, np.full(N, 8.0 / 3.0), dtype=np.float64)
+    u0 = _rows(np.ones(N), np.zeros(N), np.zeros(N), dtype=np.float64)
+    tspan = _rows(np.zeros(N), np.ones(N), dtype=np.float64)
+    return Ensemble("lorenz_fp64", "lorenz", "tsit5", params, u0, tspan,
+                    np.array([1.0]), abstol=1e-8, reltol=1e-8)
+
+
+def lorenz_draws(N: int, seed: int, dtype=np.float32):
+    """(params [3][N], u0 [3][N]) from the rho ~ U[0,28], u0 ~ (1,0,0)+N(0,0.01^2)
+    distribution, rounded to `dtype`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rho = rng.uniform(0.0, 28.0, N)
+    pert = rng.normal(0.0, 0.01, (3, N))
+    params = _rows(np.full(N, 10.0), rho, np.full(N, 8.0 / 3.0), dtype=dtype)
+    u0 = np.ascontiguousarray(np.array([[1.0], [0.0], [0.0]]) + pert, dtype=dtype)
+    return params, u0
+
+
+def lorenz_fp32(N: int = FULL_N["lorenz_fp32"], seed: int = SEEDS["lorenz_fp32"]):
+    params, u0 = lorenz_draws(N, seed, np.float32)
+    tspan = _rows(np.zeros(N), np.ones(N), dtype=np.float64)
+    theta = (np.arange(16, dtype=np.float64) + 1.0) / 16.0
+    return Ensemble("lorenz_fp32", "lorenz", "tsit5", params, u0, tspan, theta,
+                    abstol=1e-6, reltol=1e-6)
+
+
+def robertson(N: int = FULL_N["robertson"], seed: int = SEEDS["robertson"],
+              dtype=np.float32):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scale = np.exp(rng.uniform(np.log(0.5), np.log(2.0), (3, N)))
+    k = np.array([[0.04], [3e7], [1e4]]) * scale
+    tf = np.exp(rng.uniform(0.0, np.log(1e5), N))
+    params = np.ascontiguousarray(k, dtype=dtype)
+    u0 = _rows(np.ones(N), np.zeros(N), np.zeros(N), dtype=dtype)
+    tspan = _rows(np.zeros(N), tf, dtype=np.float64)
+    return Ensemble("robertson", "robertson", "rodas4", params, u0, tspan,
+                    np.array([1.0]), abstol=1e-8, reltol=1e-6, h0=1e-4)
+
+
+def gbm(N: int = FULL_N["gbm"], seed: int = SEEDS["gbm"]):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = rng.uniform(-0.5, 0.5, N)
+    sigma = rng.uniform(0.05, 0.5, N)
+    params = _rows(mu, sigma, dtype=np.float32)
+    u0 = np.ones((4, N), dtype=np.float32)
+    tspan = _rows(np.zeros(N), np.ones(N), dtype=np.float64)
+    return Ensemble("gbm", "gbm4", "em", params, u0, tspan, np.array([1.0]),
+                    dt=1.0 / 256.0, n_steps=256, seed=seed)
+
+
+def sample_indices(N: int, k: int) -> np.ndarray:
+    """Every (N/k)-th trajectory: the fixed oracle subsample of a large ensemble."""
+    if k >= N:
+        return np.arange(N)
+    return (np.arange(k, dtype=np.int64) * (N // k)).astype(np.int64)
