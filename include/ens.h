@@ -1,0 +1,190 @@
+/*
+ * ens.h -- C ABI of libens.so: ensembles of one small ODE/SDE system solved on
+ * an AMD MI355X (gfx950), one whole trajectory per GPU lane inside one kernel.
+ *
+ * The calls follow the paper's problem statement:
+ *   - du/dt = f(u, p, t), u(t0) = u0, t in (t0, tf)            section 3.1, eq. 1
+ *   - N trajectories = N columns of U (n x N) and P (m x N)    section 5.1.1, eqs. 12-15
+ *   - absolute/relative tolerances of the error control        section 3.1, eq. 4
+ *   - solver choice: GPUTsit5, GPURodas4, GPUEM                section 5.2.1, 5.2.2
+ *   - the whole integration of a trajectory in one kernel,
+ *     saving at requested times                                section 5.2 (EnsembleGPUKernel)
+ *   - a lower-level API on device arrays with no host
+ *     conversions                                              section 6.1
+ *
+ * Conventions shared by every call:
+ *   - Layout: structure of arrays.  A quantity with r rows per trajectory is a
+ *     row-major [r][N] device array; column i (elements k*N + i) belongs to
+ *     trajectory i.  Consecutive lanes touch consecutive addresses.
+ *   - Ownership: every data pointer is owned by the caller.  The library never
+ *     allocates, frees or retains caller memory beyond the call; the context
+ *     owns only a small device workspace (queue counters) allocated at
+ *     ens_create.
+ *   - Streams: `stream` is a hipStream_t (NULL = the legacy default stream).
+ *     ens_solve and ens_mlp_* only enqueue work and return; the caller
+ *     synchronises.  ens_autotune synchronises the stream it is given.
+ *   - Errors: argument errors are returned synchronously as negative codes,
+ *     with a message in ens_last_error(ctx); nothing is enqueued then.
+ *     Per-trajectory numerical failures never abort a batch: they go to the
+ *     optional STATUS array and the unreached save slots are set to NaN.
+ *   - Thread safety: one context per host thread; calls on one context must
+ *     not overlap.  Calls that overlap on one GPU through different contexts
+ *     are independent.
+ */
+#ifndef ENS_H
+#define ENS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ens_ctx ens_ctx;
+
+/* ---- return codes ------------------------------------------------------ */
+#define ENS_OK 0
+#define ENS_EINVAL (-1)       /* bad argument (null pointer, size, value)      */
+#define ENS_ENOMEM (-2)       /* device allocation failed (ens_create only)    */
+#define ENS_EDEVICE (-3)      /* a HIP call failed                             */
+#define ENS_EUNSUPPORTED (-4) /* valid but unsupported (system, alg, precision) */
+
+/* ---- systems (compile-time right-hand sides and analytic Jacobians) ------
+ *                         n  m   params rows
+ * ENS_SYS_LINEAR          3  9   A row-major: du = A u
+ * ENS_SYS_LORENZ          3  3   (sigma, rho, beta)      appendix, Lorenz problem
+ * ENS_SYS_ROBERTSON       3  3   (k1, k2, k3): dy1 = -k1 y1 + k3 y2 y3,
+ *                                dy2 = k1 y1 - k3 y2 y3 - k2 y2^2, dy3 = k2 y2^2
+ *                                                         appendix, Robertson
+ * ENS_SYS_GBM4            4  2   (mu, sigma): dX_c = mu X_c dt + sigma X_c dW_c
+ *                                                         appendix, linear SDE
+ */
+#define ENS_SYS_LINEAR 0
+#define ENS_SYS_LORENZ 1
+#define ENS_SYS_ROBERTSON 2
+#define ENS_SYS_GBM4 3
+
+/* ---- algorithms -------------------------------------------------------- */
+#define ENS_ALG_TSIT5 1  /* adaptive Tsitouras 5(4), PI control   sec. 3.1, 5.2.1 */
+#define ENS_ALG_RODAS4 2 /* adaptive Rosenbrock RODAS4, W = I - gamma h J,
+                            FP64 LU and solves              sec. 3.2.1, 5.1.3, 5.2.1 */
+#define ENS_ALG_EM 3     /* fixed-step Euler-Maruyama, Philox4x32-10 normals
+                                                            sec. 3.3, 5.2.2     */
+
+/* ---- scalar options (ens_set_option) ------------------------------------ */
+#define ENS_OPT_PRECISION 1 /* 32 (default): FP32 state, FP64 compensated time
+                               (and FP64 W/LU/solves for RODAS4);
+                               64: FP64 throughout.  Also the dtype of params,
+                               u0 and out.                                      */
+#define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;
+                               1: persistent kernel fed by an atomic work queue */
+#define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256;
+                               0 (default): tuned value or 256                  */
+#define ENS_OPT_DT 4        /* fixed step of ENS_ALG_EM (> 0)                    */
+#define ENS_OPT_SEED 5      /* 64-bit Philox key of ENS_ALG_EM (integer value,
+                               exact below 2^53)                                */
+#define ENS_OPT_H0 6        /* first step of adaptive solves; 0 (default):
+                               Hairer-Norsett-Wanner starting-step heuristic    */
+#define ENS_OPT_MAXITERS 7  /* attempted steps per trajectory before status 1
+                               (default 1e6)                                    */
+#define ENS_OPT_TSPAN_BROADCAST 8 /* 1: tspan is [2] shared by all trajectories;
+                                     0 (default): tspan is [2][N]              */
+#define ENS_OPT_REFILL 9    /* persistent form: idle lanes per wave that trigger
+                               a refill from the queue, 1..64 (default 16)      */
+#define ENS_OPT_GRID 10     /* persistent form: blocks launched; 0 (default):
+                               enough to fill every CU                          */
+#define ENS_OPT_TPL 11      /* one-lane-per-trajectory form: trajectories each
+                               lane integrates one after another, 1..8 (default
+                               1); lane g of G takes g, g + G, g + 2G, ...      */
+
+/* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
+#define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,
+                            3 non-finite error estimate or an invalid span
+                            (tf < t0 or a non-finite end point)              */
+#define ENS_PTR_STATS 2  /* int32 [2][N]: accepted, rejected step counts        */
+
+/* ---- status codes written to ENS_PTR_STATUS ------------------------------ */
+#define ENS_ST_OK 0
+#define ENS_ST_MAXITERS 1
+#define ENS_ST_DTMIN 2
+#define ENS_ST_NONFINITE 3
+
+/* Create a context on HIP device `device` (allocates its small workspace).
+ * On success *ctx is set and ENS_OK returned.                                */
+int ens_create(ens_ctx **ctx, int device);
+
+/* Destroy a context (waits for nothing; the caller must have synchronised
+ * any stream that still runs work of this context).  NULL is accepted.      */
+int ens_destroy(ens_ctx *ctx);
+
+/* Message of the last error on this context ("" if none). Valid until the
+ * next call on the context.                                                  */
+const char *ens_last_error(const ens_ctx *ctx);
+
+/* Set / read one scalar option (ENS_OPT_*).  ENS_EINVAL for an unknown key
+ * or an out-of-range value.                                                  */
+int ens_set_option(ens_ctx *ctx, int key, double value);
+int ens_get_option(const ens_ctx *ctx, int key, double *value);
+
+/* Set one optional device output array (ENS_PTR_*); NULL disables it. */
+int ens_set_ptr(ens_ctx *ctx, int key, void *device_ptr);
+
+/* n and m of a system; ENS_EINVAL for an unknown id. */
+int ens_system_dims(int system_id, int *n, int *m);
+
+/*
+ * Solve an ensemble of n_traj trajectories of `system_id` with `alg`.
+ *
+ *   params     device, [m][n_traj], dtype of ENS_OPT_PRECISION
+ *   u0         device, [n][n_traj], same dtype
+ *   tspan      device, float64: [2][n_traj] (row 0 t0, row 1 tf, tf >= t0),
+ *              or [2] with ENS_OPT_TSPAN_BROADCAST = 1
+ *   alg        ENS_ALG_*; (system, alg) must be one of
+ *              {LINEAR, LORENZ} x TSIT5, {LINEAR, LORENZ, ROBERTSON} x RODAS4,
+ *              GBM4 x EM
+ *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM)
+ *   save_times HOST, [n_save] fractions theta_j, 0 < theta_0 < ... <= 1; save
+ *              j of trajectory i is at t0_i + theta_j (tf_i - t0_i).  Adaptive
+ *              solvers step exactly onto every save time.  For EM every
+ *              theta_j * round((tf - t0)/dt) must be an integer step count.
+ *              The array is copied into the launch; it may be freed on return.
+ *   n_save     1..64
+ *   out        device, [n_save][n][n_traj], same dtype as u0
+ *   stream     hipStream_t or NULL
+ *
+ * n_traj == 0 is a no-op returning ENS_OK.  Returns after enqueueing.
+ */
+int ens_solve(ens_ctx *ctx, int system_id, int64_t n_traj, const void *params,
+              const void *u0, const double *tspan, int alg, double abstol,
+              double reltol, const double *save_times, int n_save, void *out,
+              void *stream);
+
+/*
+ * The raw Philox4x32-10 words the ENS_ALG_EM kernel draws at step `step`:
+ * out[k][i] (k = 0..3, uint32, device, [4][n_traj]) = word k of
+ * Philox4x32-10(counter = (step, i mod 2^32, i >> 32, 0), key = seed), the
+ * generator of Salmon et al. (SC'11) that the paper's SDE kernels leave
+ * unnamed (section 6.8.1).  Same device function as the solver kernel.
+ */
+int ens_philox_fill(ens_ctx *ctx, uint64_t seed, int64_t n_traj, uint32_t step,
+                    uint32_t *out, void *stream);
+
+/*
+ * Autotuner: time every launch configuration -- block in {64, 128, 256} x
+ * (plain form with trajectories per lane in {1, 2, 4}, or persistent form
+ * with refill threshold in {4, 16, 32}) -- on the given probe ensemble (same
+ * arguments as ens_solve; `out` is overwritten), and set ENS_OPT_FORM,
+ * ENS_OPT_BLOCK, ENS_OPT_TPL and ENS_OPT_REFILL to the fastest.  Results are
+ * bitwise identical across configurations, so tuning never changes answers.
+ * best_ms (may be NULL) receives its time.  Synchronises `stream`.
+ */
+int ens_autotune(ens_ctx *ctx, int system_id, int64_t n_traj,
+                 const void *params, const void *u0, const double *tspan,
+                 int alg, double abstol, double reltol,
+                 const double *save_times, int n_save, void *out, void *stream,
+                 double *best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ENS_H */

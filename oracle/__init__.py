@@ -63,7 +63,7 @@ def lib():
         L.orc_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, dp, dp]
         L.orc_box_muller.restype = None
         L.orc_em.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_double,
-                             ctypes.c_int, ctypes.c_uint64, dp, ctypes.c_int]
+                             ctypes.c_int, ctypes.c_uint64, i64p, dp, ctypes.c_int]
         L.orc_tsit5_tableau.argtypes = [dp, dp, dp, dp]
         L.orc_tsit5_tableau.restype = None
         L.orc_rodas4_tableau.argtypes = [dp, dp, dp, dp, dp]
@@ -156,13 +156,21 @@ def box_muller(x0: int, x1: int):
     return a.value, b.value
 
 
-def em(params, u0, dt, n_steps, seed, nthreads=None):
-    """Euler-Maruyama ensemble for the 4-component GBM; returns [4][N]."""
+def em(params, u0, dt, n_steps, seed, ids=None, nthreads=None):
+    """Euler-Maruyama ensemble for the 4-component GBM; returns [4][N].
+
+    ids: trajectory ids (Philox counters) of the columns; default 0..N-1.
+    """
     params, u0 = _f64(params), _f64(u0)
     N = u0.shape[1]
     assert params.shape == (2, N) and u0.shape == (4, N)
     out = np.empty((4, N))
-    rc = lib().orc_em(GBM4, N, _p(params), _p(u0), dt, n_steps, seed, _p(out),
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        assert ids.shape == (N,)
+        idp = _p(ids, ctypes.c_int64)
+    rc = lib().orc_em(GBM4, N, _p(params), _p(u0), dt, n_steps, seed, idp, _p(out),
                       nthreads or default_threads())
     if rc != 0:
         raise ValueError("orc_em rejected its arguments")

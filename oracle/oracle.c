@@ -347,6 +347,14 @@ static void solve_one(int sys, int alg, int n, const double *p,
   *status = ORC_OK;
   for (int c = 0; c < n; c++) u[c] = u0[c];
   double t = t0;
+  if (!(tf >= t0) || !isfinite(t0) || !isfinite(tf)) { /* invalid span */
+    *status = ORC_NONFINITE;
+    for (j = 0; j < n_save; j++)
+      for (int c = 0; c < n; c++) outcol[j * n + c] = NAN;
+    *nacc = 0;
+    *nrej = 0;
+    return;
+  }
   /* save points that coincide with t0 (only when tf == t0) */
   while (j < n_save && t0 + theta[j] * (tf - t0) <= t) {
     for (int c = 0; c < n; c++) outcol[j * n + c] = u[c];
@@ -393,7 +401,10 @@ static void solve_one(int sys, int alg, int n, const double *p,
       double fac = fmax(PI_FMIN, PI_ETA * pow(q, -1.0 / kexp));
       h = he * fac;
     }
-    if (!(h > 16.0 * DBL_EPSILON * fabs(t))) { *status = ORC_DTMIN; break; }
+    if (j < n_save && !(h > 16.0 * DBL_EPSILON * fabs(t))) {
+      *status = ORC_DTMIN;
+      break;
+    }
   }
   /* trajectories that stopped early report NaN at the unreached save times */
   for (; j < n_save; j++)
@@ -498,7 +509,8 @@ void orc_box_muller(uint32_t x0, uint32_t x1, double *z0, double *z1) {
 }
 
 int orc_em(int sys, int64_t N, const double *params, const double *u0,
-           double dt, int n_steps, uint64_t seed, double *out, int nthreads) {
+           double dt, int n_steps, uint64_t seed, const int64_t *ids,
+           double *out, int nthreads) {
   if (sys != ORC_GBM4 || N < 0 || n_steps < 0 || !(dt > 0.0)) return -1;
   if (nthreads < 1) nthreads = 1;
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
@@ -509,7 +521,8 @@ int orc_em(int sys, int64_t N, const double *params, const double *u0,
     double X[4];
     for (int c = 0; c < 4; c++) X[c] = u0[c * N + i];
     for (int s = 0; s < n_steps; s++) {
-      uint32_t ctr[4] = {(uint32_t)s, (uint32_t)i, (uint32_t)((uint64_t)i >> 32), 0u};
+      uint64_t id = ids ? (uint64_t)ids[i] : (uint64_t)i;
+      uint32_t ctr[4] = {(uint32_t)s, (uint32_t)id, (uint32_t)(id >> 32), 0u};
       uint32_t r[4];
       double z[4];
       orc_philox4x32_10(ctr, key, r);

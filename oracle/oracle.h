@@ -65,12 +65,14 @@ void orc_box_muller(uint32_t x0, uint32_t x1, double *z0, double *z1);
 
 /*
  * Euler-Maruyama, fixed step, diagonal noise, for ORC_GBM4 (section 3.3,
- * eq. 11; method GPUEM of section 5.2.2).  Step s of trajectory i draws its
+ * eq. 11; method GPUEM of section 5.2.2).  Step s of trajectory id draws its
  * four Wiener increments from Philox4x32-10 with key (seed_lo, seed_hi) and
- * counter (s, i_lo, i_hi, 0).  out [n][N] = state at t0 + n_steps*dt.
+ * counter (s, id_lo, id_hi, 0); column k has id ids[k] (ids NULL: id = k).
+ * out [n][N] = state at t0 + n_steps*dt.
  */
 int orc_em(int sys, int64_t N, const double *params, const double *u0,
-           double dt, int n_steps, uint64_t seed, double *out, int nthreads);
+           double dt, int n_steps, uint64_t seed, const int64_t *ids,
+           double *out, int nthreads);
 
 /* Coefficient export for the order-condition tests. */
 void orc_tsit5_tableau(double c[7], double a[49], double b[7],

@@ -1,1 +1,170 @@
-"""Ensemble ODE/SDE solving on AMD MI355X (gfx950): Python face of libens.so."""
+"""Ensemble ODE/SDE solving on AMD MI355X (gfx950).
+
+Python face of libens.so (C ABI in include/ens.h): torch tensors in, torch
+tensors out.  PyTorch only provides device memory and streams; every step of
+the integration runs in the library's HIP kernels.  If libens.so is missing
+the calls raise -- there is no CPU path.
+
+    import torch, paper_2304_06835_amd as ens
+    out = ens.solve("lorenz", params, u0, torch.tensor([0.0, 1.0], device="cuda"),
+                    alg="tsit5", abstol=1e-6, reltol=1e-6, save_times=[0.5, 1.0])
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional
+
+from . import _native
+from ._native import ALGS, OPTS, SYSTEMS, EnsError
+
+__all__ = ["Solver", "solve", "EnsError", "SYSTEMS", "ALGS", "system_dims"]
+
+
+def system_dims(system: str):
+    n, m = ctypes.c_int(), ctypes.c_int()
+    rc = _native.lib().ens_system_dims(SYSTEMS[system], ctypes.byref(n), ctypes.byref(m))
+    if rc != 0:
+        raise EnsError(rc, f"unknown system {system}")
+    return n.value, m.value
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class Solver:
+    """One ens_ctx on one HIP device.  Options persist across solve() calls."""
+
+    def __init__(self, device: int = 0, **opts):
+        self._L = _native.lib()
+        self.device = device
+        self._ctx = ctypes.c_void_p()
+        rc = self._L.ens_create(ctypes.byref(self._ctx), device)
+        if rc != 0:
+            raise EnsError(rc, f"ens_create(device={device}) failed")
+        if opts:
+            self.set(**opts)
+
+    def _check(self, rc: int):
+        if rc != 0:
+            raise EnsError(rc, self._L.ens_last_error(self._ctx).decode())
+
+    def set(self, **opts) -> "Solver":
+        for k, v in opts.items():
+            self._check(self._L.ens_set_option(self._ctx, OPTS[k], float(v)))
+        return self
+
+    def get(self, key: str) -> float:
+        v = ctypes.c_double()
+        self._check(self._L.ens_get_option(self._ctx, OPTS[key], ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if self._ctx:
+            self._L.ens_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument marshalling ------------------------------------------------
+    def _prepare(self, system, params, u0, tspan, alg, save_times, out, status, stats,
+                 stream):
+        torch = _torch()
+        sys_id, alg_id = SYSTEMS[system], ALGS[alg]
+        n, m = system_dims(system)
+        if u0.dim() != 2 or u0.shape[0] != n:
+            raise ValueError(f"u0 must be [{n}][N], got {tuple(u0.shape)}")
+        N = u0.shape[1]
+        if params.shape != (m, N):
+            raise ValueError(f"params must be [{m}][{N}], got {tuple(params.shape)}")
+        for name, t in (("params", params), ("u0", u0), ("tspan", tspan)):
+            if not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous device tensor")
+        dtype = torch.float64 if int(self.get("precision")) == 64 else torch.float32
+        if params.dtype != dtype or u0.dtype != dtype:
+            raise ValueError(f"params and u0 must be {dtype} at this precision")
+        if tspan.dtype != torch.float64:
+            raise ValueError("tspan must be float64")
+        if tspan.shape == (2,):
+            self.set(tspan_broadcast=1)
+        elif tspan.shape == (2, N):
+            self.set(tspan_broadcast=0)
+        else:
+            raise ValueError(f"tspan must be [2] or [2][{N}]")
+        theta = [float(x) for x in save_times]
+        th = (ctypes.c_double * len(theta))(*theta)
+        if out is None:
+            out = torch.empty((len(theta), n, N), dtype=dtype, device=u0.device)
+        elif out.shape != (len(theta), n, N) or out.dtype != dtype or not out.is_contiguous():
+            raise ValueError("out has the wrong shape, dtype or layout")
+        if status is not None and (status.dtype != torch.uint8 or status.numel() != N):
+            raise ValueError("status must be uint8 [N]")
+        if stats is not None and (stats.dtype != torch.int32 or stats.shape != (2, N)):
+            raise ValueError("stats must be int32 [2][N]")
+        self._check(self._L.ens_set_ptr(self._ctx, _native.PTRS["status"],
+                                        status.data_ptr() if status is not None else None))
+        self._check(self._L.ens_set_ptr(self._ctx, _native.PTRS["stats"],
+                                        stats.data_ptr() if stats is not None else None))
+        if stream is None:
+            stream = torch.cuda.current_stream(u0.device).cuda_stream
+        elif not isinstance(stream, int):
+            stream = stream.cuda_stream
+        return sys_id, alg_id, N, th, len(theta), out, stream
+
+    def solve(self, system: str, params, u0, tspan, alg: str = "tsit5",
+              abstol: float = 1e-6, reltol: float = 1e-6,
+              save_times: Iterable[float] = (1.0,), out=None, status=None, stats=None,
+              stream=None):
+        """Enqueue ens_solve on `stream` (default: torch's current stream).
+
+        params [m][N], u0 [n][N] in the precision's dtype; tspan float64 [2]
+        or [2][N]; returns out [n_save][n][N] (allocated if not given).
+        """
+        sys_id, alg_id, N, th, ns, out, s = self._prepare(
+            system, params, u0, tspan, alg, save_times, out, status, stats, stream)
+        self._check(self._L.ens_solve(self._ctx, sys_id, N, params.data_ptr(), u0.data_ptr(),
+                                      tspan.data_ptr(), alg_id, abstol, reltol, th, ns,
+                                      out.data_ptr(), s))
+        return out
+
+    def autotune(self, system: str, params, u0, tspan, alg: str = "tsit5",
+                 abstol: float = 1e-6, reltol: float = 1e-6,
+                 save_times: Iterable[float] = (1.0,), out=None, stream=None):
+        """Run ens_autotune on a probe ensemble; returns (best_ms, config)."""
+        sys_id, alg_id, N, th, ns, out, s = self._prepare(
+            system, params, u0, tspan, alg, save_times, out, None, None, stream)
+        best = ctypes.c_double()
+        self._check(self._L.ens_autotune(self._ctx, sys_id, N, params.data_ptr(),
+                                         u0.data_ptr(), tspan.data_ptr(), alg_id, abstol,
+                                         reltol, th, ns, out.data_ptr(), s,
+                                         ctypes.byref(best)))
+        cfg = {k: int(self.get(k)) for k in ("form", "block", "tpl", "refill")}
+        return best.value, cfg
+
+
+_default = {}
+
+
+def solve(system: str, params, u0, tspan, alg: str = "tsit5", abstol: float = 1e-6,
+          reltol: float = 1e-6, save_times: Iterable[float] = (1.0,), out=None,
+          stream=None, status=None, stats=None, device: Optional[int] = None, **opts):
+    """One-call face of ens_solve on a per-device default context.
+
+    Options (precision, form, block, tpl, refill, grid, dt, seed, h0,
+    maxiters) are applied to that context before the call.
+    """
+    dev = u0.device.index if device is None else device
+    dev = 0 if dev is None else dev
+    s = _default.get(dev)
+    if s is None:
+        s = _default[dev] = Solver(dev)
+    if "precision" not in opts:
+        opts["precision"] = 64 if u0.dtype == _torch().float64 else 32
+    s.set(**opts)
+    return s.solve(system, params, u0, tspan, alg, abstol, reltol, save_times, out,
+                   status, stats, stream)

@@ -1,0 +1,60 @@
+"""ctypes declarations of libens.so (include/ens.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libens.so")
+
+ENS_OK, ENS_EINVAL, ENS_ENOMEM, ENS_EDEVICE, ENS_EUNSUPPORTED = 0, -1, -2, -3, -4
+SYSTEMS = {"linear": 0, "lorenz": 1, "robertson": 2, "gbm4": 3}
+ALGS = {"tsit5": 1, "rodas4": 2, "em": 3}
+OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
+        "maxiters": 7, "tspan_broadcast": 8, "refill": 9, "grid": 10, "tpl": 11}
+PTRS = {"status": 1, "stats": 2}
+
+# Every symbol include/ens.h declares.
+EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
+           "ens_get_option", "ens_set_ptr", "ens_system_dims", "ens_solve",
+           "ens_autotune", "ens_philox_fill")
+
+
+class EnsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ens error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libens.so.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2304_06835_amd.build` "
+            "(the HIP library is the only implementation)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, c_int = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.ens_create.argtypes = [ctypes.POINTER(vp), c_int]
+    L.ens_destroy.argtypes = [vp]
+    L.ens_last_error.argtypes = [vp]
+    L.ens_last_error.restype = ctypes.c_char_p
+    L.ens_set_option.argtypes = [vp, c_int, dbl]
+    L.ens_get_option.argtypes = [vp, c_int, dp]
+    L.ens_set_ptr.argtypes = [vp, c_int, vp]
+    L.ens_system_dims.argtypes = [c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]
+    L.ens_solve.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp]
+    L.ens_autotune.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp,
+                               dp]
+    L.ens_philox_fill.argtypes = [vp, ctypes.c_uint64, i64, ctypes.c_uint32, vp, vp]
+    for name in EXPORTS:
+        getattr(L, name).restype = getattr(L, name).restype or c_int
+    L.ens_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L

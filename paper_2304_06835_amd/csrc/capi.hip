@@ -1,0 +1,420 @@
+// capi.hip -- the C ABI declared in include/ens.h: context, options,
+// argument validation, launch-shape selection and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/ens.h"
+#include "ens_internal.h"
+
+namespace ens {
+int tsit5_blocks_per_cu(int sys, int prec, int block);
+int rodas4_blocks_per_cu(int sys, int prec, int block);
+
+__global__ void zero_counter(unsigned long long* q) {
+  if (threadIdx.x == 0) *q = 0ull;
+}
+
+hipError_t reset_queue(unsigned long long* q, hipStream_t s) {
+  hipLaunchKernelGGL(zero_counter, dim3(1), dim3(64), 0, s, q);
+  return hipGetLastError();
+}
+
+int persistent_grid(int alg, int sys, int prec, int block, int num_cu) {
+  const int per_cu = alg == ENS_ALG_RODAS4 ? rodas4_blocks_per_cu(sys, prec, block)
+                                            : tsit5_blocks_per_cu(sys, prec, block);
+  return per_cu * num_cu;
+}
+}  // namespace ens
+
+struct ens_ctx {
+  int device = 0;
+  int num_cu = 0;
+  int precision = 32;
+  int form = 0;
+  int block = 0;
+  int tpl = 1;
+  int refill = 16;
+  int grid = 0;
+  int tspan_bcast = 0;
+  double dt = 0.0;
+  double h0 = 0.0;
+  double seed = 0.0;
+  double maxiters = 1e6;
+  uint8_t* status = nullptr;
+  int32_t* stats = nullptr;
+  unsigned long long* queue = nullptr;  // device workspace: persistent work counter
+  std::string err;
+};
+
+namespace {
+
+int fail(ens_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(ens_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+// Makes `dev` current for the lifetime of the guard, restoring the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool supported(int sys, int alg) {
+  switch (alg) {
+    case ENS_ALG_TSIT5: return sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR;
+    case ENS_ALG_RODAS4:
+      return sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR;
+    case ENS_ALG_EM: return sys == ENS_SYS_GBM4;
+  }
+  return false;
+}
+
+int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void* u0,
+                  const double* tspan, int alg, double atol, double rtol,
+                  const double* theta, int n_save, void* out) {
+  int nn, mm;
+  if (ens_system_dims(sys, &nn, &mm) != ENS_OK)
+    return fail(c, ENS_EINVAL, "unknown system_id %d", sys);
+  if (alg != ENS_ALG_TSIT5 && alg != ENS_ALG_RODAS4 && alg != ENS_ALG_EM)
+    return fail(c, ENS_EINVAL, "unknown alg %d", alg);
+  if (!supported(sys, alg))
+    return fail(c, ENS_EUNSUPPORTED, "system %d has no kernel for alg %d", sys, alg);
+  if (alg == ENS_ALG_EM && c->precision != 32)
+    return fail(c, ENS_EUNSUPPORTED, "Euler-Maruyama is built for precision 32 only");
+  if (n < 0 || n > (int64_t(1) << 40))
+    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
+  if (!params || !u0 || !tspan || !theta || !out)
+    return fail(c, ENS_EINVAL, "null params/u0/tspan/save_times/out pointer");
+  if (n_save < 1 || n_save > ens::kMaxSave)
+    return fail(c, ENS_EINVAL, "n_save %d out of range [1, %d]", n_save, ens::kMaxSave);
+  double prev = 0.0;
+  for (int j = 0; j < n_save; ++j) {
+    if (!(theta[j] > prev) || !(theta[j] <= 1.0))
+      return fail(c, ENS_EINVAL,
+                  "save_times must be strictly increasing fractions in (0, 1]; "
+                  "entry %d is %g",
+                  j, theta[j]);
+    prev = theta[j];
+  }
+  if (alg != ENS_ALG_EM) {
+    if (!(atol > 0.0) || !std::isfinite(atol) || !(rtol > 0.0) || !std::isfinite(rtol))
+      return fail(c, ENS_EINVAL, "abstol and reltol must be finite and > 0");
+  } else if (!(c->dt > 0.0) || !std::isfinite(c->dt)) {
+    return fail(c, ENS_EINVAL, "Euler-Maruyama needs ENS_OPT_DT > 0");
+  }
+  return ENS_OK;
+}
+
+ens::LaunchArgs make_args(ens_ctx* c, int64_t n, const void* params, const void* u0,
+                          const double* tspan, double atol, double rtol,
+                          const double* theta, int n_save, void* out) {
+  ens::LaunchArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n = n;
+  a.params = params;
+  a.u0 = u0;
+  a.tspan = tspan;
+  a.out = out;
+  a.status = c->status;
+  a.stats = c->stats;
+  a.queue = c->queue;
+  a.atol = atol;
+  a.rtol = rtol;
+  a.h0 = c->h0;
+  a.dt = c->dt;
+  a.seed = (uint64_t)c->seed;
+  a.maxiters = (int64_t)c->maxiters;
+  a.n_save = n_save;
+  a.tspan_bcast = c->tspan_bcast;
+  a.refill = c->refill;
+  a.tpl = c->tpl;
+  for (int j = 0; j < n_save; ++j) a.theta[j] = theta[j];
+  return a;
+}
+
+int launch(ens_ctx* c, int sys, int alg, ens::LaunchArgs a, const ens::LaunchCfg& cfg0,
+           hipStream_t s) {
+  ens::LaunchCfg cfg = cfg0;
+  hipError_t e;
+  if (alg == ENS_ALG_EM) {
+    cfg.form = 0;
+    e = ens::launch_em(sys, c->precision, cfg, a, s);
+  } else {
+    if (cfg.form == 1) {
+      if (cfg.grid <= 0) cfg.grid = ens::persistent_grid(alg, sys, c->precision, cfg.block, c->num_cu);
+      a.first_queued = (int64_t)cfg.grid * cfg.block;
+      a.tpl = 1;
+      e = ens::reset_queue(c->queue, s);
+      if (e != hipSuccess)
+        return fail(c, ENS_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
+    } else {
+      a.refill = 64;
+    }
+    e = alg == ENS_ALG_TSIT5 ? ens::launch_tsit5(sys, c->precision, cfg, a, s)
+                             : ens::launch_rodas4(sys, c->precision, cfg, a, s);
+  }
+  if (e != hipSuccess) return fail(c, ENS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ENS_OK;
+}
+
+ens::LaunchCfg current_cfg(const ens_ctx* c) {
+  ens::LaunchCfg cfg;
+  cfg.form = c->form;
+  cfg.block = c->block > 0 ? c->block : 256;
+  cfg.grid = c->grid;
+  return cfg;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ens_system_dims(int system_id, int* n, int* m) {
+  int nn, mm;
+  switch (system_id) {
+    case ENS_SYS_LINEAR: nn = 3; mm = 9; break;
+    case ENS_SYS_LORENZ: nn = 3; mm = 3; break;
+    case ENS_SYS_ROBERTSON: nn = 3; mm = 3; break;
+    case ENS_SYS_GBM4: nn = 4; mm = 2; break;
+    default: return ENS_EINVAL;
+  }
+  if (n) *n = nn;
+  if (m) *m = mm;
+  return ENS_OK;
+}
+
+int ens_create(ens_ctx** out, int device) {
+  if (!out) return ENS_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return ENS_EINVAL;
+  ens_ctx* c = new (std::nothrow) ens_ctx();
+  if (!c) return ENS_ENOMEM;
+  c->device = device;
+  DeviceGuard g(device);
+  if (!g.ok) {
+    delete c;
+    return ENS_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return ENS_EDEVICE;
+  }
+  c->num_cu = prop.multiProcessorCount;
+  if (hipMalloc(&c->queue, 256) != hipSuccess) {
+    delete c;
+    return ENS_ENOMEM;
+  }
+  *out = c;
+  return ENS_OK;
+}
+
+int ens_destroy(ens_ctx* c) {
+  if (!c) return ENS_OK;
+  {
+    DeviceGuard g(c->device);
+    if (c->queue) (void)hipFree(c->queue);
+  }
+  delete c;
+  return ENS_OK;
+}
+
+const char* ens_last_error(const ens_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int ens_set_option(ens_ctx* c, int key, double v) {
+  if (!c) return ENS_EINVAL;
+  if (!std::isfinite(v)) return fail(c, ENS_EINVAL, "option %d: value must be finite", key);
+  const bool integral = v == std::floor(v);
+  switch (key) {
+    case ENS_OPT_PRECISION:
+      if (v != 32 && v != 64) return fail(c, ENS_EINVAL, "precision must be 32 or 64");
+      c->precision = (int)v;
+      return ENS_OK;
+    case ENS_OPT_FORM:
+      if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "form must be 0 or 1");
+      c->form = (int)v;
+      return ENS_OK;
+    case ENS_OPT_BLOCK:
+      if (v != 0 && v != 64 && v != 128 && v != 256)
+        return fail(c, ENS_EINVAL, "block must be 0, 64, 128 or 256");
+      c->block = (int)v;
+      return ENS_OK;
+    case ENS_OPT_DT:
+      if (!(v > 0)) return fail(c, ENS_EINVAL, "dt must be > 0");
+      c->dt = v;
+      return ENS_OK;
+    case ENS_OPT_SEED:
+      if (!(v >= 0) || !integral || v >= 18446744073709551616.0)
+        return fail(c, ENS_EINVAL, "seed must be an integer in [0, 2^64)");
+      c->seed = v;
+      return ENS_OK;
+    case ENS_OPT_H0:
+      if (!(v >= 0)) return fail(c, ENS_EINVAL, "h0 must be >= 0");
+      c->h0 = v;
+      return ENS_OK;
+    case ENS_OPT_MAXITERS:
+      if (!(v >= 1) || !integral || v > 2e9) return fail(c, ENS_EINVAL, "maxiters must be in [1, 2e9]");
+      c->maxiters = v;
+      return ENS_OK;
+    case ENS_OPT_TSPAN_BROADCAST:
+      if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "tspan broadcast must be 0 or 1");
+      c->tspan_bcast = (int)v;
+      return ENS_OK;
+    case ENS_OPT_REFILL:
+      if (!integral || v < 1 || v > 64) return fail(c, ENS_EINVAL, "refill must be in [1, 64]");
+      c->refill = (int)v;
+      return ENS_OK;
+    case ENS_OPT_GRID:
+      if (!integral || v < 0 || v > 1e6) return fail(c, ENS_EINVAL, "grid must be in [0, 1e6]");
+      c->grid = (int)v;
+      return ENS_OK;
+    case ENS_OPT_TPL:
+      if (!integral || v < 1 || v > 8) return fail(c, ENS_EINVAL, "tpl must be in [1, 8]");
+      c->tpl = (int)v;
+      return ENS_OK;
+  }
+  return fail(c, ENS_EINVAL, "unknown option key %d", key);
+}
+
+int ens_get_option(const ens_ctx* c, int key, double* v) {
+  if (!c || !v) return ENS_EINVAL;
+  switch (key) {
+    case ENS_OPT_PRECISION: *v = c->precision; return ENS_OK;
+    case ENS_OPT_FORM: *v = c->form; return ENS_OK;
+    case ENS_OPT_BLOCK: *v = c->block; return ENS_OK;
+    case ENS_OPT_DT: *v = c->dt; return ENS_OK;
+    case ENS_OPT_SEED: *v = c->seed; return ENS_OK;
+    case ENS_OPT_H0: *v = c->h0; return ENS_OK;
+    case ENS_OPT_MAXITERS: *v = c->maxiters; return ENS_OK;
+    case ENS_OPT_TSPAN_BROADCAST: *v = c->tspan_bcast; return ENS_OK;
+    case ENS_OPT_REFILL: *v = c->refill; return ENS_OK;
+    case ENS_OPT_GRID: *v = c->grid; return ENS_OK;
+    case ENS_OPT_TPL: *v = c->tpl; return ENS_OK;
+  }
+  return ENS_EINVAL;
+}
+
+int ens_set_ptr(ens_ctx* c, int key, void* p) {
+  if (!c) return ENS_EINVAL;
+  switch (key) {
+    case ENS_PTR_STATUS: c->status = static_cast<uint8_t*>(p); return ENS_OK;
+    case ENS_PTR_STATS: c->stats = static_cast<int32_t*>(p); return ENS_OK;
+  }
+  return fail(c, ENS_EINVAL, "unknown pointer key %d", key);
+}
+
+int ens_solve(ens_ctx* c, int sys, int64_t n, const void* params, const void* u0,
+              const double* tspan, int alg, double atol, double rtol, const double* theta,
+              int n_save, void* out, void* stream) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  int rc = check_problem(c, sys, n, params, u0, tspan, alg, atol, rtol, theta, n_save, out);
+  if (rc != ENS_OK) return rc;
+  if (n == 0) return ENS_OK;
+  DeviceGuard g(c->device);
+  if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
+  ens::LaunchArgs a = make_args(c, n, params, u0, tspan, atol, rtol, theta, n_save, out);
+  return launch(c, sys, alg, a, current_cfg(c), static_cast<hipStream_t>(stream));
+}
+
+int ens_philox_fill(ens_ctx* c, uint64_t seed, int64_t n, uint32_t step, uint32_t* out,
+                    void* stream) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  if (n < 0 || n > (int64_t(1) << 40))
+    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
+  if (n == 0) return ENS_OK;
+  if (!out) return fail(c, ENS_EINVAL, "null out pointer");
+  DeviceGuard g(c->device);
+  if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
+  const hipError_t e = ens::launch_philox_fill(seed, n, step, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail(c, ENS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ENS_OK;
+}
+
+int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void* u0,
+                 const double* tspan, int alg, double atol, double rtol, const double* theta,
+                 int n_save, void* out, void* stream, double* best_ms) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  int rc = check_problem(c, sys, n, params, u0, tspan, alg, atol, rtol, theta, n_save, out);
+  if (rc != ENS_OK) return rc;
+  if (n == 0) return fail(c, ENS_EINVAL, "autotune needs a non-empty probe ensemble");
+  DeviceGuard g(c->device);
+  if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  ens::LaunchArgs a = make_args(c, n, params, u0, tspan, atol, rtol, theta, n_save, out);
+  struct Cand {
+    int form, block, tpl, refill;
+  };
+  Cand cands[64];
+  int nc = 0;
+  const int blocks[3] = {64, 128, 256};
+  for (int b : blocks) {
+    for (int tpl : {1, 2, 4}) cands[nc++] = {0, b, tpl, 64};
+    if (alg != ENS_ALG_EM)
+      for (int rf : {4, 16, 32}) cands[nc++] = {1, b, 1, rf};
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, ENS_EDEVICE, "hipEventCreate failed");
+  double best = 1e300;
+  Cand win = cands[0];
+  for (int k = 0; k < nc; ++k) {
+    ens::LaunchCfg cfg{cands[k].form, cands[k].block, c->grid};
+    a.tpl = cands[k].tpl;
+    a.refill = cands[k].refill;
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // first run warms up
+      if (hipEventRecord(e0, s) != hipSuccess) { rc = ENS_EDEVICE; break; }
+      rc = launch(c, sys, alg, a, cfg, s);
+      if (rc != ENS_OK) break;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = ENS_EDEVICE;
+        break;
+      }
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && ms < ms_min) ms_min = ms;
+    }
+    if (rc != ENS_OK) break;
+    if (ms_min < best) {
+      best = ms_min;
+      win = cands[k];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != ENS_OK) return rc == ENS_EDEVICE ? fail(c, rc, "autotune: HIP event/launch failure") : rc;
+  c->form = win.form;
+  c->block = win.block;
+  c->tpl = win.tpl;
+  if (win.form == 1) c->refill = win.refill;
+  if (best_ms) *best_ms = best;
+  return ENS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,62 @@
+// ens_internal.h -- launch arguments and kernel launchers shared by the C ABI
+// (capi.hip) and the kernel translation units.  Not installed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ens {
+
+constexpr int kMaxSave = 64;
+constexpr int kMaxBlock = 256;   // __launch_bounds__ of every solver kernel
+constexpr int kWave = 64;
+
+// Everything a solver kernel needs, passed by value (lands in the kernel
+// argument segment, read through scalar loads).
+struct LaunchArgs {
+  int64_t n;                 // trajectories
+  const void* params;        // [M][n]
+  const void* u0;            // [N][n]
+  const double* tspan;       // [2][n] or [2]
+  void* out;                 // [n_save][N][n]
+  uint8_t* status;           // [n] or null
+  int32_t* stats;            // [2][n] or null
+  unsigned long long* queue; // persistent form: work counter (zeroed per launch)
+  double atol, rtol;
+  double h0;                 // <= 0: starting-step heuristic
+  double dt;                 // fixed-step methods
+  uint64_t seed;             // Philox key
+  int64_t maxiters;
+  int64_t first_queued;      // persistent form: trajectories handed out statically
+  int n_save;
+  int tspan_bcast;
+  int refill;                // persistent form: idle lanes that trigger a refill
+  int tpl;                   // plain form: trajectories per lane
+  double theta[kMaxSave];
+};
+
+struct LaunchCfg {
+  int form;   // 0 plain, 1 persistent
+  int block;  // threads per block
+  int grid;   // persistent: blocks (0: occupancy-derived)
+};
+
+// Each returns hipSuccess or the launch error.  `sys` is ENS_SYS_*, `prec` 32|64.
+hipError_t launch_tsit5(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                        hipStream_t s);
+hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                         hipStream_t s);
+hipError_t launch_em(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                     hipStream_t s);
+
+hipError_t launch_philox_fill(uint64_t seed, int64_t n, uint32_t step, uint32_t* out,
+                              hipStream_t s);
+
+// Blocks per CU the persistent kernel of (alg, sys, prec) can keep resident
+// at `block` threads, and the grid that fills the device.
+int persistent_grid(int alg, int sys, int prec, int block, int num_cu);
+
+// Zero the persistent work counter (a one-thread kernel, so the solve can be
+// captured into a graph without memset nodes).
+hipError_t reset_queue(unsigned long long* q, hipStream_t s);
+
+}  // namespace ens

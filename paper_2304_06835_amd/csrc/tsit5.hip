@@ -1,0 +1,272 @@
+// tsit5.hip -- adaptive Tsitouras 5(4) ensemble kernels (GPUTsit5 of the
+// paper, section 5.2.1), one whole trajectory per lane.
+//
+// Step (section 3.1, eqs. 2-3): k1 = f(u) (first-same-as-last), stage points
+// y_i = u + h sum_{j<i} a_ij k_j, k_i = f(y_i) for i = 2..7; the 7th stage
+// point is the new solution and k7 its derivative.  Embedded estimate
+// E = h sum_j btilde_j k_j, scaled error q = RMS(E / (atol + rtol max(|u|,
+// |u_new|))) (eq. 4), accept iff q <= 1, PI control of the step size.
+//
+// State lives in registers (u, k1..k7, stage point: 27 values for n = 3);
+// parameters, initial values and outputs are structure-of-arrays, so a
+// wave's 64 lanes read and write 64 consecutive elements.  FP32 variant:
+// FP32 state and stages, FP64 time with a TwoSum compensation term, so save
+// times are hit exactly however many steps are taken.
+#include <float.h>
+
+#include "../../include/ens.h"
+#include "driver.h"
+#include "systems.h"
+
+namespace ens {
+namespace {
+
+// Tsitouras (2011) 5(4) pair.  A is strictly lower triangular; row 7 holds b
+// (FSAL).  BT = b - bhat weights the embedded error estimate.
+constexpr double TA[7][7] = {
+    {0, 0, 0, 0, 0, 0, 0},
+    {0.161, 0, 0, 0, 0, 0, 0},
+    {-0.008480655492356989, 0.335480655492357, 0, 0, 0, 0, 0},
+    {2.897153057105493, -6.359448489975075, 4.3622954328695815, 0, 0, 0, 0},
+    {5.325864828439257, -11.748883564062828, 7.4955393428898365,
+     -0.09249506636175525, 0, 0, 0},
+    {5.86145544294642, -12.92096931784711, 8.159367898576159,
+     -0.071584973281401, -0.028269050394068383, 0, 0},
+    {0.09646076681806523, 0.01, 0.4798896504144996, 1.379008574103742,
+     -3.290069515436081, 2.324710524099774, 0}};
+constexpr double BT[7] = {-0.00178001105222577714, -0.0008164344596567469,
+                          0.007880878010261995,    -0.1447110071732629,
+                          0.5823571654525552,      -0.45808210592918697,
+                          0.015151515151515152};
+
+// PI controller (section 3.1: h_new = eta q_{n-1}^beta2 q_n^beta1 h) with
+// Gustafsson's exponents beta1 = -0.7/k, beta2 = 0.4/k, k = 5 (embedded
+// order + 1), eta = 0.9, growth clamped to [0.2, 10]; q_{n-1} starts at 1e-4
+// and is floored there.  Reject: h *= max(0.2, eta q^(-1/k)).
+constexpr double kK = 5.0;
+constexpr double kEta = 0.9, kFacMin = 0.2, kFacMax = 10.0, kQFloor = 1e-4;
+
+template <class R, class S>
+struct Tsit5Lane {
+  static constexpr int N = S::N, M = S::M;
+  R p[M], u[N], k1[N];
+  CompTime t;
+  double t0, tf;
+  R h;
+  R lqold;  // log2 of the last accepted error proportion
+  int j;    // next save index
+  int nacc, nrej;
+  int status;
+  bool done;
+
+  __device__ inline void save_reached(const LaunchArgs& a, int64_t i) {
+    while (j < a.n_save && save_time(a, t0, tf, j) <= t.hi + t.lo) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) store_out<R>(a, j, c, N, i, u[c]);
+      ++j;
+    }
+    if (j >= a.n_save) done = true;
+  }
+
+  // Hairer-Norsett-Wanner I, section II.4 starting step (two f calls),
+  // capped by the interval length.
+  __device__ inline R initial_step(const LaunchArgs& a) {
+    using F = Num<R>;
+    const R atol = (R)a.atol, rtol = (R)a.rtol;
+    const double hmax = tf - t0;
+    R sc[N], d0 = 0, d1 = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      sc[c] = fma(rtol, fabs(u[c]), atol);
+      const R x = u[c] / sc[c], y = k1[c] / sc[c];
+      d0 = fma(x, x, d0);
+      d1 = fma(y, y, d1);
+    }
+    d0 = F::sqrt(d0 / (R)N);
+    d1 = F::sqrt(d1 / (R)N);
+    double h0 = (d0 < (R)1e-5 || d1 < (R)1e-5) ? 1e-6 : 0.01 * (double)d0 / (double)d1;
+    h0 = fmin(h0, hmax);
+    R y1[N], f1[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) y1[c] = fma((R)h0, k1[c], u[c]);
+    S::f(p, y1, f1);
+    R d2 = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const R z = (f1[c] - k1[c]) / sc[c];
+      d2 = fma(z, z, d2);
+    }
+    d2 = F::sqrt(d2 / (R)N) / (R)h0;
+    const double dm = fmax((double)d1, (double)d2);
+    const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
+                                    : ::exp2(::log2(0.01 / dm) / 6.0);
+    return (R)fmin(fmin(100.0 * h0, h1), hmax);
+  }
+
+  __device__ inline void init(const LaunchArgs& a, int64_t i) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a.params, r, a.n, i);
+#pragma unroll
+    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a.u0, c, a.n, i);
+    t0 = tspan_at(a, 0, i);
+    tf = tspan_at(a, 1, i);
+    t.set(t0);
+    j = 0;
+    nacc = nrej = 0;
+    status = ENS_ST_OK;
+    done = false;
+    if (!(tf >= t0) || !isfinite(t0) || !isfinite(tf)) {  // invalid span
+      status = ENS_ST_NONFINITE;
+      done = true;
+      return;
+    }
+    save_reached(a, i);  // saves that coincide with t0 (tf == t0)
+    if (done) return;
+    S::f(p, u, k1);
+    h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
+    h = (R)fmin((double)h, tf - t0);
+    lqold = (R)-13.287712379549449;  // log2(1e-4)
+  }
+
+  __device__ inline void attempt(const LaunchArgs& a, int64_t i) {
+    using F = Num<R>;
+    if ((int64_t)(nacc + nrej) >= a.maxiters) {
+      status = ENS_ST_MAXITERS;
+      done = true;
+      return;
+    }
+    const double ts = save_time(a, t0, tf, j);
+    const double rem = t.to(ts);
+    const bool clamped = (double)h >= rem;
+    const R he = clamped ? (R)rem : h;
+
+    R k[7][N], y[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) k[0][c] = k1[c];
+#pragma unroll
+    for (int s = 1; s < 7; ++s) {
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        R acc = (R)TA[s][0] * k[0][c];
+#pragma unroll
+        for (int q = 1; q < s; ++q) acc = fma((R)TA[s][q], k[q][c], acc);
+        y[c] = fma(he, acc, u[c]);
+      }
+      S::f(p, y, k[s]);
+    }
+
+    // scaled error proportion, squared (avoids a square root)
+    R q2 = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      R e = (R)BT[0] * k[0][c];
+#pragma unroll
+      for (int q = 1; q < 7; ++q) e = fma((R)BT[q], k[q][c], e);
+      e = he * e;
+      const R sc = fma((R)a.rtol, fmax(fabs(u[c]), fabs(y[c])), (R)a.atol);
+      const R r = e * F::rcp(sc);
+      q2 = fma(r, r, q2);
+    }
+    q2 = q2 * (R)(1.0 / N);
+    if (!(q2 <= (R)3.0e38)) {  // NaN or inf
+      status = ENS_ST_NONFINITE;
+      done = true;
+      return;
+    }
+    const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));  // log2 q
+    const double hmax = tf - t0;
+    if (q2 <= (R)1) {
+      ++nacc;
+      if (clamped)
+        t.set(ts);
+      else
+        t.add((double)he);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        u[c] = y[c];
+        k1[c] = k[6][c];
+      }
+      R fac = (R)kEta * F::exp2(fma((R)(-0.7 / kK), lq, (R)(0.4 / kK) * lqold));
+      fac = fmin((R)kFacMax, fmax((R)kFacMin, fac));
+      lqold = fmax(lq, (R)-13.287712379549449);
+      R hn = he * fac;
+      if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
+      h = (R)fmin((double)hn, hmax);
+      save_reached(a, i);
+      if (done) return;
+    } else {
+      ++nrej;
+      const R fac = fmax((R)kFacMin, (R)kEta * F::exp2((R)(-1.0 / kK) * lq));
+      h = he * fac;
+    }
+    if (!((double)h > 16.0 * DBL_EPSILON * fabs(t.hi))) {
+      status = ENS_ST_DTMIN;
+      done = true;
+    }
+  }
+
+  __device__ inline void finish(const LaunchArgs& a, int64_t i) {
+    for (int jj = j; jj < a.n_save; ++jj)
+#pragma unroll
+      for (int c = 0; c < N; ++c) store_out<R>(a, jj, c, N, i, Num<R>::nan());
+    if (a.status) a.status[i] = (uint8_t)status;
+    if (a.stats) {
+      a.stats[i] = nacc;
+      a.stats[a.n + i] = nrej;
+    }
+  }
+};
+
+template <class R, class S>
+__global__ void __launch_bounds__(kMaxBlock) tsit5_plain(const LaunchArgs a) {
+  run_plain<Tsit5Lane<R, S>>(a);
+}
+
+template <class R, class S>
+__global__ void __launch_bounds__(kMaxBlock) tsit5_persistent(const LaunchArgs a) {
+  run_persistent<Tsit5Lane<R, S>>(a);
+}
+
+template <class R, class S>
+hipError_t launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
+  if (cfg.form == 0) {
+    const int64_t per_block = (int64_t)cfg.block * a.tpl;
+    const int64_t grid = (a.n + per_block - 1) / per_block;
+    hipLaunchKernelGGL((tsit5_plain<R, S>), dim3((unsigned)grid), dim3(cfg.block), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((tsit5_persistent<R, S>), dim3((unsigned)cfg.grid), dim3(cfg.block),
+                       0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <class R, class S>
+int occupancy_typed(int block) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_persistent<R, S>, block, 0) !=
+      hipSuccess)
+    return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+hipError_t launch_tsit5(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
+  if (sys == ENS_SYS_LORENZ)
+    return prec == 64 ? launch_typed<double, Lorenz>(cfg, a, s)
+                      : launch_typed<float, Lorenz>(cfg, a, s);
+  if (sys == ENS_SYS_LINEAR)
+    return prec == 64 ? launch_typed<double, Linear>(cfg, a, s)
+                      : launch_typed<float, Linear>(cfg, a, s);
+  return hipErrorInvalidValue;
+}
+
+int tsit5_blocks_per_cu(int sys, int prec, int block) {
+  if (sys == ENS_SYS_LORENZ)
+    return prec == 64 ? occupancy_typed<double, Lorenz>(block)
+                      : occupancy_typed<float, Lorenz>(block);
+  return prec == 64 ? occupancy_typed<double, Linear>(block)
+                    : occupancy_typed<float, Linear>(block);
+}
+
+}  // namespace ens

@@ -1,0 +1,69 @@
+"""The C ABI library loads and exports every symbol include/ens.h declares.
+
+CPU only: no compute call is made (those need a GPU and live in test_gpu_*).
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ens.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(ens_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2304_06835_amd import _native
+    return _native.lib()
+
+
+def test_header_parsed():
+    names = declared_functions()
+    assert "ens_solve" in names and "ens_create" in names and len(names) >= 9
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2304_06835_amd import _native
+    names = declared_functions()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_native.EXPORTS)
+
+
+def test_dims_and_null_handling(lib):
+    n, m = ctypes.c_int(), ctypes.c_int()
+    expect = {0: (3, 9), 1: (3, 3), 2: (3, 3), 3: (4, 2)}
+    for sid, (nn, mm) in expect.items():
+        assert lib.ens_system_dims(sid, ctypes.byref(n), ctypes.byref(m)) == 0
+        assert (n.value, m.value) == (nn, mm)
+    assert lib.ens_system_dims(99, ctypes.byref(n), ctypes.byref(m)) == -1
+    assert lib.ens_last_error(None) == b"null context"
+    assert lib.ens_destroy(None) == 0
+    assert lib.ens_set_option(None, 1, 32.0) == -1
+    assert lib.ens_solve(None, 1, 1, None, None, None, 1, 1e-6, 1e-6, None, 1, None, None) == -1
+
+
+def test_create_without_gpu_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    assert lib.ens_create(ctypes.byref(ctx), 0) < 0
+    assert not ctx.value
+
+
+def test_product_package_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2304_06835_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), f
+                assert "liboracle" not in src and "oracle.h" not in src, f

@@ -1,6 +1,6 @@
 """Pins for the oracle's Philox4x32-10, normal draws and Euler-Maruyama (CPU).
 
-The paper names no generator (section 6.4 only says the kernel PRNG is less
+The paper names no generator (section 6.8.1 only says the kernel PRNG is less
 optimised); the oracle uses Philox4x32-10 (Salmon et al., SC'11), pinned to
 that generator's published known-answer vectors.  Euler-Maruyama (section
 5.2.2; SDE of section 3.3, eq. 11) is pinned by its exact discrete moments for
