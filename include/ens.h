@@ -152,7 +152,8 @@ int ens_system_dims(int system_id, int *n, int *m);
  *   out        device, [n_save][n][n_traj], same dtype as u0
  *   stream     hipStream_t or NULL
  *
- * n_traj == 0 is a no-op returning ENS_OK.  Returns after enqueueing.
+ * n_traj == 0 is a no-op returning ENS_OK (the device pointers may then be
+ * NULL).  Returns after enqueueing.
  */
 int ens_solve(ens_ctx *ctx, int system_id, int64_t n_traj, const void *params,
               const void *u0, const double *tspan, int alg, double abstol,

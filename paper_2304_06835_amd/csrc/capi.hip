@@ -104,10 +104,12 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
     return fail(c, ENS_EUNSUPPORTED, "Euler-Maruyama is built for precision 32 only");
   if (n < 0 || n > (int64_t(1) << 40))
     return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
-  if (!params || !u0 || !tspan || !theta || !out)
-    return fail(c, ENS_EINVAL, "null params/u0/tspan/save_times/out pointer");
   if (n_save < 1 || n_save > ens::kMaxSave)
     return fail(c, ENS_EINVAL, "n_save %d out of range [1, %d]", n_save, ens::kMaxSave);
+  if (!theta) return fail(c, ENS_EINVAL, "null save_times pointer");
+  // an empty ensemble may come with null (zero-size) device arrays
+  if (n > 0 && (!params || !u0 || !tspan || !out))
+    return fail(c, ENS_EINVAL, "null params/u0/tspan/out pointer");
   double prev = 0.0;
   for (int j = 0; j < n_save; ++j) {
     if (!(theta[j] > prev) || !(theta[j] <= 1.0))
@@ -132,6 +134,8 @@ ens::LaunchArgs make_args(ens_ctx* c, int64_t n, const void* params, const void*
   ens::LaunchArgs a;
   std::memset(&a, 0, sizeof a);
   a.n = n;
+  a.in_stride = n;
+  a.out_stride = n;
   a.params = params;
   a.u0 = u0;
   a.tspan = tspan;

@@ -54,24 +54,35 @@ struct CompTime {
   __device__ inline double to(double target) const { return (target - hi) - lo; }
 };
 
+// Number of work items of a launch: `n`, or the device-side count when the
+// launch was sized on the host for an upper bound.
+__device__ inline int64_t work_items(const LaunchArgs& a) {
+  if (!a.n_dev) return a.n;
+  const int64_t d = (int64_t)*a.n_dev;
+  return d < a.n ? d : a.n;
+}
+
+// Column of work item k in the input arrays, and in `out`.
+__device__ inline int64_t in_col(const LaunchArgs& a, int64_t k) {
+  return a.idx ? a.idx[k] : k;
+}
+__device__ inline int64_t out_col(const LaunchArgs& a, int64_t k, int64_t i) {
+  return a.scatter ? i : k;
+}
+
 __device__ inline double save_time(const LaunchArgs& a, double t0, double tf, int j) {
   return t0 + a.theta[j] * (tf - t0);
 }
 
 __device__ inline double tspan_at(const LaunchArgs& a, int row, int64_t i) {
-  return a.tspan_bcast ? a.tspan[row] : a.tspan[row * a.n + i];
+  return a.tspan_bcast ? a.tspan[row] : a.tspan[row * a.in_stride + i];
 }
 
 template <class R>
-__device__ inline R load_col(const void* base, int row, int64_t n, int64_t i) {
-  return static_cast<const R*>(base)[row * n + i];
+__device__ inline R load_col(const LaunchArgs& a, const void* base, int row, int64_t i) {
+  return static_cast<const R*>(base)[row * a.in_stride + i];
 }
 
-template <class R>
-__device__ inline void store_out(const LaunchArgs& a, int j, int c, int ncomp,
-                                 int64_t i, R v) {
-  static_cast<R*>(a.out)[((int64_t)j * ncomp + c) * a.n + i] = v;
-}
 
 // ---------------------------------------------------------------------------
 // Form 0: lane g of G integrates trajectories g, g + G, ... (tpl of them),
@@ -80,57 +91,85 @@ __device__ inline void store_out(const LaunchArgs& a, int j, int c, int ncomp,
 template <class Lane>
 __device__ inline void run_plain(const LaunchArgs& a) {
   const int64_t G = (int64_t)gridDim.x * blockDim.x;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  for (int k = 0; k < a.tpl; ++k, i += G) {
-    if (i >= a.n) return;
+  const int64_t n = work_items(a);
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int r = 0; r < a.tpl; ++r, k += G) {
+    if (k >= n) return;
     Lane L;
-    L.init(a, i);
-    while (!L.done) L.attempt(a, i);
-    L.finish(a, i);
+    L.init(a, k);
+    while (!L.done) L.attempt(a, k);
+    L.finish(a, k);
   }
 }
 
-// Form 1: a resident grid.  Thread g starts on trajectory g (< first_queued);
-// whenever at least `refill` lanes of a wave are idle, the wave takes that
-// many consecutive ids from the queue with one atomicAdd (ballot + popcount
-// + prefix count give each idle lane its id).  Every wave leaves the loop once
-// the queue is drained and all its lanes are idle; each lane's work is
+// Form 1: a resident grid.  Thread g starts on work item g (< first_queued).
+// Each wave keeps a pocket of consecutive ids claimed from the global queue
+// kChunk at a time with one atomicAdd (so the one counter sees a few atomics
+// per kChunk trajectories, not one per refill).  Whenever at least `refill`
+// lanes of a wave are idle, the wave hands them ids from its pocket (ballot +
+// popcount + prefix count give each idle lane its rank), claiming a new
+// chunk when the pocket runs short.  A wave leaves the loop once the queue
+// and its pocket are empty and all its lanes are idle; each lane's work is
 // bounded by maxiters attempts, so the grid always drains.
+constexpr int64_t kChunk = 128;
+
 template <class Lane>
 __device__ inline void run_persistent(const LaunchArgs& a) {
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool active = i < a.n;
-  bool drained = a.first_queued >= a.n;
+  const int64_t n = work_items(a);
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool active = k < n;
+  bool queue_empty = a.first_queued >= n;
+  int64_t pk_next = 0, pk_end = 0;  // the wave's pocket [pk_next, pk_end)
   Lane L;
-  if (active) L.init(a, i);
+  if (active) L.init(a, k);
   while (true) {
     if (active) {
-      if (!L.done) L.attempt(a, i);
+      if (!L.done) L.attempt(a, k);
       if (L.done) {
-        L.finish(a, i);
+        L.finish(a, k);
         active = false;
       }
     }
-    if (!drained) {
+    if (!queue_empty || pk_next < pk_end) {
       const unsigned long long idle = __ballot(!active);
       const int nidle = __popcll(idle);
       if (nidle >= a.refill) {
-        const int leader = __ffsll((long long)idle) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)nidle);
-        base = __shfl(base, leader);
-        const int64_t first = a.first_queued + (int64_t)base;
+        const int64_t left = pk_end - pk_next;
+        int64_t c0 = 0, c1 = 0;  // newly claimed chunk
+        if (left < nidle && !queue_empty) {
+          const int leader = __ffsll((long long)idle) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kChunk);
+          base = __shfl(base, leader);
+          c0 = a.first_queued + (int64_t)base;
+          c1 = c0 + kChunk < n ? c0 + kChunk : n;
+          if (c0 >= n) {
+            queue_empty = true;
+            c0 = c1 = 0;
+          }
+        }
         if (!active) {
-          const int64_t mine = first + __popcll(idle & below);
-          if (mine < a.n) {
-            i = mine;
-            L.init(a, i);
+          const int64_t r = __popcll(idle & below);
+          int64_t id = -1;
+          if (r < left)
+            id = pk_next + r;
+          else if (r - left < c1 - c0)
+            id = c0 + (r - left);
+          if (id >= 0) {
+            k = id;
+            L.init(a, k);
             active = true;
           }
         }
-        if (first + nidle >= a.n) drained = true;
+        if (c1 > c0) {  // leftovers were used up first; keep the rest of the chunk
+          const int64_t used = nidle - left;
+          pk_next = c0 + (used < c1 - c0 ? used : c1 - c0);
+          pk_end = c1;
+        } else {
+          pk_next += (nidle < left ? nidle : left);
+        }
       }
     }
     if (__ballot(active) == 0ull) break;

@@ -56,15 +56,15 @@ __global__ void __launch_bounds__(kMaxBlock) em_gbm4(const LaunchArgs a) {
   const float* P = static_cast<const float*>(a.params);
   const float* U0 = static_cast<const float*>(a.u0);
   float* out = static_cast<float*>(a.out);
-  const float mu = P[i], sigma = P[a.n + i];
+  const float mu = P[i], sigma = P[a.in_stride + i];
   float X[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) X[c] = U0[c * a.n + i];
+  for (int c = 0; c < 4; ++c) X[c] = U0[c * a.in_stride + i];
   const double t0 = tspan_at(a, 0, i), tf = tspan_at(a, 1, i);
   if (!(tf >= t0) || !isfinite(t0) || !isfinite(tf)) {  // invalid span
     for (int j = 0; j < a.n_save; ++j)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.n + i] = __builtin_nanf("");
+      for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.out_stride + i] = __builtin_nanf("");
     if (a.status) a.status[i] = ENS_ST_NONFINITE;
     return;
   }
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(kMaxBlock) em_gbm4(const LaunchArgs a) {
   int64_t next = llround(a.theta[0] * (double)nsteps);
   while (j < a.n_save && next <= 0) {  // saves at t0
 #pragma unroll
-    for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.n + i] = X[c];
+    for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.out_stride + i] = X[c];
     ++j;
     next = j < a.n_save ? llround(a.theta[j] * (double)nsteps) : -1;
   }
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(kMaxBlock) em_gbm4(const LaunchArgs a) {
     }
     while (j < a.n_save && s + 1 == next) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.n + i] = X[c];
+      for (int c = 0; c < 4; ++c) out[((int64_t)j * 4 + c) * a.out_stride + i] = X[c];
       ++j;
       next = j < a.n_save ? llround(a.theta[j] * (double)nsteps) : -1;
     }

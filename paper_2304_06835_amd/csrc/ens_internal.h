@@ -13,13 +13,18 @@ constexpr int kWave = 64;
 // Everything a solver kernel needs, passed by value (lands in the kernel
 // argument segment, read through scalar loads).
 struct LaunchArgs {
-  int64_t n;                 // trajectories
-  const void* params;        // [M][n]
-  const void* u0;            // [N][n]
-  const double* tspan;       // [2][n] or [2]
-  void* out;                 // [n_save][N][n]
-  uint8_t* status;           // [n] or null
-  int32_t* stats;            // [2][n] or null
+  int64_t n;                 // work items (an upper bound when n_dev is set)
+  int64_t in_stride;         // row stride of params / u0 / tspan
+  int64_t out_stride;        // row stride of out
+  const void* params;        // [M][in_stride]
+  const void* u0;            // [N][in_stride]
+  const double* tspan;       // [2][in_stride] or [2]
+  void* out;                 // [n_save][N][out_stride]
+  const int64_t* idx;        // work item k reads column idx[k] (null: k)
+  const unsigned long long* n_dev;  // device-side work count (null: n)
+  int scatter;               // 1: work item k writes column idx[k]; 0: column k
+  uint8_t* status;           // [n] (by work item) or null
+  int32_t* stats;            // [2][n] (by work item) or null
   unsigned long long* queue; // persistent form: work counter (zeroed per launch)
   double atol, rtol;
   double h0;                 // <= 0: starting-step heuristic

@@ -105,16 +105,22 @@ struct Rodas4Lane {
   R p[M], u[N];
   CompTime t;
   double t0, tf;
+  double ts;  // next save time
   R h;
   R lqold;
+  R* sp;        // out[j][0][col]: where the next save goes
   int j, nacc, nrej, status;
   bool done;
 
-  __device__ inline void save_reached(const LaunchArgs& a, int64_t i) {
-    while (j < a.n_save && save_time(a, t0, tf, j) <= t.hi + t.lo) {
+  // Store u at every save time reached; sp walks the [n_save][N][stride]
+  // output one save at a time, so a save costs N stores and an add.
+  __device__ inline void save_reached(const LaunchArgs& a) {
+    while (j < a.n_save && ts <= t.hi + t.lo) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) store_out<R>(a, j, c, N, i, u[c]);
+      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
+      sp += N * a.out_stride;
       ++j;
+      if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
     if (j >= a.n_save) done = true;
   }
@@ -158,11 +164,13 @@ struct Rodas4Lane {
     return (R)fmin(fmin(100.0 * h0, h1), hmax);
   }
 
-  __device__ inline void init(const LaunchArgs& a, int64_t i) {
+  __device__ inline void init(const LaunchArgs& a, int64_t k) {
+    const int64_t i = in_col(a, k);
+    sp = static_cast<R*>(a.out) + out_col(a, k, i);
 #pragma unroll
-    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a.params, r, a.n, i);
+    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
 #pragma unroll
-    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a.u0, c, a.n, i);
+    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a, a.u0, c, i);
     t0 = tspan_at(a, 0, i);
     tf = tspan_at(a, 1, i);
     t.set(t0);
@@ -175,21 +183,21 @@ struct Rodas4Lane {
       done = true;
       return;
     }
-    save_reached(a, i);
+    ts = save_time(a, t0, tf, 0);
+    save_reached(a);
     if (done) return;
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
     h = (R)fmin((double)h, tf - t0);
     lqold = (R)kLog2QFloor;
   }
 
-  __device__ inline void attempt(const LaunchArgs& a, int64_t i) {
+  __device__ inline void attempt(const LaunchArgs& a, int64_t) {
     using F = Num<R>;
     if ((int64_t)(nacc + nrej) >= a.maxiters) {
       status = ENS_ST_MAXITERS;
       done = true;
       return;
     }
-    const double ts = save_time(a, t0, tf, j);
     const double rem = t.to(ts);
     const bool clamped = (double)h >= rem;
     const R he = clamped ? (R)rem : h;
@@ -263,7 +271,7 @@ struct Rodas4Lane {
       R hn = he * fac;
       if (clamped) hn = fmax(hn, h);
       h = (R)fmin((double)hn, hmax);
-      save_reached(a, i);
+      save_reached(a);
       if (done) return;
     } else {
       ++nrej;
@@ -276,14 +284,14 @@ struct Rodas4Lane {
     }
   }
 
-  __device__ inline void finish(const LaunchArgs& a, int64_t i) {
-    for (int jj = j; jj < a.n_save; ++jj)
+  __device__ inline void finish(const LaunchArgs& a, int64_t k) {
+    for (int jj = j; jj < a.n_save; ++jj, sp += N * a.out_stride)
 #pragma unroll
-      for (int c = 0; c < N; ++c) store_out<R>(a, jj, c, N, i, Num<R>::nan());
-    if (a.status) a.status[i] = (uint8_t)status;
+      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = Num<R>::nan();
+    if (a.status) a.status[k] = (uint8_t)status;
     if (a.stats) {
-      a.stats[i] = nacc;
-      a.stats[a.n + i] = nrej;
+      a.stats[k] = nacc;
+      a.stats[a.n + k] = nrej;
     }
   }
 };

@@ -52,62 +52,72 @@ struct Tsit5Lane {
   R p[M], u[N], k1[N];
   CompTime t;
   double t0, tf;
+  double ts;  // next save time
   R h;
   R lqold;  // log2 of the last accepted error proportion
-  int j;    // next save index
+  R* sp;        // out[j][0][col]: where the next save goes
+  int j;        // next save index
   int nacc, nrej;
   int status;
   bool done;
 
-  __device__ inline void save_reached(const LaunchArgs& a, int64_t i) {
-    while (j < a.n_save && save_time(a, t0, tf, j) <= t.hi + t.lo) {
+  // Store u at every save time reached; sp walks the [n_save][N][stride]
+  // output one save at a time, so a save costs N stores and an add.
+  __device__ inline void save_reached(const LaunchArgs& a) {
+    while (j < a.n_save && ts <= t.hi + t.lo) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) store_out<R>(a, j, c, N, i, u[c]);
+      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
+      sp += N * a.out_stride;
       ++j;
+      if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
     if (j >= a.n_save) done = true;
   }
 
-  // Hairer-Norsett-Wanner I, section II.4 starting step (two f calls),
-  // capped by the interval length.
+  // Hairer-Norsett-Wanner I, section II.4 starting step (two f calls, order
+  // p = 5), capped by the interval length.  Written on squared norms:
+  // d0 = ||u0/sc||, d1 = ||f0/sc||, h0 = 0.01 d0/d1 (1e-6 if either is below
+  // 1e-5), d2 = ||(f(u0 + h0 f0) - f0)/sc|| / h0,
+  // h1 = (0.01 / max(d1, d2))^(1/6), h = min(100 h0, h1).
   __device__ inline R initial_step(const LaunchArgs& a) {
     using F = Num<R>;
     const R atol = (R)a.atol, rtol = (R)a.rtol;
-    const double hmax = tf - t0;
-    R sc[N], d0 = 0, d1 = 0;
+    const R hmax = (R)(tf - t0);
+    R isc[N], s0 = 0, s1 = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      sc[c] = fma(rtol, fabs(u[c]), atol);
-      const R x = u[c] / sc[c], y = k1[c] / sc[c];
-      d0 = fma(x, x, d0);
-      d1 = fma(y, y, d1);
+      isc[c] = F::rcp(fma(rtol, fabs(u[c]), atol));
+      const R x = u[c] * isc[c], y = k1[c] * isc[c];
+      s0 = fma(x, x, s0);
+      s1 = fma(y, y, s1);
     }
-    d0 = F::sqrt(d0 / (R)N);
-    d1 = F::sqrt(d1 / (R)N);
-    double h0 = (d0 < (R)1e-5 || d1 < (R)1e-5) ? 1e-6 : 0.01 * (double)d0 / (double)d1;
+    const R small = (R)(1e-10 * N);  // d < 1e-5  <=>  s / N < 1e-10
+    R h0 = (s0 < small || s1 < small) ? (R)1e-6 : (R)0.01 * F::sqrt(s0 * F::rcp(s1));
     h0 = fmin(h0, hmax);
     R y1[N], f1[N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) y1[c] = fma((R)h0, k1[c], u[c]);
+    for (int c = 0; c < N; ++c) y1[c] = fma(h0, k1[c], u[c]);
     S::f(p, y1, f1);
-    R d2 = 0;
+    R s2 = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const R z = (f1[c] - k1[c]) / sc[c];
-      d2 = fma(z, z, d2);
+      const R z = (f1[c] - k1[c]) * isc[c];
+      s2 = fma(z, z, s2);
     }
-    d2 = F::sqrt(d2 / (R)N) / (R)h0;
-    const double dm = fmax((double)d1, (double)d2);
-    const double h1 = (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3)
-                                    : ::exp2(::log2(0.01 / dm) / 6.0);
-    return (R)fmin(fmin(100.0 * h0, h1), hmax);
+    const R dm2 = fmax(s1, s2 * F::rcp(h0 * h0)) * (R)(1.0 / N);  // max(d1, d2)^2
+    const R h1 = (dm2 <= (R)1e-30)
+                     ? fmax((R)1e-6, h0 * (R)1e-3)
+                     : F::exp2(((R)-6.643856189774724 - (R)0.5 * F::log2(dm2)) * (R)(1.0 / 6.0));
+    return fmin(fmin((R)100 * h0, h1), hmax);
   }
 
-  __device__ inline void init(const LaunchArgs& a, int64_t i) {
+  __device__ inline void init(const LaunchArgs& a, int64_t k) {
+    const int64_t i = in_col(a, k);
+    sp = static_cast<R*>(a.out) + out_col(a, k, i);
 #pragma unroll
-    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a.params, r, a.n, i);
+    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
 #pragma unroll
-    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a.u0, c, a.n, i);
+    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a, a.u0, c, i);
     t0 = tspan_at(a, 0, i);
     tf = tspan_at(a, 1, i);
     t.set(t0);
@@ -120,7 +130,8 @@ struct Tsit5Lane {
       done = true;
       return;
     }
-    save_reached(a, i);  // saves that coincide with t0 (tf == t0)
+    ts = save_time(a, t0, tf, 0);
+    save_reached(a);  // saves that coincide with t0 (tf == t0)
     if (done) return;
     S::f(p, u, k1);
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
@@ -128,14 +139,13 @@ struct Tsit5Lane {
     lqold = (R)-13.287712379549449;  // log2(1e-4)
   }
 
-  __device__ inline void attempt(const LaunchArgs& a, int64_t i) {
+  __device__ inline void attempt(const LaunchArgs& a, int64_t) {
     using F = Num<R>;
     if ((int64_t)(nacc + nrej) >= a.maxiters) {
       status = ENS_ST_MAXITERS;
       done = true;
       return;
     }
-    const double ts = save_time(a, t0, tf, j);
     const double rem = t.to(ts);
     const bool clamped = (double)h >= rem;
     const R he = clamped ? (R)rem : h;
@@ -192,7 +202,7 @@ struct Tsit5Lane {
       R hn = he * fac;
       if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
       h = (R)fmin((double)hn, hmax);
-      save_reached(a, i);
+      save_reached(a);
       if (done) return;
     } else {
       ++nrej;
@@ -205,14 +215,14 @@ struct Tsit5Lane {
     }
   }
 
-  __device__ inline void finish(const LaunchArgs& a, int64_t i) {
-    for (int jj = j; jj < a.n_save; ++jj)
+  __device__ inline void finish(const LaunchArgs& a, int64_t k) {
+    for (int jj = j; jj < a.n_save; ++jj, sp += N * a.out_stride)
 #pragma unroll
-      for (int c = 0; c < N; ++c) store_out<R>(a, jj, c, N, i, Num<R>::nan());
-    if (a.status) a.status[i] = (uint8_t)status;
+      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = Num<R>::nan();
+    if (a.status) a.status[k] = (uint8_t)status;
     if (a.stats) {
-      a.stats[i] = nacc;
-      a.stats[a.n + i] = nrej;
+      a.stats[k] = nacc;
+      a.stats[a.n + k] = nrej;
     }
   }
 };
