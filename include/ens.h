@@ -185,6 +185,106 @@ int ens_autotune(ens_ctx *ctx, int system_id, int64_t n_traj,
                  const double *save_times, int n_save, void *out, void *stream,
                  double *best_ms);
 
+/* ==========================================================================
+ * Learned surrogate: a multilayer perceptron (rho, x0, y0, z0) -> 256 -> 256
+ * -> 256 -> 48 (the Lorenz state at 16 save times), SiLU hidden activations,
+ * bfloat16 weights and activations with FP32 accumulation on the matrix
+ * cores, trained by the library's own forward / backward / Adam kernels on
+ * trajectories that ens_solve produces, and audited by the Tsit5 solver,
+ * which also answers every query the surrogate is not validated for.  The
+ * paper has no such component; it extends the ensemble solve.
+ *
+ * Ownership: an ens_surrogate owns its device buffers (weights, Adam moments,
+ * gradient, normalisation, workspaces) -- the one exception to "the library
+ * allocates nothing of the caller's".  Everything else is caller-owned.
+ * Inputs use the ens_solve layout of ENS_SYS_LORENZ at precision 32: params
+ * [3][n] (sigma, rho, beta; only rho is a network input), u0 [3][n], outputs
+ * [16][3][n] float32.
+ * ======================================================================== */
+typedef struct ens_surrogate ens_surrogate;
+
+#define ENS_SURR_NIN 4
+#define ENS_SURR_HIDDEN 256
+#define ENS_SURR_NOUT 48
+#define ENS_SURR_NPARAM 145200 /* flat: per layer W [out][in] row-major, b [out] */
+
+/* buffers of a model, for ens_surrogate_copy */
+#define ENS_SURR_MASTER 1       /* float  [NPARAM] FP32 master weights            */
+#define ENS_SURR_WEIGHTS_BF16 2 /* uint16 [NPARAM] bfloat16 copy used by kernels  */
+#define ENS_SURR_GRAD 3         /* float  [NPARAM] gradient of the last step      */
+#define ENS_SURR_ADAM_M 4       /* float  [NPARAM] Adam first moment              */
+#define ENS_SURR_ADAM_V 5       /* float  [NPARAM] Adam second moment             */
+#define ENS_SURR_NORM 6         /* float  [160]: input mean[4], 1/std[4], min[4],
+                                   max[4]; output mean[48], 1/std[48], std[48]   */
+
+/* Allocate a model on the context's device; weights He-uniform from
+ * Philox4x32-10(seed), biases 0, identity normalisation.  Synchronises the
+ * device.                                                                    */
+int ens_surrogate_create(ens_ctx *ctx, uint64_t seed, ens_surrogate **out);
+int ens_surrogate_destroy(ens_surrogate *s);
+/* Copy one model buffer (ENS_SURR_*) to (to_model = 0) or from (to_model = 1)
+ * the caller's device array `dev_ptr` of the buffer's size, on `stream`.
+ * Writing ENS_SURR_MASTER also refreshes the bfloat16 weights.               */
+int ens_surrogate_copy(ens_ctx *ctx, ens_surrogate *s, int which, void *dev_ptr,
+                       int to_model, void *stream);
+/* Adam step counter (bias correction); restored with the moments on resume. */
+int ens_surrogate_get_step(const ens_surrogate *s, int64_t *step);
+int ens_surrogate_set_step(ens_surrogate *s, int64_t step);
+
+/* Normalisation from a training set: per input feature and per output row,
+ * mean and standard deviation over n trajectories (FP64 sums, fixed order),
+ * and the input min / max that bound the validated region.  y [48][n].     */
+int ens_surrogate_fit_norm(ens_ctx *ctx, ens_surrogate *s, const float *params,
+                           const float *u0, const float *y, int64_t n,
+                           void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on the
+ * minibatch of items first .. first+batch-1, item b being trajectory
+ * (mult * b + add) mod n (mult coprime with n: a permutation of the set).
+ * Loss = mean squared error of the normalised outputs; written to *loss
+ * (device float) when loss is not NULL.                                      */
+int ens_surrogate_train_step(ens_ctx *ctx, ens_surrogate *s,
+                             const float *params, const float *u0,
+                             const float *y, int64_t n, int64_t first,
+                             int64_t batch, uint64_t mult, uint64_t add,
+                             double lr, float *loss, void *stream);
+
+/* `epochs` passes over floor(n / batch) minibatches, a fresh pseudo-random
+ * permutation per epoch drawn from `seed`, learning rate decayed from lr_max
+ * to lr_min on a cosine; epoch_loss (device float [epochs], may be NULL)
+ * receives the loss of each epoch's last minibatch.                          */
+int ens_surrogate_train(ens_ctx *ctx, ens_surrogate *s, const float *params,
+                        const float *u0, const float *y, int64_t n, int epochs,
+                        int64_t batch, double lr_max, double lr_min,
+                        uint64_t seed, float *epoch_loss, void *stream);
+
+/* Surrogate answers for n queries into out [48][n] = [16][3][n]. */
+int ens_surrogate_predict(ens_ctx *ctx, ens_surrogate *s, const float *params,
+                          const float *u0, int64_t n, float *out, void *stream);
+
+/*
+ * Audited surrogate solve of n Lorenz queries (same arguments as ens_solve
+ * for ENS_SYS_LORENZ / ENS_ALG_TSIT5 at precision 32, n_save must be 16):
+ *   1. the surrogate answers every query;
+ *   2. each query is audited with probability audit_frac (Philox4x32-10 on
+ *      the query id and audit_seed) and re-solved by the FP32 Tsit5 kernel;
+ *      an audited query always returns the solver's answer;
+ *   3. if an audited query's normwise error (max over save times of
+ *      ||surrogate - solver||_inf / ||solver||_inf) exceeds fallback_tol, its
+ *      rho bin (28 equal bins over the training range of rho) is flagged;
+ *   4. every query in a flagged bin, or outside the training box (any input
+ *      outside its training min / max), is re-solved by the solver.
+ * used_solver (device uint8 [n], may be NULL): 0 surrogate, 1 audited,
+ * 2 fallback.  report (device float [4], may be NULL): audited count,
+ * fallback count, flagged bins, max audited error.  Asynchronous.
+ */
+int ens_surrogate_solve(ens_ctx *ctx, ens_surrogate *s, const float *params,
+                        const float *u0, const double *tspan, double abstol,
+                        double reltol, const double *save_times, int n_save,
+                        int64_t n, double audit_frac, double fallback_tol,
+                        uint64_t audit_seed, float *out, uint8_t *used_solver,
+                        float *report, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ from typing import Iterable, Optional
 from . import _native
 from ._native import ALGS, OPTS, SYSTEMS, EnsError
 
-__all__ = ["Solver", "solve", "EnsError", "SYSTEMS", "ALGS", "system_dims"]
+__all__ = ["Solver", "Surrogate", "solve", "EnsError", "SYSTEMS", "ALGS", "system_dims"]
 
 
 def system_dims(system: str):
@@ -168,3 +168,124 @@ def solve(system: str, params, u0, tspan, alg: str = "tsit5", abstol: float = 1e
     s.set(**opts)
     return s.solve(system, params, u0, tspan, alg, abstol, reltol, save_times, out,
                    status, stats, stream)
+
+
+class Surrogate:
+    """The learned surrogate of include/ens.h (ens_surrogate_*), bound to a Solver.
+
+    Lorenz queries in the ens_solve layout at precision 32: params [3][N]
+    (sigma, rho, beta), u0 [3][N]; outputs [16][3][N].
+    """
+
+    NPARAM = _native.SURR_NPARAM
+
+    def __init__(self, solver: Solver, seed: int = 0):
+        self.solver = solver
+        self._L = solver._L
+        self._s = ctypes.c_void_p()
+        solver._check(self._L.ens_surrogate_create(solver._ctx, seed, ctypes.byref(self._s)))
+
+    def close(self):
+        if self._s:
+            self._L.ens_surrogate_destroy(self._s)
+            self._s = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream(stream):
+        torch = _torch()
+        if stream is None:
+            return torch.cuda.current_stream().cuda_stream
+        return stream if isinstance(stream, int) else stream.cuda_stream
+
+    def _c(self, rc):
+        self.solver._check(rc)
+
+    def buffer(self, which: str, stream=None):
+        """A device copy of one model buffer (master, weights_bf16, grad, adam_m,
+        adam_v, norm)."""
+        torch = _torch()
+        n = 160 if which == "norm" else self.NPARAM
+        dt = torch.int16 if which == "weights_bf16" else torch.float32
+        t = torch.empty(n, dtype=dt, device=f"cuda:{self.solver.device}")
+        self._c(self._L.ens_surrogate_copy(self.solver._ctx, self._s, _native.SURR_BUFFERS[which],
+                                           t.data_ptr(), 0, self._stream(stream)))
+        return t
+
+    def load(self, which: str, t, stream=None):
+        """Overwrite one model buffer from a device tensor of its size."""
+        assert t.is_cuda and t.is_contiguous()
+        self._c(self._L.ens_surrogate_copy(self.solver._ctx, self._s, _native.SURR_BUFFERS[which],
+                                           t.data_ptr(), 1, self._stream(stream)))
+
+    @property
+    def step(self) -> int:
+        v = ctypes.c_int64()
+        self._c(self._L.ens_surrogate_get_step(self._s, ctypes.byref(v)))
+        return v.value
+
+    @step.setter
+    def step(self, k: int):
+        self._c(self._L.ens_surrogate_set_step(self._s, int(k)))
+
+    def fit_norm(self, params, u0, y, stream=None):
+        self._c(self._L.ens_surrogate_fit_norm(self.solver._ctx, self._s, params.data_ptr(),
+                                               u0.data_ptr(), y.data_ptr(), u0.shape[1],
+                                               self._stream(stream)))
+
+    def train_step(self, params, u0, y, first, batch, mult=1, add=0, lr=1e-3, loss=None,
+                   stream=None):
+        self._c(self._L.ens_surrogate_train_step(
+            self.solver._ctx, self._s, params.data_ptr(), u0.data_ptr(), y.data_ptr(),
+            u0.shape[1], first, batch, mult, add, lr,
+            loss.data_ptr() if loss is not None else None, self._stream(stream)))
+
+    def train(self, params, u0, y, epochs, batch=4096, lr_max=1e-3, lr_min=1e-5, seed=0,
+              stream=None):
+        """Returns the per-epoch loss (device tensor [epochs])."""
+        torch = _torch()
+        losses = torch.zeros(epochs, dtype=torch.float32, device=u0.device)
+        self._c(self._L.ens_surrogate_train(
+            self.solver._ctx, self._s, params.data_ptr(), u0.data_ptr(), y.data_ptr(),
+            u0.shape[1], epochs, batch, lr_max, lr_min, seed, losses.data_ptr(),
+            self._stream(stream)))
+        return losses
+
+    def predict(self, params, u0, out=None, stream=None):
+        torch = _torch()
+        N = u0.shape[1]
+        if out is None:
+            out = torch.empty((16, 3, N), dtype=torch.float32, device=u0.device)
+        self._c(self._L.ens_surrogate_predict(self.solver._ctx, self._s, params.data_ptr(),
+                                              u0.data_ptr(), N, out.data_ptr(),
+                                              self._stream(stream)))
+        return out
+
+    def solve(self, params, u0, tspan, abstol, reltol, save_times, audit_frac=0.01,
+              fallback_tol=1e-3, audit_seed=8, out=None, used=None, report=None, stream=None):
+        """Audited surrogate solve; returns (out, used [N] uint8, report [4])."""
+        torch = _torch()
+        N = u0.shape[1]
+        dev = u0.device
+        if out is None:
+            out = torch.empty((16, 3, N), dtype=torch.float32, device=dev)
+        if used is None:
+            used = torch.empty(N, dtype=torch.uint8, device=dev)
+        if report is None:
+            report = torch.zeros(4, dtype=torch.float32, device=dev)
+        if tspan.shape == (2,):
+            self.solver.set(tspan_broadcast=1)
+        else:
+            self.solver.set(tspan_broadcast=0)
+        theta = [float(x) for x in save_times]
+        th = (ctypes.c_double * len(theta))(*theta)
+        self._c(self._L.ens_surrogate_solve(
+            self.solver._ctx, self._s, params.data_ptr(), u0.data_ptr(), tspan.data_ptr(),
+            abstol, reltol, th, len(theta), N, audit_frac, fallback_tol, audit_seed,
+            out.data_ptr(), used.data_ptr(), report.data_ptr(), self._stream(stream)))
+        return out, used, report

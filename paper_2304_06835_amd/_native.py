@@ -17,7 +17,12 @@ PTRS = {"status": 1, "stats": 2}
 # Every symbol include/ens.h declares.
 EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
            "ens_get_option", "ens_set_ptr", "ens_system_dims", "ens_solve",
-           "ens_autotune", "ens_philox_fill")
+           "ens_autotune", "ens_philox_fill", "ens_surrogate_create", "ens_surrogate_destroy",
+           "ens_surrogate_copy", "ens_surrogate_get_step", "ens_surrogate_set_step",
+           "ens_surrogate_fit_norm", "ens_surrogate_train_step", "ens_surrogate_train",
+           "ens_surrogate_predict", "ens_surrogate_solve")
+SURR_BUFFERS = {"master": 1, "weights_bf16": 2, "grad": 3, "adam_m": 4, "adam_v": 5, "norm": 6}
+SURR_NPARAM = 145200
 
 
 class EnsError(RuntimeError):
@@ -53,6 +58,19 @@ def lib() -> ctypes.CDLL:
     L.ens_autotune.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp,
                                dp]
     L.ens_philox_fill.argtypes = [vp, ctypes.c_uint64, i64, ctypes.c_uint32, vp, vp]
+    u64 = ctypes.c_uint64
+    L.ens_surrogate_create.argtypes = [vp, u64, ctypes.POINTER(vp)]
+    L.ens_surrogate_destroy.argtypes = [vp]
+    L.ens_surrogate_copy.argtypes = [vp, vp, c_int, vp, c_int, vp]
+    L.ens_surrogate_get_step.argtypes = [vp, ctypes.POINTER(i64)]
+    L.ens_surrogate_set_step.argtypes = [vp, i64]
+    L.ens_surrogate_fit_norm.argtypes = [vp, vp, vp, vp, vp, i64, vp]
+    L.ens_surrogate_train_step.argtypes = [vp, vp, vp, vp, vp, i64, i64, i64, u64, u64, dbl, vp,
+                                           vp]
+    L.ens_surrogate_train.argtypes = [vp, vp, vp, vp, vp, i64, c_int, i64, dbl, dbl, u64, vp, vp]
+    L.ens_surrogate_predict.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.ens_surrogate_solve.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, dp, c_int, i64, dbl, dbl, u64,
+                                      vp, vp, vp, vp]
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or c_int
     L.ens_last_error.restype = ctypes.c_char_p

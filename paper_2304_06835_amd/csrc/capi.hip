@@ -32,29 +32,7 @@ int persistent_grid(int alg, int sys, int prec, int block, int num_cu) {
 }
 }  // namespace ens
 
-struct ens_ctx {
-  int device = 0;
-  int num_cu = 0;
-  int precision = 32;
-  int form = 0;
-  int block = 0;
-  int tpl = 1;
-  int refill = 16;
-  int grid = 0;
-  int tspan_bcast = 0;
-  double dt = 0.0;
-  double h0 = 0.0;
-  double seed = 0.0;
-  double maxiters = 1e6;
-  uint8_t* status = nullptr;
-  int32_t* stats = nullptr;
-  unsigned long long* queue = nullptr;  // device workspace: persistent work counter
-  std::string err;
-};
-
-namespace {
-
-int fail(ens_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+namespace ens {
 int fail(ens_ctx* c, int code, const char* fmt, ...) {
   if (c) {
     char buf[512];
@@ -66,19 +44,11 @@ int fail(ens_ctx* c, int code, const char* fmt, ...) {
   }
   return code;
 }
+}  // namespace ens
 
-// Makes `dev` current for the lifetime of the guard, restoring the caller's.
-struct DeviceGuard {
-  int prev = -1;
-  bool ok = false;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) return;
-    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
-  }
-  ~DeviceGuard() {
-    if (ok && prev >= 0) (void)hipSetDevice(prev);
-  }
-};
+namespace {
+using ens::DeviceGuard;
+using ens::fail;
 
 bool supported(int sys, int alg) {
   switch (alg) {
@@ -159,6 +129,13 @@ ens::LaunchArgs make_args(ens_ctx* c, int64_t n, const void* params, const void*
 
 int launch(ens_ctx* c, int sys, int alg, ens::LaunchArgs a, const ens::LaunchCfg& cfg0,
            hipStream_t s) {
+  return ens::launch_solve(c, sys, alg, a, cfg0, s);
+}
+
+}  // namespace
+
+int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
+                      const ens::LaunchCfg& cfg0, hipStream_t s) {
   ens::LaunchCfg cfg = cfg0;
   hipError_t e;
   if (alg == ENS_ALG_EM) {
@@ -181,6 +158,8 @@ int launch(ens_ctx* c, int sys, int alg, ens::LaunchArgs a, const ens::LaunchCfg
   if (e != hipSuccess) return fail(c, ENS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return ENS_OK;
 }
+
+namespace {
 
 ens::LaunchCfg current_cfg(const ens_ctx* c) {
   ens::LaunchCfg cfg;

@@ -12,30 +12,10 @@
 // One lane per trajectory; no divergence: every lane takes the same steps.
 #include "../../include/ens.h"
 #include "driver.h"
+#include "philox.h"
 
 namespace ens {
 namespace {
-
-struct Philox4 {
-  uint32_t x0, x1, x2, x3;
-};
-
-__device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                        uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-    k0 += 0x9E3779B9u;
-    k1 += 0xBB67AE85u;
-  }
-  return {c0, c1, c2, c3};
-}
 
 __device__ inline float unit_open(uint32_t x) {
   return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace ens {
 
 constexpr int kMaxSave = 64;
@@ -63,5 +65,50 @@ int persistent_grid(int alg, int sys, int prec, int block, int num_cu);
 // Zero the persistent work counter (a one-thread kernel, so the solve can be
 // captured into a graph without memset nodes).
 hipError_t reset_queue(unsigned long long* q, hipStream_t s);
+
+}  // namespace ens
+
+// The context behind the opaque ens_ctx handle of include/ens.h.
+struct ens_ctx {
+  int device = 0;
+  int num_cu = 0;
+  int precision = 32;
+  int form = 0;
+  int block = 0;
+  int tpl = 1;
+  int refill = 16;
+  int grid = 0;
+  int tspan_bcast = 0;
+  double dt = 0.0;
+  double h0 = 0.0;
+  double seed = 0.0;
+  double maxiters = 1e6;
+  uint8_t* status = nullptr;
+  int32_t* stats = nullptr;
+  unsigned long long* queue = nullptr;  // device workspace: persistent work counter
+  std::string err;
+};
+
+namespace ens {
+
+// Records a formatted message on the context and returns `code`.
+int fail(ens_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+
+// Makes `dev` current for the lifetime of the guard, restoring the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = (prev == dev) || (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (ok && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Launch one adaptive or fixed-step solve described by `a` with `cfg`
+// (resets the persistent queue first when cfg.form == 1).
+int launch_solve(ens_ctx* c, int sys, int alg, LaunchArgs a, const LaunchCfg& cfg, hipStream_t s);
 
 }  // namespace ens

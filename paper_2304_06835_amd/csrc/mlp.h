@@ -1,0 +1,73 @@
+// mlp.h -- host-visible structures of the surrogate's kernels (mlp.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ens {
+
+constexpr int kMlpMaxLayers = 4;
+
+// Flat parameter vector: for each layer l, W_l row-major [dims[l+1]][dims[l]]
+// at w_off[l], then b_l [dims[l+1]] at b_off[l].
+struct MlpLayout {
+  int layers;
+  int dims[kMlpMaxLayers + 1];
+  int64_t w_off[kMlpMaxLayers];
+  int64_t b_off[kMlpMaxLayers];
+  int64_t total;
+};
+
+inline MlpLayout make_layout(const int* dims, int layers) {
+  MlpLayout L{};
+  L.layers = layers;
+  int64_t off = 0;
+  for (int l = 0; l <= layers; ++l) L.dims[l] = dims[l];
+  for (int l = 0; l < layers; ++l) {
+    L.w_off[l] = off;
+    off += (int64_t)dims[l] * dims[l + 1];
+    L.b_off[l] = off;
+    off += dims[l + 1];
+  }
+  L.total = off;
+  return L;
+}
+
+// Normalisation block (FP32, device): inputs (rho, x0, y0, z0) and the 48
+// outputs, each with mean, 1/std, std; the inputs also with the min / max of
+// the training set (the validated box).
+constexpr int kInMean = 0, kInIStd = 4, kInLo = 8, kInHi = 12;
+constexpr int kOutMean = 16, kOutIStd = 64, kOutStd = 112, kNormSize = 160;
+
+// Operand storage of the tiled matrix-core product: element (r, k) at
+// [r * ld + k] (kRowK) or [k * ld + r] (kKRow).
+enum { kRowK = 0, kKRow = 1 };
+
+struct MlpActs {
+  bool keep_all;        // training: every hidden layer's Z and A are kept
+  float* z[kMlpMaxLayers];
+  uint16_t* act[kMlpMaxLayers];
+  float* g[2];          // gradient ping-pong, FP32
+  uint16_t* gb[2];      // and bf16
+};
+
+struct RowSet {
+  const float* ptr[64];
+};
+
+hipError_t mlp_init(float* w, uint16_t* wb, const MlpLayout& L, uint64_t seed, hipStream_t s);
+hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s);
+hipError_t mlp_adam(float* w, float* m, float* v, const float* g, uint16_t* wb, int64_t n,
+                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t mlp_gather(const float* params, const float* u0, const float* y, int64_t n, int64_t q0,
+                      int64_t count, uint64_t mult, uint64_t add, const float* norm, uint16_t* a0,
+                      float* T, int nout, hipStream_t s);
+hipError_t mlp_row_stats(const RowSet& rows, int nrows, int64_t n, float* mean, float* istd,
+                         float* sd, float* lo, float* hi, hipStream_t s);
+hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, const float* norm,
+                       const uint16_t* a0, int64_t count, MlpActs& acts, float* Y,
+                       float* soa_out, int64_t soa_stride, int64_t q0, hipStream_t s);
+hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
+                        MlpActs& acts, const float* Y, const float* T, float* grad,
+                        double* partial, float* loss, hipStream_t s);
+
+}  // namespace ens

@@ -1,0 +1,595 @@
+// surrogate.hip -- C ABI of the learned surrogate (include/ens.h): model
+// storage, normalisation, training, inference, and the audited solve in
+// which the Tsit5 solver checks a random 1% of the answers and replaces the
+// surrogate wherever it is not validated.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+
+#include "../../include/ens.h"
+#include "ens_internal.h"
+#include "mlp.h"
+#include "philox.h"
+
+namespace {
+
+using ens::DeviceGuard;
+using ens::fail;
+
+constexpr int kDims[5] = {4, 256, 256, 256, 48};
+constexpr int kBins = 28;  // rho bins of the audit / fallback rule
+constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
+
+template <class T>
+hipError_t alloc(T** p, int64_t count) {
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * (size_t)(count > 0 ? count : 1));
+}
+
+// ---- audit / fallback kernels ----------------------------------------------
+
+__device__ inline void wave_append(bool take, int64_t value, int64_t* list, int64_t cap,
+                                   unsigned long long* count) {
+  const unsigned long long m = __ballot(take);
+  if (m == 0ull) return;
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader);
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t slot = (int64_t)base + __popcll(m & below);
+  if (take && slot < cap) list[slot] = value;
+}
+
+__device__ inline int rho_bin(float rho, const float* norm) {
+  const float lo = norm[ens::kInLo], hi = norm[ens::kInHi];
+  const float f = (rho - lo) / fmaxf(hi - lo, 1e-30f) * (float)kBins;
+  const int b = (int)floorf(f);
+  return b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+}
+
+__device__ inline bool in_box(const float* params, const float* u0, int64_t n, int64_t i,
+                              const float* norm) {
+  const float x[4] = {params[n + i], u0[i], u0[n + i], u0[2 * n + i]};
+  bool ok = true;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) ok = ok && x[f] >= norm[ens::kInLo + f] && x[f] <= norm[ens::kInHi + f];
+  return ok;
+}
+
+// Bernoulli(frac) audit draw per query from Philox4x32-10 (counter = query id).
+__global__ void select_audit(int64_t n, uint32_t thr, uint64_t seed, int64_t* list, int64_t cap,
+                             unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = false;
+  if (i < n) {
+    const ens::Philox4 r = ens::philox4x32_10((uint32_t)i, (uint32_t)((uint64_t)i >> 32), 7u, 0u,
+                                              (uint32_t)seed, (uint32_t)(seed >> 32));
+    take = r.x0 < thr;
+  }
+  wave_append(take, i, list, cap, count);
+}
+
+// For each audited query: normwise error of the surrogate against the solver
+// answer (max over save times of ||surr - sol||_inf / ||sol||_inf); a bin
+// with any error above tol (or non-finite) is flagged; the solver answer is
+// returned for the audited query itself.
+__global__ void audit_compare(const int64_t* list, const unsigned long long* count, int64_t cap,
+                              const float* sol, float* out, int64_t n, int n_save, int ncomp,
+                              const float* params, const float* norm, float tol,
+                              unsigned int* bins, uint8_t* used, unsigned int* max_err_bits) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cnt = (int64_t)(*count < (unsigned long long)cap ? *count : cap);
+  if (k >= cnt) return;
+  const int64_t i = list[k];
+  float err = 0.0f;
+  for (int j = 0; j < n_save; ++j) {
+    float num = 0.0f, den = 0.0f;
+    for (int c = 0; c < ncomp; ++c) {
+      const int64_t row = (int64_t)j * ncomp + c;
+      const float s = sol[row * cap + k];
+      const float g = out[row * n + i];
+      num = fmaxf(num, fabsf(g - s));
+      den = fmaxf(den, fabsf(s));
+      out[row * n + i] = s;
+    }
+    const float e = num / den;
+    err = (e == e) ? fmaxf(err, e) : 3.0e38f;
+  }
+  if (!(err <= tol)) atomicOr(&bins[rho_bin(params[n + i], norm)], 1u);
+  if (used) used[i] = 1;
+  atomicMax(max_err_bits, __float_as_uint(err));
+}
+
+// Queries that go to the solver: not audited, and outside the training box
+// or in a flagged rho bin.
+__global__ void select_fallback(int64_t n, const float* params, const float* u0,
+                                const float* norm, const unsigned int* bins, uint8_t* used,
+                                int64_t* list, unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool take = false;
+  if (i < n && used[i] == 0) {
+    take = !in_box(params, u0, n, i, norm) || bins[rho_bin(params[n + i], norm)] != 0u;
+    if (take) used[i] = 2;
+  }
+  wave_append(take, i, list, n, count);
+}
+
+__global__ void zero_u8(uint8_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void zero_words(unsigned int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// report = {audited, fallback, flagged bins, max audit error}
+__global__ void write_report(const unsigned long long* counts, const unsigned int* bins,
+                             const unsigned int* max_err_bits, float* report) {
+  if (threadIdx.x != 0) return;
+  int flagged = 0;
+  for (int b = 0; b < kBins; ++b) flagged += bins[b] != 0u;
+  report[0] = (float)counts[0];
+  report[1] = (float)counts[1];
+  report[2] = (float)flagged;
+  report[3] = __uint_as_float(*max_err_bits);
+}
+
+unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+struct ens_surrogate {
+  int device = 0;
+  ens::MlpLayout L{};
+  float* w = nullptr;
+  uint16_t* wb = nullptr;
+  float* m = nullptr;
+  float* v = nullptr;
+  float* grad = nullptr;
+  float* norm = nullptr;
+  int64_t step = 0;
+  // training workspace (batch capacity)
+  int64_t cap_batch = 0;
+  uint16_t* a0 = nullptr;
+  float* z[3] = {};
+  uint16_t* act[3] = {};
+  float* Y = nullptr;
+  float* T = nullptr;
+  float* g[2] = {};
+  uint16_t* gb[2] = {};
+  double* partial = nullptr;
+  // inference workspace (chunk capacity)
+  int64_t cap_chunk = 0;
+  uint16_t* ia0 = nullptr;
+  uint16_t* iact[2] = {};
+  // audited solve workspace
+  int64_t cap_n = 0, cap_audit = 0;
+  int64_t* alist = nullptr;
+  int64_t* flist = nullptr;
+  float* scratch = nullptr;
+  uint8_t* used = nullptr;
+  unsigned long long* counts = nullptr;  // [0] audited, [1] fallback
+  unsigned int* words = nullptr;         // [0, kBins) bins, [kBins] max error bits
+};
+
+namespace {
+
+void free_all(ens_surrogate* s) {
+  void* ps[] = {s->w, s->wb, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
+                s->act[0], s->act[1], s->act[2], s->Y, s->T, s->g[0], s->g[1], s->gb[0],
+                s->gb[1], s->partial, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
+                s->scratch, s->used, s->counts, s->words};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+}
+
+int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
+  if (B <= s->cap_batch) return ENS_OK;
+  void* old[] = {s->a0, s->z[0], s->z[1], s->z[2], s->act[0], s->act[1], s->act[2], s->Y, s->T,
+                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial};
+  for (void* p : old)
+    if (p) (void)hipFree(p);
+  const int H = kDims[1], O = kDims[4];
+  bool ok = alloc(&s->a0, B * kDims[0]) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
+            alloc(&s->T, B * O) == hipSuccess &&
+            alloc(&s->partial, (B * H + 255) / 256 + 1) == hipSuccess;
+  for (int l = 0; l < 3 && ok; ++l)
+    ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
+  for (int l = 0; l < 2 && ok; ++l)
+    ok = alloc(&s->g[l], B * H) == hipSuccess && alloc(&s->gb[l], B * H) == hipSuccess;
+  if (!ok) {
+    s->cap_batch = 0;
+    return fail(c, ENS_ENOMEM, "cannot allocate the training workspace for batch %lld",
+                (long long)B);
+  }
+  s->cap_batch = B;
+  return ENS_OK;
+}
+
+int ensure_chunk(ens_ctx* c, ens_surrogate* s, int64_t C) {
+  if (C <= s->cap_chunk) return ENS_OK;
+  void* old[] = {s->ia0, s->iact[0], s->iact[1]};
+  for (void* p : old)
+    if (p) (void)hipFree(p);
+  if (alloc(&s->ia0, C * kDims[0]) != hipSuccess || alloc(&s->iact[0], C * kDims[1]) != hipSuccess ||
+      alloc(&s->iact[1], C * kDims[1]) != hipSuccess) {
+    s->cap_chunk = 0;
+    return fail(c, ENS_ENOMEM, "cannot allocate the inference workspace");
+  }
+  s->cap_chunk = C;
+  return ENS_OK;
+}
+
+int check_model(ens_ctx* c, ens_surrogate* s) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  if (!s) return fail(c, ENS_EINVAL, "null surrogate");
+  if (s->device != c->device)
+    return fail(c, ENS_EINVAL, "surrogate lives on device %d, context on %d", s->device,
+                c->device);
+  return ENS_OK;
+}
+
+int predict(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0, int64_t n,
+            float* out, hipStream_t st) {
+  const int64_t C = n < ((int64_t)1 << 18) ? n : ((int64_t)1 << 18);
+  int rc = ensure_chunk(c, s, C);
+  if (rc != ENS_OK) return rc;
+  ens::MlpActs acts{};
+  acts.keep_all = false;
+  acts.act[0] = s->iact[0];
+  acts.act[1] = s->iact[1];
+  for (int64_t q0 = 0; q0 < n; q0 += C) {
+    const int64_t cnt = (n - q0) < C ? (n - q0) : C;
+    hipError_t e = ens::mlp_gather(params, u0, nullptr, n, q0, cnt, 1, 0, s->norm, s->ia0,
+                                   nullptr, kDims[4], st);
+    if (e == hipSuccess)
+      e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->ia0, cnt, acts, nullptr, out, n, q0, st);
+    if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate forward: %s", hipGetErrorString(e));
+  }
+  return ENS_OK;
+}
+
+int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+               const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult, uint64_t add,
+               double lr, float* loss, hipStream_t st) {
+  int rc = ensure_batch(c, s, B);
+  if (rc != ENS_OK) return rc;
+  ens::MlpActs acts{};
+  acts.keep_all = true;
+  for (int l = 0; l < 3; ++l) {
+    acts.z[l] = s->z[l];
+    acts.act[l] = s->act[l];
+  }
+  for (int l = 0; l < 2; ++l) {
+    acts.g[l] = s->g[l];
+    acts.gb[l] = s->gb[l];
+  }
+  hipError_t e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T,
+                                 kDims[4], st);
+  if (e == hipSuccess)
+    e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->a0, B, acts, s->Y, nullptr, 0, 0, st);
+  if (e == hipSuccess)
+    e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, s->grad, s->partial, loss, st);
+  if (e == hipSuccess) {
+    s->step += 1;
+    const double c1 = 1.0 / (1.0 - std::pow((double)kAdamB1, (double)s->step));
+    const double c2 = 1.0 / (1.0 - std::pow((double)kAdamB2, (double)s->step));
+    e = ens::mlp_adam(s->w, s->m, s->v, s->grad, s->wb, s->L.total, (float)lr, kAdamB1, kAdamB2,
+                      kAdamEps, (float)c1, (float)c2, st);
+  }
+  if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate train step: %s", hipGetErrorString(e));
+  return ENS_OK;
+}
+
+uint64_t splitmix(uint64_t& x) {
+  uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+uint64_t gcd(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ens_surrogate_create(ens_ctx* c, uint64_t seed, ens_surrogate** out) {
+  if (!c || !out) return ENS_EINVAL;
+  c->err.clear();
+  *out = nullptr;
+  DeviceGuard g(c->device);
+  if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
+  ens_surrogate* s = new (std::nothrow) ens_surrogate();
+  if (!s) return ENS_ENOMEM;
+  s->device = c->device;
+  s->L = ens::make_layout(kDims, 4);
+  const int64_t P = s->L.total;
+  bool ok = alloc(&s->w, P) == hipSuccess && alloc(&s->wb, P) == hipSuccess &&
+            alloc(&s->m, P) == hipSuccess && alloc(&s->v, P) == hipSuccess &&
+            alloc(&s->grad, P) == hipSuccess && alloc(&s->norm, ens::kNormSize) == hipSuccess &&
+            alloc(&s->counts, 2) == hipSuccess && alloc(&s->words, kBins + 1) == hipSuccess;
+  if (ok) ok = hipMemset(s->m, 0, sizeof(float) * P) == hipSuccess &&
+               hipMemset(s->v, 0, sizeof(float) * P) == hipSuccess &&
+               hipMemset(s->grad, 0, sizeof(float) * P) == hipSuccess;
+  if (ok) {
+    // identity normalisation until ens_surrogate_fit_norm is called
+    float nh[ens::kNormSize];
+    for (int k = 0; k < ens::kNormSize; ++k) nh[k] = 0.0f;
+    for (int f = 0; f < 4; ++f) {
+      nh[ens::kInIStd + f] = 1.0f;
+      nh[ens::kInLo + f] = -3.0e38f;
+      nh[ens::kInHi + f] = 3.0e38f;
+    }
+    for (int o = 0; o < 48; ++o) nh[ens::kOutIStd + o] = nh[ens::kOutStd + o] = 1.0f;
+    ok = hipMemcpy(s->norm, nh, sizeof nh, hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (ok) ok = ens::mlp_init(s->w, s->wb, s->L, seed, nullptr) == hipSuccess &&
+               hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    free_all(s);
+    delete s;
+    return fail(c, ENS_ENOMEM, "cannot allocate or initialise the surrogate");
+  }
+  *out = s;
+  return ENS_OK;
+}
+
+int ens_surrogate_destroy(ens_surrogate* s) {
+  if (!s) return ENS_OK;
+  {
+    DeviceGuard g(s->device);
+    free_all(s);
+  }
+  delete s;
+  return ENS_OK;
+}
+
+int ens_surrogate_copy(ens_ctx* c, ens_surrogate* s, int which, void* p, int to_model,
+                       void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (!p || (to_model != 0 && to_model != 1)) return fail(c, ENS_EINVAL, "bad copy arguments");
+  void* buf = nullptr;
+  size_t bytes = sizeof(float) * (size_t)s->L.total;
+  switch (which) {
+    case ENS_SURR_MASTER: buf = s->w; break;
+    case ENS_SURR_WEIGHTS_BF16: buf = s->wb; bytes = sizeof(uint16_t) * (size_t)s->L.total; break;
+    case ENS_SURR_GRAD: buf = s->grad; break;
+    case ENS_SURR_ADAM_M: buf = s->m; break;
+    case ENS_SURR_ADAM_V: buf = s->v; break;
+    case ENS_SURR_NORM: buf = s->norm; bytes = sizeof(float) * ens::kNormSize; break;
+    default: return fail(c, ENS_EINVAL, "unknown surrogate buffer %d", which);
+  }
+  DeviceGuard g(c->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = to_model ? hipMemcpyAsync(buf, p, bytes, hipMemcpyDeviceToDevice, st)
+                          : hipMemcpyAsync(p, buf, bytes, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && to_model && which == ENS_SURR_MASTER)
+    e = ens::mlp_to_bf16(s->w, s->wb, s->L.total, st);
+  return e == hipSuccess ? ENS_OK : fail(c, ENS_EDEVICE, "%s", hipGetErrorString(e));
+}
+
+int ens_surrogate_set_step(ens_surrogate* s, int64_t step) {
+  if (!s || step < 0) return ENS_EINVAL;
+  s->step = step;
+  return ENS_OK;
+}
+
+int ens_surrogate_get_step(const ens_surrogate* s, int64_t* step) {
+  if (!s || !step) return ENS_EINVAL;
+  *step = s->step;
+  return ENS_OK;
+}
+
+int ens_surrogate_fit_norm(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                           const float* y, int64_t n, void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 2 || !params || !u0 || !y) return fail(c, ENS_EINVAL, "need n >= 2 and device arrays");
+  DeviceGuard g(c->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ens::RowSet in{}, outr{};
+  in.ptr[0] = params + n;  // rho
+  for (int f = 0; f < 3; ++f) in.ptr[1 + f] = u0 + (int64_t)f * n;
+  for (int o = 0; o < kDims[4]; ++o) outr.ptr[o] = y + (int64_t)o * n;
+  hipError_t e = ens::mlp_row_stats(in, 4, n, s->norm + ens::kInMean, s->norm + ens::kInIStd,
+                                    nullptr, s->norm + ens::kInLo, s->norm + ens::kInHi, st);
+  if (e == hipSuccess)
+    e = ens::mlp_row_stats(outr, kDims[4], n, s->norm + ens::kOutMean, s->norm + ens::kOutIStd,
+                           s->norm + ens::kOutStd, nullptr, nullptr, st);
+  return e == hipSuccess ? ENS_OK : fail(c, ENS_EDEVICE, "%s", hipGetErrorString(e));
+}
+
+int ens_surrogate_train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                             const float* y, int64_t n, int64_t first, int64_t batch,
+                             uint64_t mult, uint64_t add, double lr, float* loss, void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 1 || batch < 1 || !params || !u0 || !y || !(lr >= 0.0))
+    return fail(c, ENS_EINVAL, "bad training arguments");
+  if (gcd(mult % (uint64_t)n, (uint64_t)n) != 1 && n > 1)
+    return fail(c, ENS_EINVAL, "mult must be coprime with n (a permutation of the set)");
+  DeviceGuard g(c->device);
+  return train_step(c, s, params, u0, y, n, first, batch, mult, add, lr, loss,
+                    static_cast<hipStream_t>(stream));
+}
+
+int ens_surrogate_train(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                        const float* y, int64_t n, int epochs, int64_t batch, double lr_max,
+                        double lr_min, uint64_t seed, float* epoch_loss, void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 1 || batch < 1 || batch > n || epochs < 1 || !params || !u0 || !y ||
+      !(lr_max >= lr_min) || !(lr_min >= 0.0))
+    return fail(c, ENS_EINVAL, "bad training arguments");
+  DeviceGuard g(c->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t steps = n / batch;
+  const int64_t total = steps * epochs;
+  uint64_t sm = seed;
+  int64_t k = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    uint64_t mult = splitmix(sm) % (uint64_t)n;
+    while (n > 1 && (mult == 0 || gcd(mult, (uint64_t)n) != 1)) mult = (mult + 1) % (uint64_t)n;
+    if (n == 1) mult = 1;
+    const uint64_t add = splitmix(sm) % (uint64_t)n;
+    for (int64_t b = 0; b < steps; ++b, ++k) {
+      const double lr =
+          lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(M_PI * (double)k / (double)total));
+      float* lp = (epoch_loss && b == steps - 1) ? epoch_loss + ep : nullptr;
+      rc = train_step(c, s, params, u0, y, n, b * batch, batch, mult, add, lr, lp, st);
+      if (rc != ENS_OK) return rc;
+    }
+  }
+  return ENS_OK;
+}
+
+int ens_surrogate_predict(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                          int64_t n, float* out, void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 0) return fail(c, ENS_EINVAL, "n < 0");
+  if (n == 0) return ENS_OK;
+  if (!params || !u0 || !out) return fail(c, ENS_EINVAL, "null device array");
+  DeviceGuard g(c->device);
+  return predict(c, s, params, u0, n, out, static_cast<hipStream_t>(stream));
+}
+
+int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                        const double* tspan, double abstol, double reltol,
+                        const double* save_times, int n_save, int64_t n, double audit_frac,
+                        double fallback_tol, uint64_t audit_seed, float* out,
+                        uint8_t* used_solver, float* report, void* stream) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 0) return fail(c, ENS_EINVAL, "n < 0");
+  if (n_save * 3 != kDims[4]) return fail(c, ENS_EINVAL, "the surrogate predicts 16 save times");
+  if (!(audit_frac >= 0.0 && audit_frac <= 1.0) || !(fallback_tol > 0.0))
+    return fail(c, ENS_EINVAL, "audit_frac in [0, 1] and fallback_tol > 0 required");
+  if (!save_times || !(abstol > 0.0) || !(reltol > 0.0))
+    return fail(c, ENS_EINVAL, "save_times and positive tolerances required");
+  for (int j = 0; j < n_save; ++j)
+    if (!(save_times[j] > (j ? save_times[j - 1] : 0.0)) || !(save_times[j] <= 1.0))
+      return fail(c, ENS_EINVAL, "save_times must be strictly increasing in (0, 1]");
+  if (n == 0) return ENS_OK;
+  if (!params || !u0 || !tspan || !out) return fail(c, ENS_EINVAL, "null device array");
+  DeviceGuard g(c->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // workspace for n queries
+  const int64_t cap_a = (int64_t)std::ceil(audit_frac * (double)n * 1.5) + 4096;
+  if (n > s->cap_n || cap_a > s->cap_audit) {
+    void* old[] = {s->alist, s->flist, s->scratch, s->used};
+    for (void* p : old)
+      if (p) (void)hipFree(p);
+    s->alist = s->flist = nullptr;
+    s->scratch = nullptr;
+    s->used = nullptr;
+    s->cap_n = s->cap_audit = 0;
+    const int64_t nn = n > s->cap_n ? n : s->cap_n;
+    if (alloc(&s->alist, cap_a) != hipSuccess || alloc(&s->flist, nn) != hipSuccess ||
+        alloc(&s->scratch, cap_a * kDims[4]) != hipSuccess || alloc(&s->used, nn) != hipSuccess)
+      return fail(c, ENS_ENOMEM, "cannot allocate the audit workspace");
+    s->cap_n = nn;
+    s->cap_audit = cap_a;
+  }
+  uint8_t* used = used_solver ? used_solver : s->used;
+  hipError_t e = hipSuccess;
+#define ENS_TRY(x)                                                                   \
+  do {                                                                               \
+    if ((e = (x)) != hipSuccess)                                                     \
+      return fail(c, ENS_EDEVICE, "surrogate solve: %s", hipGetErrorString(e));     \
+  } while (0)
+  hipLaunchKernelGGL(zero_u8, dim3(grid_of(n)), dim3(256), 0, st, used, n);
+  ENS_TRY(hipGetLastError());
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, s->words, kBins + 1);
+  ENS_TRY(hipGetLastError());
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st,
+                     reinterpret_cast<unsigned int*>(s->counts), 4);
+  ENS_TRY(hipGetLastError());
+
+  // 1. surrogate answers for every query
+  rc = predict(c, s, params, u0, n, out, st);
+  if (rc != ENS_OK) return rc;
+
+  // 2. audit sample: Bernoulli(audit_frac) per query
+  const double thr_d = std::floor(audit_frac * 4294967296.0);
+  const uint32_t thr = thr_d >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)thr_d;
+  hipLaunchKernelGGL(select_audit, dim3(grid_of(n)), dim3(256), 0, st, n, thr, audit_seed,
+                     s->alist, s->cap_audit, s->counts);
+  ENS_TRY(hipGetLastError());
+
+  // 3. solve the audited queries (persistent Tsit5, FP32, count read on the device)
+  ens::LaunchArgs a{};
+  a.n = s->cap_audit;
+  a.in_stride = n;
+  a.out_stride = s->cap_audit;
+  a.params = params;
+  a.u0 = u0;
+  a.tspan = tspan;
+  a.out = s->scratch;
+  a.idx = s->alist;
+  a.n_dev = s->counts;
+  a.scatter = 0;
+  a.queue = c->queue;
+  a.atol = abstol;
+  a.rtol = reltol;
+  a.h0 = 0.0;
+  a.maxiters = (int64_t)c->maxiters;
+  a.n_save = n_save;
+  a.tspan_bcast = c->tspan_bcast;
+  a.refill = c->refill;
+  a.tpl = 1;
+  for (int j = 0; j < n_save; ++j) a.theta[j] = save_times[j];
+  const int saved_prec = c->precision;
+  c->precision = 32;
+  ens::LaunchCfg cfg{1, 256, 0};
+  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
+  c->precision = saved_prec;
+  if (rc != ENS_OK) return rc;
+
+  // 4. compare, flag bins, return the solver's answer for audited queries
+  hipLaunchKernelGGL(audit_compare, dim3(grid_of(s->cap_audit)), dim3(256), 0, st, s->alist,
+                     s->counts, s->cap_audit, s->scratch, out, n, n_save, 3, params, s->norm,
+                     (float)fallback_tol, s->words, used, s->words + kBins);
+  ENS_TRY(hipGetLastError());
+
+  // 5. fallback set: outside the box or in a flagged bin
+  hipLaunchKernelGGL(select_fallback, dim3(grid_of(n)), dim3(256), 0, st, n, params, u0, s->norm,
+                     s->words, used, s->flist, s->counts + 1);
+  ENS_TRY(hipGetLastError());
+
+  // 6. solve them straight into out
+  a.n = n;
+  a.out = out;
+  a.out_stride = n;
+  a.idx = s->flist;
+  a.n_dev = s->counts + 1;
+  a.scatter = 1;
+  c->precision = 32;
+  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
+  c->precision = saved_prec;
+  if (rc != ENS_OK) return rc;
+
+  if (report) {
+    hipLaunchKernelGGL(write_report, dim3(1), dim3(64), 0, st, s->counts, s->words,
+                       s->words + kBins, report);
+    ENS_TRY(hipGetLastError());
+  }
+#undef ENS_TRY
+  return ENS_OK;
+}
+
+}  // extern "C"
