@@ -176,6 +176,11 @@ def test_training_reduces_loss(ens):
     assert m.step == 30 * 16
 
 
+def bits(x):
+    """Byte view of a (possibly fancy-indexed, hence strided) float array."""
+    return np.ascontiguousarray(x).view(np.uint8)
+
+
 def test_audit_and_fallback_rule(ens):
     """tol -> 0: every bin fails its audit, so every answer is the solver's
     (bit-identical to ens_solve); tol -> inf: only the audited queries are
@@ -200,9 +205,9 @@ def test_audit_and_fallback_rule(ens):
     out, used, rep = to_host(out), to_host(used), to_host(rep)
     assert rep[2] == 0 and (used == 2).sum() == rep[1]
     a = used == 1
-    assert np.array_equal(out[:, :, a].view(np.uint8), sol[:, :, a].view(np.uint8))
+    assert np.array_equal(bits(out[:, :, a]), bits(sol[:, :, a]))
     z = used == 0
-    assert np.array_equal(out[:, :, z].view(np.uint8), pred[:, :, z].view(np.uint8))
+    assert np.array_equal(bits(out[:, :, z]), bits(pred[:, :, z]))
     # the same audit sample for the same seed
     _, used2, _ = m.solve(P, U, T, e.abstol, e.reltol, e.theta, audit_frac=0.05,
                           fallback_tol=1e30, audit_seed=8)
