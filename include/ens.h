@@ -96,6 +96,9 @@ typedef struct ens_ctx ens_ctx;
 #define ENS_OPT_TPL 11      /* one-lane-per-trajectory form: trajectories each
                                lane integrates one after another, 1..8 (default
                                1); lane g of G takes g, g + G, g + 2G, ...      */
+#define ENS_OPT_MLP_TILE 12 /* surrogate inference: 16-query subtiles per wave of
+                               the fused kernel (2, 3 or 4; default 4), or 0 for
+                               the layer-by-layer tiled-product path          */
 
 /* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
 #define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,

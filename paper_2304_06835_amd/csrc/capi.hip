@@ -278,6 +278,11 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       if (!integral || v < 1 || v > 8) return fail(c, ENS_EINVAL, "tpl must be in [1, 8]");
       c->tpl = (int)v;
       return ENS_OK;
+    case ENS_OPT_MLP_TILE:
+      if (v != 0 && v != 2 && v != 3 && v != 4)
+        return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3 or 4");
+      c->mlp_tile = (int)v;
+      return ENS_OK;
   }
   return fail(c, ENS_EINVAL, "unknown option key %d", key);
 }
@@ -296,6 +301,7 @@ int ens_get_option(const ens_ctx* c, int key, double* v) {
     case ENS_OPT_REFILL: *v = c->refill; return ENS_OK;
     case ENS_OPT_GRID: *v = c->grid; return ENS_OK;
     case ENS_OPT_TPL: *v = c->tpl; return ENS_OK;
+    case ENS_OPT_MLP_TILE: *v = c->mlp_tile; return ENS_OK;
   }
   return ENS_EINVAL;
 }

@@ -70,4 +70,12 @@ hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* 
                         MlpActs& acts, const float* Y, const float* T, float* grad,
                         double* partial, float* loss, hipStream_t s);
 
+// Fused inference kernel (mlp_fused.hip): weights re-laid out fragment-major
+// by mlp_pack into a buffer of mlp_packed_elems() bf16 values.
+int64_t mlp_packed_elems();
+hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hipStream_t s);
+hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const float* w,
+                             const float* norm, const float* params, const float* u0, int64_t n,
+                             float* out, int64_t stride, int num_cu, int ns, hipStream_t s);
+
 }  // namespace ens

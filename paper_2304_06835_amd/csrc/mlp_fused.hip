@@ -1,0 +1,330 @@
+// mlp_fused.hip -- inference of the surrogate MLP (rho, x0, y0, z0) -> 256 ->
+// 256 -> 256 -> 48 in one persistent kernel.
+//
+// Layer l computes Z_l = W_l A_{l-1} + b_l for a tile of queries on the
+// matrix cores (v_mfma_f32_16x16x32_bf16: bf16 operands, FP32 accumulation)
+// and A_l = bf16(silu(Z_l)).  The activations never leave registers: a
+// 16 x 16 accumulator tile leaves each lane with four consecutive output
+// features of one query, and two such tiles (32 features) are exactly the
+// eight k-values one lane feeds into the next layer's product -- provided
+// the next layer's weights are read with the matching permutation of k
+// inside every 32-wide block.  `pack_weights` stores the weights in that
+// permuted, fragment-major order (one 1 KiB fragment = one wave-wide
+// 16-byte-per-lane load), so the kernel streams them into LDS with direct
+// global->LDS loads and each lane reads its fragment with one ds_read_b128.
+//
+// Per block (4 waves, one per SIMD) and tile of 64*NS queries: layer 1 (K = 4,
+// zero-padded to 32) and layer 4 (48 outputs) read their fragments from LDS
+// copies made once per block; the two 256 x 256 layers stream through a
+// double-buffered ring of 32 KiB chunks (64 output rows each), the next
+// chunk loading while the current one is used.  Each fragment read from LDS
+// feeds NS products (one per 16-query subtile), which keeps LDS traffic at
+// 1/NS of the matrix-core operand rate.
+#include "../../include/ens.h"
+#include "ens_internal.h"
+#include "mlp.h"
+
+namespace ens {
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kH = 256, kNO = 48;
+constexpr int kFrag = 512;  // bf16 elements of one fragment (64 lanes x 8)
+// packed fragment-major weights (bf16 elements)
+constexpr int64_t kP1 = 0;                  // layer 1: 16 row blocks
+constexpr int64_t kP2 = kP1 + 16 * kFrag;   // layer 2: 16 row blocks x 8 k-blocks
+constexpr int64_t kP3 = kP2 + 128 * kFrag;  // layer 3: same
+constexpr int64_t kP4 = kP3 + 128 * kFrag;  // layer 4: 3 row blocks x 8 k-blocks
+constexpr int64_t kPTotal = kP4 + 24 * kFrag;
+constexpr int kChunkBytes = 32 * kFrag * 2;  // 4 row blocks x 8 k-blocks
+
+// LDS map (bytes)
+constexpr int kLdsW1 = 0;
+constexpr int kLdsW4 = kLdsW1 + 16 * kFrag * 2;
+constexpr int kLdsRing = kLdsW4 + 24 * kFrag * 2;
+constexpr int kLdsBias = kLdsRing + 2 * kChunkBytes;
+// floats at kLdsBias: b1 [256], b2 [256], b3 [256], b4 [48], out mean [48],
+// out std [48], in mean [4], in 1/std [4]
+constexpr int kBB1 = 0, kBB2 = 256, kBB3 = 512, kBB4 = 768, kBMean = 816, kBStd = 864,
+              kBInMean = 912, kBInIStd = 916, kBCount = 920;
+constexpr int kLdsBytes = kLdsBias + kBCount * 4;
+
+// Logical k (0..31) of a lane's B-operand slot -> feature inside the 32-block:
+// lane group g holds features 4g..4g+3 of the first 16-row accumulator tile
+// and 16+4g..16+4g+3 of the second.
+__host__ __device__ constexpr int perm32(int k) {
+  return (k & 7) < 4 ? 4 * (k >> 3) + (k & 7) : 16 + 4 * (k >> 3) + (k & 7) - 4;
+}
+
+__global__ void pack_weights(const uint16_t* __restrict__ wb, MlpLayout L,
+                             uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kPTotal) return;
+  const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+  const int64_t f = i >> 9;
+  const int r16 = lane & 15, g = lane >> 4;
+  uint16_t v = 0;
+  if (i < kP2) {  // A operand of layer 1: row 16f + r16, k = 8g + e (< 4 real)
+    const int row = 16 * (int)f + r16, k = 8 * g + e;
+    if (k < 4) v = wb[L.w_off[0] + row * 4 + k];
+  } else {
+    int layer;
+    int64_t ff;
+    if (i < kP3) {
+      layer = 1;
+      ff = f - kP2 / kFrag;
+    } else if (i < kP4) {
+      layer = 2;
+      ff = f - kP3 / kFrag;
+    } else {
+      layer = 3;
+      ff = f - kP4 / kFrag;
+    }
+    const int rb = (int)(ff >> 3), kb = (int)(ff & 7);
+    const int row = 16 * rb + r16, col = 32 * kb + perm32(8 * g + e);
+    v = wb[L.w_off[layer] + (int64_t)row * kH + col];
+  }
+  out[i] = v;
+}
+
+struct FusedArgs {
+  const uint16_t* packed;
+  const float* w;  // FP32 master parameters (biases)
+  const float* norm;
+  const float* params;  // [3][n]: sigma, rho, beta
+  const float* u0;      // [3][n]
+  float* out;           // [48][stride]
+  int64_t n, stride;
+  int64_t b_off[4];
+};
+
+__device__ inline float silu(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+
+__device__ inline bf16x8_t silu_pack(f32x4_t lo, f32x4_t hi) {
+  bf16x8_t r;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    r[e] = (__bf16)silu(lo[e]);
+    r[4 + e] = (__bf16)silu(hi[e]);
+  }
+  return r;
+}
+
+__device__ inline bf16x8_t frag(const uint8_t* lds, int byte_off, int lane) {
+  return *reinterpret_cast<const bf16x8_t*>(lds + byte_off + lane * 16);
+}
+
+__device__ inline f32x4_t bias4(const uint8_t* lds, int idx) {
+  return *reinterpret_cast<const f32x4_t*>(lds + kLdsBias + idx * 4);
+}
+
+// This wave's quarter of one 32 KiB chunk: 8 fragments, global -> LDS.
+__device__ inline void load_chunk(const uint16_t* src, uint8_t* slot, int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int fi = wave * 8 + j;
+    __builtin_amdgcn_global_load_lds(
+        reinterpret_cast<const void*>(src + (int64_t)fi * kFrag + lane * 8),
+        (__attribute__((address_space(3))) void*)(slot + fi * kFrag * 2), 16, 0, 0);
+  }
+}
+
+__device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// One 64-row chunk of a 256 x 256 layer: pairs of 16-row blocks (2c, 2c+1)
+// and (2c+2, 2c+3) of the output for every subtile.
+template <int NS>
+__device__ inline void chunk_layer(const uint8_t* lds, int slot_off, int c, int bias0, int g,
+                                   int lane, const bf16x8_t (&x)[NS][8], bf16x8_t (&y)[NS][8]) {
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const int rb = 4 * c + 2 * pp;  // global row block of the pair's first tile
+    f32x4_t acc[2][NS];
+    const f32x4_t b0 = bias4(lds, bias0 + 16 * rb + 4 * g);
+    const f32x4_t b1 = bias4(lds, bias0 + 16 * (rb + 1) + 4 * g);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      acc[0][s] = b0;
+      acc[1][s] = b1;
+    }
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) {
+      const bf16x8_t a0 = frag(lds, slot_off + ((2 * pp) * 8 + kb) * kFrag * 2, lane);
+      const bf16x8_t a1 = frag(lds, slot_off + ((2 * pp + 1) * 8 + kb) * kFrag * 2, lane);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        acc[0][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, x[s][kb], acc[0][s], 0, 0, 0);
+        acc[1][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x[s][kb], acc[1][s], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) y[s][rb >> 1] = silu_pack(acc[0][s], acc[1][s]);
+  }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+mlp_fused_fwd(const FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, col = lane & 15;
+
+  {  // per-block copies: layer-1 and layer-4 fragments, biases, normalisation
+    const uint4* s1 = reinterpret_cast<const uint4*>(a.packed + kP1);
+    const uint4* s4 = reinterpret_cast<const uint4*>(a.packed + kP4);
+    uint4* d1 = reinterpret_cast<uint4*>(lds + kLdsW1);
+    uint4* d4 = reinterpret_cast<uint4*>(lds + kLdsW4);
+    for (int i = tid; i < 16 * kFrag / 8; i += 256) d1[i] = s1[i];
+    for (int i = tid; i < 24 * kFrag / 8; i += 256) d4[i] = s4[i];
+    float* bs = reinterpret_cast<float*>(lds + kLdsBias);
+    bs[kBB1 + tid] = a.w[a.b_off[0] + tid];
+    bs[kBB2 + tid] = a.w[a.b_off[1] + tid];
+    bs[kBB3 + tid] = a.w[a.b_off[2] + tid];
+    if (tid < kNO) {
+      bs[kBB4 + tid] = a.w[a.b_off[3] + tid];
+      bs[kBMean + tid] = a.norm[kOutMean + tid];
+      bs[kBStd + tid] = a.norm[kOutStd + tid];
+    }
+    if (tid < 4) {
+      bs[kBInMean + tid] = a.norm[kInMean + tid];
+      bs[kBInIStd + tid] = a.norm[kInIStd + tid];
+    }
+  }
+  load_chunk(a.packed + kP2, lds + kLdsRing, wave, lane);  // layer 2, chunk 0 -> slot 0
+  __syncthreads();
+
+  const float* bs = reinterpret_cast<const float*>(lds + kLdsBias);
+  const int64_t n = a.n, tq = 64 * NS;
+  const int64_t ntiles = (n + tq - 1) / tq;
+  int slot = 0;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t qw = tile * tq + (int64_t)wave * 16 * NS;  // this wave's first query
+    bf16x8_t xa[NS][8], xb[NS][8];
+
+    // ---- layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane group 0
+    {
+      bf16x8_t xin[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int64_t q = qw + 16 * s + col;
+        float f[4] = {0.f, 0.f, 0.f, 0.f};
+        if (g == 0 && q < n) {
+          f[0] = a.params[n + q];
+          f[1] = a.u0[q];
+          f[2] = a.u0[n + q];
+          f[3] = a.u0[2 * n + q];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) f[k] = (f[k] - bs[kBInMean + k]) * bs[kBInIStd + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          xin[s][k] = (__bf16)f[k];
+          xin[s][4 + k] = (__bf16)0.0f;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < 8; ++p) {
+        const bf16x8_t a0 = frag(lds, kLdsW1 + (2 * p) * kFrag * 2, lane);
+        const bf16x8_t a1 = frag(lds, kLdsW1 + (2 * p + 1) * kFrag * 2, lane);
+        const f32x4_t b0 = bias4(lds, kBB1 + 32 * p + 4 * g);
+        const f32x4_t b1 = bias4(lds, kBB1 + 32 * p + 16 + 4 * g);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const f32x4_t z0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, xin[s], b0, 0, 0, 0);
+          const f32x4_t z1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, xin[s], b1, 0, 0, 0);
+          xa[s][p] = silu_pack(z0, z1);
+        }
+      }
+    }
+
+    // ---- layers 2 and 3: four chunks each through the LDS ring
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      wait_vm();
+      __syncthreads();
+      load_chunk(a.packed + (c < 3 ? kP2 + (c + 1) * 32 * kFrag : kP3),
+                 lds + kLdsRing + (slot ^ 1) * kChunkBytes, wave, lane);
+      chunk_layer<NS>(lds, kLdsRing + slot * kChunkBytes, c, kBB2, g, lane, xa, xb);
+      slot ^= 1;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      wait_vm();
+      __syncthreads();
+      load_chunk(a.packed + (c < 3 ? kP3 + (c + 1) * 32 * kFrag : kP2),
+                 lds + kLdsRing + (slot ^ 1) * kChunkBytes, wave, lane);
+      chunk_layer<NS>(lds, kLdsRing + slot * kChunkBytes, c, kBB3, g, lane, xb, xa);
+      slot ^= 1;
+    }
+
+    // ---- layer 4: 48 outputs, de-normalised into out[o][q]
+#pragma unroll
+    for (int rb = 0; rb < 3; ++rb) {
+      f32x4_t acc[NS];
+      const f32x4_t b = bias4(lds, kBB4 + 16 * rb + 4 * g);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) acc[s] = b;
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) {
+        const bf16x8_t w = frag(lds, kLdsW4 + (rb * 8 + kb) * kFrag * 2, lane);
+#pragma unroll
+        for (int s = 0; s < NS; ++s)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xa[s][kb], acc[s], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const int64_t q = qw + 16 * s + col;
+        if (q < n) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int o = 16 * rb + 4 * g + r;
+            a.out[(int64_t)o * a.stride + q] = fmaf(acc[s][r], bs[kBStd + o], bs[kBMean + o]);
+          }
+        }
+      }
+    }
+  }
+  wait_vm();  // no global->LDS load may land after the block has left
+}
+
+}  // namespace
+
+int64_t mlp_packed_elems() { return kPTotal; }
+
+hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hipStream_t s) {
+  hipLaunchKernelGGL(pack_weights, dim3((unsigned)((kPTotal + 255) / 256)), dim3(256), 0, s, wb,
+                     L, packed);
+  return hipGetLastError();
+}
+
+// out[o][q] for q in [0, n), o in [0, 48); `stride` is the row length of out.
+hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const float* w,
+                             const float* norm, const float* params, const float* u0, int64_t n,
+                             float* out, int64_t stride, int num_cu, int ns, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  FusedArgs a{};
+  a.packed = packed;
+  a.w = w;
+  a.norm = norm;
+  a.params = params;
+  a.u0 = u0;
+  a.out = out;
+  a.n = n;
+  a.stride = stride;
+  for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
+  const int64_t tq = 64 * (int64_t)ns;
+  const int64_t ntiles = (n + tq - 1) / tq;
+  const unsigned grid = (unsigned)(ntiles < num_cu ? ntiles : num_cu);
+  switch (ns) {
+    case 2: hipLaunchKernelGGL(mlp_fused_fwd<2>, dim3(grid), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(mlp_fused_fwd<3>, dim3(grid), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(mlp_fused_fwd<4>, dim3(grid), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ens

@@ -146,6 +146,7 @@ struct ens_surrogate {
   ens::MlpLayout L{};
   float* w = nullptr;
   uint16_t* wb = nullptr;
+  uint16_t* packed = nullptr;  // fragment-major copy of wb for the fused kernel
   float* m = nullptr;
   float* v = nullptr;
   float* grad = nullptr;
@@ -178,7 +179,7 @@ struct ens_surrogate {
 namespace {
 
 void free_all(ens_surrogate* s) {
-  void* ps[] = {s->w, s->wb, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
+  void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
                 s->act[0], s->act[1], s->act[2], s->Y, s->T, s->g[0], s->g[1], s->gb[0],
                 s->gb[1], s->partial, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
                 s->scratch, s->used, s->counts, s->words};
@@ -235,6 +236,14 @@ int check_model(ens_ctx* c, ens_surrogate* s) {
 
 int predict(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0, int64_t n,
             float* out, hipStream_t st) {
+  if (c->mlp_tile != 0) {  // fused kernel on weights re-packed from the current bf16 copy
+    hipError_t e = ens::mlp_pack(s->wb, s->L, s->packed, st);
+    if (e == hipSuccess)
+      e = ens::mlp_forward_fused(s->L, s->packed, s->w, s->norm, params, u0, n, out, n, c->num_cu,
+                                 c->mlp_tile, st);
+    if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate forward: %s", hipGetErrorString(e));
+    return ENS_OK;
+  }
   const int64_t C = n < ((int64_t)1 << 18) ? n : ((int64_t)1 << 18);
   int rc = ensure_chunk(c, s, C);
   if (rc != ENS_OK) return rc;
@@ -317,6 +326,7 @@ int ens_surrogate_create(ens_ctx* c, uint64_t seed, ens_surrogate** out) {
   s->L = ens::make_layout(kDims, 4);
   const int64_t P = s->L.total;
   bool ok = alloc(&s->w, P) == hipSuccess && alloc(&s->wb, P) == hipSuccess &&
+            alloc(&s->packed, ens::mlp_packed_elems()) == hipSuccess &&
             alloc(&s->m, P) == hipSuccess && alloc(&s->v, P) == hipSuccess &&
             alloc(&s->grad, P) == hipSuccess && alloc(&s->norm, ens::kNormSize) == hipSuccess &&
             alloc(&s->counts, 2) == hipSuccess && alloc(&s->words, kBins + 1) == hipSuccess;

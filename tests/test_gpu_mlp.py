@@ -75,11 +75,16 @@ def test_init_statistics(ens):
     assert np.array_equal(mlp.bf16_round(th).astype(np.float32).view(np.uint32) >> 16, wb)
 
 
-def test_forward_matches_oracle(ens):
+@pytest.mark.parametrize("tile", [0, 2, 3, 4])
+def test_forward_matches_oracle(ens, tile):
+    """tile 0: layer-by-layer tiled products (64-query tiles: 15 full + a
+    ragged one); 2/3/4: the fused kernel with 128/192/256-query block tiles
+    (ragged last tile in every case)."""
     th = random_theta(1)
-    e = W.lorenz_fp32(N=1000, seed=11)   # 15 full tiles of 64 + a ragged one
-    banner("mlp forward N=1000")
+    e = W.lorenz_fp32(N=1000, seed=11)
+    banner(f"mlp forward N=1000 tile={tile}")
     s, m = make_model(ens, th)
+    s.set(mlp_tile=tile)
     out = to_host(m.predict(to_dev(e.params), to_dev(e.u0)))
     Y, _ = mlp.forward(th, features(e.params, e.u0), bf16=True)
     got = out.reshape(48, -1).T
@@ -88,6 +93,32 @@ def test_forward_matches_oracle(ens):
     print("forward: max rel %.3e (no-rounding network differs by %.3e)"
           % (err, np.abs(got - ref_nb).max() / np.abs(Y).max()))
     assert err <= FWD_BAR
+
+
+@pytest.mark.parametrize("tile", [2, 3, 4])
+def test_fused_forward_matches_tiled_path_across_many_tiles(ens, tile):
+    """The fused kernel against the layer-by-layer path on 300,007 queries:
+    more tiles than blocks (every block loops, the LDS weight ring wraps many
+    times) and a ragged last tile.  Both use the same bf16 operands; only
+    FP32 accumulation order and the SiLU evaluation differ."""
+    th = random_theta(4)
+    e = W.lorenz_fp32(N=300007, seed=13)
+    banner(f"fused vs tiled N=300007 tile={tile}")
+    s, m = make_model(ens, th)
+    P, U = to_dev(e.params), to_dev(e.u0)
+    s.set(mlp_tile=0)
+    ref = to_host(m.predict(P, U))
+    s.set(mlp_tile=tile)
+    got = to_host(m.predict(P, U))
+    assert np.isfinite(got).all()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("fused vs tiled: max rel %.3e" % err)
+    assert err <= FWD_BAR
+    # and against the oracle on a sample of queries spread over all tiles
+    idx = np.linspace(0, e.n - 1, 997).astype(np.int64)
+    Y, _ = mlp.forward(th, features(e.params[:, idx], e.u0[:, idx]), bf16=True)
+    g = got.reshape(48, -1)[:, idx].T
+    assert np.abs(g - Y).max() / np.abs(Y).max() <= FWD_BAR
 
 
 def test_gradient_and_adam_match_oracle(ens):
