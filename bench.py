@@ -6,18 +6,23 @@ Tsit5 at reltol = abstol = 1e-6, 16 evenly spaced saves on t in [0, 1].
 One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
     python bench.py [--steps K] [--warmup W] [--workload lorenz_fp32|lorenz_fp64|
-                     robertson|gbm] [--form plain|persistent|auto] [--no-cpu-baseline]
+                     robertson|gbm] [--form plain|persistent|sorted|auto]
+                    [--no-cpu-baseline] [--no-variants] [--no-surrogate]
 
-Prints one JSON line.  The roofline object reports the solver kernel's
-algorithmic FP32 (or FP64) flop rate -- flops per attempted step of the
-method x attempted steps, over the kernel time measured with events on the
-launch stream -- against the non-packed VALU peak.  The cpu_baseline leg times
-the FP64 C oracle on a bounded sample on the host cores and reports the max
-normwise relative error of the GPU result against the oracle.
+Prints one JSON line.  `roofline` reports the solver kernel's algorithmic
+flop rate -- flops per attempted step of the method x attempted steps, over
+the kernel time measured with events on the launch stream -- against the
+MI355X vector peak of the arithmetic type.  `variants` times the other
+work-assignment forms on the same inputs (bitwise-identical answers), the
+stiff Robertson ensemble's forms, and the learned surrogate's audited solve
+against the plain solver.  `cpu_baseline` times the FP64 C oracle on a
+bounded sample on the host cores; `accuracy` is the GPU result's max
+normwise relative error against the FP64 oracle on a 4096 subsample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,29 +44,36 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 #  EM, GBM4: per step 4 x (2 flops for the increment + 2 for the update) +
 #    Box-Muller 2 x 8  -> 32 (Philox is integer work, counted separately).
 FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("em", "gbm4"): 32}
+MLP_FLOPS_PER_QUERY = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 48)  # 288,768
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.  A non-packed FMA retires
-# 2 flops per lane per cycle in FP32 and in FP64: 78.6 TFLOP/s for both.
-# (The published 157.3 TFLOP/s FP32 figure counts packed dual-FP32 FMAs,
-# which this library does not emit.)
-PEAK_FP32_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-PEAK_FP32_PUBLISHED = 157.3
-PEAK_FP64 = 78.6
+# MI355X published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s, FP64
+# 78.6 TFLOP/s; dense bf16 MFMA 2.5 PFLOP/s.  The FP32 figure is reached by
+# ordinary (non-packed) FP32 instructions on gfx950: a microbenchmark of
+# independent v_fma/v_mul/v_add_f32 chains issues 21-23 lane-ops per SIMD
+# clock, above the 16 of a 16-lane SIMD (FP64 FMA: 12.3; exp/rcp: ~7).
+PEAK = {32: 157.3, 64: 78.6}
+PEAK_BF16_MFMA = 2500.0
+
+FORMS = {"plain": {"form": 0}, "persistent": {"form": 1},
+         "sorted": {"form": 2, "block": 256}}
+DEFAULT_FORM = {"lorenz_fp32": "sorted", "lorenz_fp64": "plain", "robertson": "sorted",
+                "gbm": "plain"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lorenz_fp32",
                     choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm"])
     ap.add_argument("--n", type=int, default=0, help="override the ensemble size")
-    ap.add_argument("--form", default="plain", choices=["plain", "persistent", "auto"])
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--form", default="", choices=["", "plain", "persistent", "sorted", "auto"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-epochs", type=int, default=120)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU-baseline sample")
     return ap.parse_args()
 
@@ -85,16 +97,40 @@ def describe(e):
     return "GBM 4-component 2^22-ensemble, Euler-Maruyama dt=1/256, Philox4x32-10, FP32"
 
 
+def dev(a):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def event_time(fn, steps, warmup):
+    """Run fn warmup + steps times; (wall s, mean event ms, min event ms) of the
+    timed steps, events recorded on torch's current stream (the launch stream)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ker = [a.elapsed_time(b) for a, b in evs]
+    return wall, sum(ker) / len(ker), min(ker)
+
+
 class Runner:
     """Device copies of one workload and a configured solver context."""
 
     def __init__(self, e, precision, **opts):
-        import numpy as np
         import torch
 
         import paper_2304_06835_amd as ens
         self.e = e
-        dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
         self.params, self.u0, self.tspan = dev(e.params), dev(e.u0), dev(e.tspan)
         self.s = ens.Solver(0, precision=precision)
         if e.h0:
@@ -120,21 +156,35 @@ class Runner:
         return int(st.to(torch.int64).sum().item()), st
 
     def time(self, steps, warmup):
-        import torch
-        for _ in range(warmup):
-            self.solve()
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(steps)]
-        t0 = time.perf_counter()
-        for a, b in evs:
-            a.record()
-            self.solve()
-            b.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ker = [a.elapsed_time(b) for a, b in evs]
-        return wall, sum(ker) / len(ker), min(ker)
+        return event_time(self.solve, steps, warmup)
+
+    def host_out(self):
+        return self.out.cpu().numpy()
+
+
+def kernel_source_hash():
+    """Hash of the solver sources a recorded traffic measurement refers to."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2304_06835_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(name, form, launches_units):
+    """HBM bytes per launch from a committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record (profiles/traffic.json), if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    r = rec.get(f"{name}/{form}")
+    if not r or r.get("source_hash") != kernel_source_hash():
+        return None
+    return r.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(e, gpu_out, seconds):
@@ -161,11 +211,18 @@ def cpu_baseline(e, gpu_out, seconds):
         rt = e.reltol if tol is None else tol
         return oracle.solve(sysid, alg, p, u, ts, at, rt, e.theta, h0=e.h0, nthreads=nth)[0]
 
-    # calibrate on 1024, then size the sample to about `seconds` of wall time
-    idx = W.sample_indices(e.n, 1024)
-    t0 = time.perf_counter()
-    run(idx)
-    rate = len(idx) / max(time.perf_counter() - t0, 1e-6)
+    # pilot runs of growing size until one takes >= 0.5 s, then size the
+    # sample for about `seconds` of wall time
+    k = 4096
+    while True:
+        idx = W.sample_indices(e.n, min(k, e.n))
+        t0 = time.perf_counter()
+        run(idx)
+        dt = time.perf_counter() - t0
+        if dt >= 0.5 or k >= e.n:
+            break
+        k *= 4
+    rate = len(idx) / max(dt, 1e-6)
     k = int(min(e.n, max(1024, rate * seconds)))
     idx = W.sample_indices(e.n, k)
     t0 = time.perf_counter()
@@ -174,7 +231,6 @@ def cpu_baseline(e, gpu_out, seconds):
     res = {"value": len(idx) / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
            "sample": f"{len(idx)} of {e.n} trajectories (every {e.n // len(idx)}-th), "
                      f"FP64 C oracle, OpenMP over trajectories, {dt:.1f} s"}
-    # accuracy of the GPU result on the fixed 4096 subsample
     idx = W.sample_indices(e.n, 4096)
     g = gpu_out[:, :, idx].astype(np.float64)
     if e.alg == "em":
@@ -186,6 +242,85 @@ def cpu_baseline(e, gpu_out, seconds):
         err = float((np.abs(g - truth).max(axis=1) / np.abs(truth).max(axis=1)).max())
         kind = "max normwise relative error vs FP64 oracle at tol 1e-12"
     return res, {"max_rel_err": err, "subsample": len(idx), "kind": kind}
+
+
+def form_variants(e, precision, steps, base_out, plain_ms):
+    """Every work-assignment form on the same inputs: time and bitwise check."""
+    out = {}
+    for name, opts in FORMS.items():
+        r = Runner(e, precision, **opts)
+        _, ms, _ = r.time(max(3, steps // 2), 1)
+        same = bool((r.host_out().view("u1") == base_out.view("u1")).all())
+        out[name] = {"kernel_ms": ms, "traj_per_s": e.n / (ms * 1e-3),
+                     "speedup_vs_plain": plain_ms / ms if plain_ms else None,
+                     "bitwise_equal_to_headline": same}
+        del r
+    return out
+
+
+def surrogate_variant(epochs, plain_ms_2p24):
+    """Learned surrogate (4 -> 256 -> 256 -> 256 -> 48, bf16 MFMA): trained on
+    2^20 solver trajectories, then the audited solve of 2^24 fresh queries
+    (1% audit by the FP32 solver, fallback where audited error > 1e-3) timed
+    against the plain solver on the same queries."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2304_06835_amd as ens
+    from paper_2304_06835_amd import workloads as W
+    s = ens.Solver(0, precision=32)
+    tr = W.lorenz_fp32(N=1 << 20, seed=W.SEEDS["surr_train"])
+    P, U, T = dev(tr.params), dev(tr.u0), dev(tr.tspan)
+    y = s.solve("lorenz", P, U, T, "tsit5", tr.abstol, tr.reltol, tr.theta)
+    m = ens.Surrogate(s, seed=1)
+    m.fit_norm(P, U, y.view(48, -1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = m.train(P, U, y.view(48, -1), epochs=epochs, batch=4096, lr_max=1e-3, lr_min=1e-5,
+                     seed=11)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del P, U, T, y
+    q = W.lorenz_fp32(seed=W.SEEDS["surr_query"])
+    Pq, Uq, Tq = dev(q.params), dev(q.u0), dev(q.tspan)
+    out = torch.empty((16, 3, q.n), dtype=torch.float32, device="cuda")
+    used = torch.empty(q.n, dtype=torch.uint8, device="cuda")
+    rep = torch.zeros(4, dtype=torch.float32, device="cuda")
+    _, pred_ms, _ = event_time(lambda: m.predict(Pq, Uq, out=out), 5, 2)
+    _, solve_ms, _ = event_time(
+        lambda: m.solve(Pq, Uq, Tq, q.abstol, q.reltol, q.theta, audit_frac=0.01,
+                        fallback_tol=1e-3, audit_seed=W.SEEDS["surr_audit"], out=out, used=used,
+                        report=rep), 3, 1)
+    rep_h = rep.cpu().numpy()
+    used_h = used.cpu().numpy()
+    idx = W.sample_indices(q.n, 4096)
+    g = out.cpu().numpy()[:, :, idx].astype(np.float64)
+    truth = oracle.solve(oracle.LORENZ, oracle.TSIT5, np.ascontiguousarray(q.params[:, idx]),
+                         np.ascontiguousarray(q.u0[:, idx]), np.ascontiguousarray(q.tspan[:, idx]),
+                         1e-12, 1e-12, q.theta)[0]
+    err = np.abs(g - truth).max(axis=1) / np.abs(truth).max(axis=1)
+    nerr = err.max(axis=0)
+    return {
+        "training": {"samples": 1 << 20, "epochs": epochs, "batch": 4096, "seconds": train_s,
+                     "final_loss": float(losses[-1].item())},
+        "predict_ms": pred_ms,
+        "predict_mfma": {"achieved": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12,
+                         "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
+                         "frac": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12
+                         / PEAK_BF16_MFMA},
+        "audited_solve_ms": solve_ms, "queries": q.n,
+        "traj_per_s": q.n / (solve_ms * 1e-3),
+        "plain_solver_ms": plain_ms_2p24,
+        "speedup_vs_plain": plain_ms_2p24 / solve_ms,
+        "predict_only_speedup_vs_plain": plain_ms_2p24 / pred_ms,
+        "audited": int(rep_h[0]), "fallback": int(rep_h[1]), "flagged_bins": int(rep_h[2]),
+        "max_audit_err": float(rep_h[3]),
+        "solver_fraction": float((used_h != 0).mean()),
+        "max_rel_err_vs_oracle": float(nerr.max()),
+        "median_rel_err_vs_oracle": float(np.median(nerr)),
+        "surrogate_answered_frac_of_subsample": float((used_h[idx] == 0).mean()),
+    }
 
 
 def main():
@@ -200,14 +335,11 @@ def main():
 
     e = make_workload(args.workload, args.n)
     precision = 64 if args.workload == "lorenz_fp64" else 32
-    opts = {}
-    if args.block:
-        opts["block"] = args.block
-    if args.form == "persistent":
-        opts["form"] = 1
-    r = Runner(e, precision, **opts)
+    form = args.form or DEFAULT_FORM[args.workload]
     tuned = None
-    if args.form == "auto":
+    if e.alg == "em":
+        form = "plain"
+    if form == "auto":
         from paper_2304_06835_amd import workloads as W
         k = min(e.n, 1 << 18)
         idx = W.sample_indices(e.n, k)
@@ -215,59 +347,68 @@ def main():
         pe.params, pe.u0, pe.tspan = (e.params[:, idx].copy(), e.u0[:, idx].copy(),
                                       e.tspan[:, idx].copy())
         probe = Runner(pe, precision)
-        ms, cfg = probe.s.autotune(pe.system, probe.params, probe.u0, probe.tspan, pe.alg,
-                                   pe.abstol, pe.reltol, pe.theta)
-        tuned = cfg
-        r.s.set(**{k2: v for k2, v in cfg.items()})
-    print(f"[bench] {e.name} N={e.n} precision={precision} form={args.form}", file=sys.stderr,
+        _, tuned = probe.s.autotune(pe.system, probe.params, probe.u0, probe.tspan, pe.alg,
+                                    pe.abstol, pe.reltol, pe.theta)
+        opts = dict(tuned)
+    else:
+        opts = dict(FORMS[form])
+    r = Runner(e, precision, **opts)
+    print(f"[bench] {e.name} N={e.n} precision={precision} form={form}", file=sys.stderr,
           flush=True)
 
     attempts, stats = r.attempts()
     wall, ker_ms, ker_min = r.time(args.steps, args.warmup)
-    out_host = r.out.cpu().numpy()
+    out_host = r.host_out()
     value = e.n * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
-    flops = FLOPS[(e.alg, e.system)] * attempts
-    peak = PEAK_FP64 if precision == 64 else PEAK_FP32_NONPACKED
+    fpa = FLOPS[(e.alg, e.system)]
+    flops = fpa * attempts
+    peak = PEAK[precision]
     achieved = flops / (ker_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None,
+            "frac": achieved / peak,
+            "traffic": recorded_traffic(e.name, form, 1),
+            "kernel": {"tsit5": "tsit5", "rodas4": "rodas4", "em": "em_gbm4"}[e.alg]
+                      + {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
+                         "auto": ""}[form] + f"<{'double' if precision == 64 else 'float'}>",
             "kernel_ms_avg": ker_ms, "kernel_ms_min": ker_min,
-            "flops_per_launch": flops, "attempted_steps": attempts,
-            "flops_per_attempt": FLOPS[(e.alg, e.system)]}
-    if precision == 32:
-        roof["frac_of_published_fp32_peak_157.3"] = achieved / PEAK_FP32_PUBLISHED
+            "flops_per_launch": flops, "attempted_steps": attempts, "flops_per_attempt": fpa}
     st = stats.cpu().numpy()
     steps_per = st.sum(axis=0)
     config = {"workload": describe(e), "name": e.name, "n_traj": e.n, "alg": e.alg,
               "abstol": e.abstol, "reltol": e.reltol, "n_save": len(e.theta),
-              "form": args.form, "block": int(r.s.get("block")) or 256,
+              "form": form, "launch": {k2: int(r.s.get(k2)) for k2 in ("form", "block", "tpl")},
               "tuned": tuned,
               "steps_per_traj_mean": float(steps_per.mean()),
               "steps_per_traj_max": int(steps_per.max()),
               "rejected_frac": float(st[1].sum() / max(1, st.sum()))}
+    del r
 
     variants = {}
-    if not args.no_variants and e.name == "lorenz_fp32":
-        rp = Runner(e, 32, form=1)
-        w2, k2, _ = rp.time(max(3, args.steps // 2), 1)
-        p_out = rp.out.cpu().numpy()
-        variants["fp32_persistent"] = {
-            "traj_per_s": e.n * max(3, args.steps // 2) / w2, "kernel_ms": k2,
-            "speedup_vs_plain": ker_ms / k2,
-            "bitwise_equal_to_plain": bool((p_out.view("u1") == out_host.view("u1")).all())}
-        del rp
-        r64 = Runner(make_workload("lorenz_fp32", args.n), 64)
-        r64.e = e  # same draws, promoted to FP64
-        import numpy as np
-        import torch as _t
-        r64.params = _t.from_numpy(e.params.astype(np.float64)).cuda()
-        r64.u0 = _t.from_numpy(e.u0.astype(np.float64)).cuda()
-        r64.out = _t.empty((len(e.theta), 3, e.n), dtype=_t.float64, device="cuda")
-        w3, k3, _ = r64.time(max(3, args.steps // 2), 1)
-        variants["fp64_plain"] = {"traj_per_s": e.n * max(3, args.steps // 2) / w3,
-                                  "kernel_ms": k3, "fp32_speedup": k3 / ker_ms}
-        del r64
+    if not args.no_variants and e.alg != "em":
+        fv = form_variants(e, precision, args.steps, out_host, None)
+        plain_ms = fv["plain"]["kernel_ms"]
+        for v in fv.values():
+            v["speedup_vs_plain"] = plain_ms / v["kernel_ms"]
+        variants["forms"] = fv
+        if e.name == "lorenz_fp32":
+            import numpy as np
+            r64 = Runner(e, 64)
+            r64.params = dev(e.params.astype(np.float64))
+            r64.u0 = dev(e.u0.astype(np.float64))
+            r64.out = torch.empty((len(e.theta), 3, e.n), dtype=torch.float64, device="cuda")
+            _, k3, _ = r64.time(max(3, args.steps // 2), 1)
+            variants["fp64_plain"] = {"kernel_ms": k3, "traj_per_s": e.n / (k3 * 1e-3),
+                                      "fp32_headline_speedup": k3 / ker_ms}
+            del r64
+            rob = make_workload("robertson", 0)
+            rv = form_variants(rob, 32, args.steps, _plain_out(rob), None)
+            rp = rv["plain"]["kernel_ms"]
+            for v in rv.values():
+                v["speedup_vs_plain"] = rp / v["kernel_ms"]
+            variants["robertson_2p20_forms"] = rv
+            if not args.no_surrogate:
+                variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms)
 
     res = {"metric": METRIC, "value": value, "unit": "trajectories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -281,6 +422,15 @@ def main():
         res["cpu_baseline"] = cb
         res["accuracy"] = acc
     print(json.dumps(res), flush=True)
+
+
+def _plain_out(e):
+    """Host copy of the plain form's answer (the reference of the bitwise checks)."""
+    r = Runner(e, 32, **FORMS["plain"])
+    r.solve()
+    out = r.host_out()
+    del r
+    return out
 
 
 if __name__ == "__main__":

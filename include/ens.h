@@ -77,9 +77,13 @@ typedef struct ens_ctx ens_ctx;
                                64: FP64 throughout.  Also the dtype of params,
                                u0 and out.                                      */
 #define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;
-                               1: persistent kernel fed by an atomic work queue */
-#define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256;
-                               0 (default): tuned value or 256                  */
+                               1: persistent kernel fed by an atomic work queue;
+                               2: one lane per trajectory, the trajectories of
+                               each block sorted by expected work (span / first
+                               step) so that a wave's lanes finish together    */
+#define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256 (forms 0, 1);
+                               256, 512 or 1024 (form 2, the sorting group);
+                               0 (default): 256, or 1024 for form 2            */
 #define ENS_OPT_DT 4        /* fixed step of ENS_ALG_EM (> 0)                    */
 #define ENS_OPT_SEED 5      /* 64-bit Philox key of ENS_ALG_EM (integer value,
                                exact below 2^53)                                */
@@ -93,12 +97,16 @@ typedef struct ens_ctx ens_ctx;
                                a refill from the queue, 1..64 (default 16)      */
 #define ENS_OPT_GRID 10     /* persistent form: blocks launched; 0 (default):
                                enough to fill every CU                          */
-#define ENS_OPT_TPL 11      /* one-lane-per-trajectory form: trajectories each
-                               lane integrates one after another, 1..8 (default
-                               1); lane g of G takes g, g + G, g + 2G, ...      */
-#define ENS_OPT_MLP_TILE 12 /* surrogate inference: 16-query subtiles per wave of
-                               the fused kernel (2, 3 or 4; default 4), or 0 for
-                               the layer-by-layer tiled-product path          */
+#define ENS_OPT_TPL 11      /* forms 0 and 2: trajectories each lane integrates
+                               one after another, 1..8 (default 1).  Form 0:
+                               lane g of G takes g, g + G, g + 2G, ...; form 2:
+                               1, 2 or 4 rounds (larger values use 4), each
+                               block sorting block x rounds trajectories      */
+#define ENS_OPT_MLP_TILE 12 /* surrogate inference: fused kernel with 2, 3 or 4
+                               16-query subtiles per wave and one wave per SIMD
+                               (2, 3, 4), or 2 or 3 subtiles and two waves per
+                               SIMD (12, 13; default 13); 0: the layer-by-layer
+                               tiled-product path                             */
 
 /* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
 #define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,
@@ -176,7 +184,8 @@ int ens_philox_fill(ens_ctx *ctx, uint64_t seed, int64_t n_traj, uint32_t step,
 /*
  * Autotuner: time every launch configuration -- block in {64, 128, 256} x
  * (plain form with trajectories per lane in {1, 2, 4}, or persistent form
- * with refill threshold in {4, 16, 32}) -- on the given probe ensemble (same
+ * with refill threshold in {4, 16, 32}), and the sorted form with block in
+ * {256, 512, 1024} -- on the given probe ensemble (same
  * arguments as ens_solve; `out` is overwritten), and set ENS_OPT_FORM,
  * ENS_OPT_BLOCK, ENS_OPT_TPL and ENS_OPT_REFILL to the fastest.  Results are
  * bitwise identical across configurations, so tuning never changes answers.

@@ -138,6 +138,17 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
                       const ens::LaunchCfg& cfg0, hipStream_t s) {
   ens::LaunchCfg cfg = cfg0;
   hipError_t e;
+  if (alg != ENS_ALG_EM) {
+    // blocks of 512 or 1024 threads exist only for the sorted form, which
+    // needs a power of two of at least 256
+    if (cfg.form == 2 && cfg.block != 256 && cfg.block != 512 && cfg.block != 1024)
+      return fail(c, ENS_EINVAL, "the sorted form (2) needs block 256, 512 or 1024, not %d",
+                  cfg.block);
+    if (cfg.form != 2 && cfg.block > ens::kMaxBlock)
+      return fail(c, ENS_EINVAL, "block %d needs the sorted form (2)", cfg.block);
+  } else if (cfg.block > ens::kMaxBlock) {
+    cfg.block = ens::kMaxBlock;
+  }
   if (alg == ENS_ALG_EM) {
     cfg.form = 0;
     e = ens::launch_em(sys, c->precision, cfg, a, s);
@@ -164,7 +175,7 @@ namespace {
 ens::LaunchCfg current_cfg(const ens_ctx* c) {
   ens::LaunchCfg cfg;
   cfg.form = c->form;
-  cfg.block = c->block > 0 ? c->block : 256;
+  cfg.block = c->block > 0 ? c->block : (c->form == 2 ? 1024 : 256);
   cfg.grid = c->grid;
   return cfg;
 }
@@ -237,12 +248,12 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       c->precision = (int)v;
       return ENS_OK;
     case ENS_OPT_FORM:
-      if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "form must be 0 or 1");
+      if (v != 0 && v != 1 && v != 2) return fail(c, ENS_EINVAL, "form must be 0, 1 or 2");
       c->form = (int)v;
       return ENS_OK;
     case ENS_OPT_BLOCK:
-      if (v != 0 && v != 64 && v != 128 && v != 256)
-        return fail(c, ENS_EINVAL, "block must be 0, 64, 128 or 256");
+      if (v != 0 && v != 64 && v != 128 && v != 256 && v != 512 && v != 1024)
+        return fail(c, ENS_EINVAL, "block must be 0, 64, 128, 256, 512 or 1024");
       c->block = (int)v;
       return ENS_OK;
     case ENS_OPT_DT:
@@ -279,8 +290,8 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       c->tpl = (int)v;
       return ENS_OK;
     case ENS_OPT_MLP_TILE:
-      if (v != 0 && v != 2 && v != 3 && v != 4)
-        return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3 or 4");
+      if (v != 0 && v != 2 && v != 3 && v != 4 && v != 12 && v != 13)
+        return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3, 4, 12 or 13");
       c->mlp_tile = (int)v;
       return ENS_OK;
   }
@@ -367,6 +378,8 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
     if (alg != ENS_ALG_EM)
       for (int rf : {4, 16, 32}) cands[nc++] = {1, b, 1, rf};
   }
+  if (alg != ENS_ALG_EM)
+    for (int b : {256, 512, 1024}) cands[nc++] = {2, b, 1, 64};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, ENS_EDEVICE, "hipEventCreate failed");

@@ -70,8 +70,19 @@ __device__ inline int64_t out_col(const LaunchArgs& a, int64_t k, int64_t i) {
   return a.scatter ? i : k;
 }
 
-__device__ inline double save_time(const LaunchArgs& a, double t0, double tf, int j) {
-  return t0 + a.theta[j] * (tf - t0);
+// The save fractions, copied into LDS once per block (stage_theta).  Each
+// lane indexes them with its own save counter; read from the kernel
+// arguments that would be a global load per save, and its wait would also
+// wait for every older store and load of the wave.
+static __shared__ double lds_theta[kMaxSave];
+
+__device__ inline void stage_theta(const LaunchArgs& a) {
+  for (int j = (int)threadIdx.x; j < a.n_save; j += (int)blockDim.x) lds_theta[j] = a.theta[j];
+  __syncthreads();
+}
+
+__device__ inline double save_time(const LaunchArgs&, double t0, double tf, int j) {
+  return t0 + lds_theta[j] * (tf - t0);
 }
 
 __device__ inline double tspan_at(const LaunchArgs& a, int row, int64_t i) {
@@ -84,19 +95,121 @@ __device__ inline R load_col(const LaunchArgs& a, const void* base, int row, int
 }
 
 
+// Inputs of one trajectory, loaded ahead of its integration so that the
+// persistent form can fetch a lane's next trajectory while the lane is still
+// busy with the current one.
+template <class R, int M, int N>
+struct LaneInput {
+  R p[M], u[N];
+  double t0, tf;
+  int64_t i;  // input column
+  __device__ inline void load(const LaunchArgs& a, int64_t k) {
+    i = in_col(a, k);
+#pragma unroll
+    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
+#pragma unroll
+    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a, a.u0, c, i);
+    t0 = tspan_at(a, 0, i);
+    tf = tspan_at(a, 1, i);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Form 2 (cost-sorted lanes): each block of B threads takes R*B consecutive
+// trajectories (R = tpl rounds), initialises each one to learn its expected
+// amount of work -- the span divided by the first step, (tf - t0) / h --
+// sorts the R*B items by that key (bitonic network in LDS), and integrates
+// them in sorted order, 64 consecutive sorted items per wave and round, so
+// that the lanes of a wave hold trajectories of similar cost and finish at
+// similar times.  Rounds alternate direction (round 0: wave w takes sorted
+// group w, round 1: group 2W-1-w, ...), so every wave of the block gets a
+// similar total and the block does not idle behind one expensive wave.  The
+// first initialisation is thrown away; the second, on the lane the item was
+// sorted to, is the same computation, so results are bit-identical to the
+// other forms.
+
+// Ascending bitonic sort of v[0..NE) in LDS by the B threads of the block.
+template <int NE, int B>
+__device__ inline void block_sort(uint64_t* v) {
+  static_assert((NE & (NE - 1)) == 0 && NE >= 2, "sort size must be a power of two");
+  const int tid = (int)threadIdx.x;
+  for (int k = 2; k <= NE; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = tid; p < NE / 2; p += B) {
+        const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));  // lower index of the pair
+        const int m = i | j;
+        const uint64_t x = v[i], y = v[m];
+        const bool up = (i & k) == 0;
+        if ((x > y) == up) {
+          v[i] = y;
+          v[m] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Expected work of an initialised lane: attempts scale with span / step.
+template <class Lane>
+__device__ inline float work_key(const Lane& L) {
+  if (L.done) return 0.0f;
+  const float r = (float)((L.tf - L.t0) / (double)L.h);
+  return (r >= 0.0f && r <= 3.0e38f) ? r : 3.0e38f;  // NaN or inf: last
+}
+
+template <class Lane, int B, int R>
+__device__ inline void run_sorted(const LaunchArgs& a) {
+  constexpr int NE = B * R, W = B / kWave;
+  __shared__ uint64_t keys[NE];
+  stage_theta(a);
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int64_t base = (int64_t)blockIdx.x * NE;
+  const int64_t n = work_items(a);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = r * B + tid;
+    float key = __builtin_inff();  // items past the end sort last
+    if (base + e < n) {
+      typename Lane::Input in;
+      in.load(a, base + e);
+      Lane L;
+      L.init(a, base + e, in);
+      key = work_key(L);
+    }
+    keys[e] = ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)e;
+  }
+  __syncthreads();
+  block_sort<NE, B>(keys);
+  for (int r = 0; r < R; ++r) {
+    const int grp = r * W + ((r & 1) ? (W - 1 - wave) : wave);
+    const int64_t k = base + (int64_t)(uint32_t)keys[grp * kWave + lane];
+    if (k >= n) continue;
+    typename Lane::Input in;
+    in.load(a, k);
+    Lane L;
+    L.init(a, k, in);
+    while (!L.done) L.attempt(a, k);
+    L.finish(a, k);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Form 0: lane g of G integrates trajectories g, g + G, ... (tpl of them),
 // one after another.  A wave stays resident until its slowest lane is done;
 // idle lanes are masked off by the SIMT loop.
 template <class Lane>
 __device__ inline void run_plain(const LaunchArgs& a) {
+  stage_theta(a);
   const int64_t G = (int64_t)gridDim.x * blockDim.x;
   const int64_t n = work_items(a);
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int r = 0; r < a.tpl; ++r, k += G) {
     if (k >= n) return;
+    typename Lane::Input in;
+    in.load(a, k);
     Lane L;
-    L.init(a, k);
+    L.init(a, k, in);
     while (!L.done) L.attempt(a, k);
     L.finish(a, k);
   }
@@ -115,6 +228,7 @@ constexpr int64_t kChunk = 128;
 
 template <class Lane>
 __device__ inline void run_persistent(const LaunchArgs& a) {
+  stage_theta(a);
   const int lane = (int)(threadIdx.x & (kWave - 1));
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const int64_t n = work_items(a);
@@ -123,7 +237,11 @@ __device__ inline void run_persistent(const LaunchArgs& a) {
   bool queue_empty = a.first_queued >= n;
   int64_t pk_next = 0, pk_end = 0;  // the wave's pocket [pk_next, pk_end)
   Lane L;
-  if (active) L.init(a, k);
+  if (active) {
+    typename Lane::Input in;
+    in.load(a, k);
+    L.init(a, k, in);
+  }
   while (true) {
     if (active) {
       if (!L.done) L.attempt(a, k);
@@ -159,7 +277,9 @@ __device__ inline void run_persistent(const LaunchArgs& a) {
             id = c0 + (r - left);
           if (id >= 0) {
             k = id;
-            L.init(a, k);
+            typename Lane::Input in;
+            in.load(a, k);
+            L.init(a, k, in);
             active = true;
           }
         }

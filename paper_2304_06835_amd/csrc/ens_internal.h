@@ -78,7 +78,7 @@ struct ens_ctx {
   int tpl = 1;
   int refill = 16;
   int grid = 0;
-  int mlp_tile = 4;
+  int mlp_tile = 13;
   int tspan_bcast = 0;
   double dt = 0.0;
   double h0 = 0.0;

@@ -48,7 +48,11 @@ struct MlpActs {
   uint16_t* act[kMlpMaxLayers];
   float* g[2];          // gradient ping-pong, FP32
   uint16_t* gb[2];      // and bf16
+  float* split;         // kSplits x (largest weight matrix) split-K partials
 };
+
+// Split-K factor of the weight-gradient products (K = batch).
+constexpr int kSplits = 16;
 
 struct RowSet {
   const float* ptr[64];

@@ -80,10 +80,13 @@ __device__ inline void stage(uint16_t (*dst)[LDW], const uint16_t* __restrict__ 
 }
 
 // C[M x N] = A[M x K] B[K x N]; A stored per LA, B per LB (with "rows" = N).
+// blockIdx.z selects the K range [z kc, min(K, (z+1) kc)) of a split-K
+// product; the epilogue sees blockIdx.z and writes that split's partial.
 template <int LA, int LB, class Epi>
 __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A, int64_t lda,
                                                  const uint16_t* __restrict__ B, int64_t ldb,
-                                                 int64_t M, int64_t N, int64_t K, Epi epi) {
+                                                 int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                 Epi epi) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -94,9 +97,11 @@ __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A,
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    stage<LA>(As, A, lda, M, K, m0, k0, tid);
-    stage<LB>(Bs, B, ldb, N, K, n0, k0, tid);
+  const int64_t kbeg = (int64_t)blockIdx.z * kc;
+  const int64_t kend = kbeg + kc < K ? kbeg + kc : K;
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    stage<LA>(As, A, lda, M, kend, m0, k0, tid);
+    stage<LB>(Bs, B, ldb, N, kend, n0, k0, tid);
     __syncthreads();
     bf16x8_t af[2], bfr[2];
 #pragma unroll
@@ -163,19 +168,24 @@ struct EpiBack {  // G = acc * silu'(Z), kept in FP32 (bias gradient) and bf16
     gb[m * ld + n] = f2bf(gg);
   }
 };
-struct EpiStore {
+struct EpiStore {  // partial product of split blockIdx.z at c + z * zstride
   float* c;
-  int64_t ld;
-  __device__ void operator()(int64_t m, int64_t n, float v) const { c[m * ld + n] = v; }
+  int64_t ld, zstride;
+  __device__ void operator()(int64_t m, int64_t n, float v) const {
+    c[(int64_t)blockIdx.z * zstride + m * ld + n] = v;
+  }
 };
 
+// `splits` > 1: K is cut into that many ranges of a multiple of BK each.
 template <int LA, int LB, class Epi>
 hipError_t gemm(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M,
-                int64_t N, int64_t K, Epi epi, hipStream_t s) {
+                int64_t N, int64_t K, Epi epi, hipStream_t s, int splits = 1) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
+  int64_t kc = (K + splits - 1) / splits;
+  kc = (kc + BK - 1) / BK * BK;
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
   hipLaunchKernelGGL((gemm_bf16<LA, LB, Epi>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K,
-                     epi);
+                     kc, epi);
   return hipGetLastError();
 }
 
@@ -274,13 +284,32 @@ __global__ void finish_sum(const double* partial, int64_t count, double factor, 
   if (threadIdx.x == 0) out[0] = (float)(factor * red[0]);
 }
 
-// db[c] = sum over rows of G[r][c] (one thread per column, fixed order).
-__global__ void col_sums(const float* G, int64_t rows, int64_t cols, float* db) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= cols) return;
+// part[y][c] = sum of G[r][c] over the y-th range of rows: 64 columns per
+// block, four row lanes per column (strided), combined in LDS in a fixed
+// order.
+__global__ void col_sums(const float* G, int64_t rows, int64_t cols, int64_t rows_per,
+                         float* part) {
+  __shared__ float red[4][64];
+  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
+  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
   float s = 0.0f;
-  for (int64_t r = 0; r < rows; ++r) s += G[r * cols + c];
-  db[c] = s;
+  if (c < cols)
+    for (int64_t r = r0 + rl; r < r1; r += 4) s += G[r * cols + c];
+  red[rl][cl] = s;
+  __syncthreads();
+  if (rl == 0 && c < cols)
+    part[(int64_t)blockIdx.y * cols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
+}
+
+// out[i] = sum over z of part[z][i] in increasing z (deterministic).
+__global__ void sum_splits(const float* part, int splits, int64_t count, float* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float s = part[i];
+  for (int z = 1; z < splits; ++z) s += part[(int64_t)z * count + i];
+  out[i] = s;
 }
 
 // Mean, 1/std and std (population, std floored at 1e-6) of `nrows` rows of
@@ -416,12 +445,22 @@ hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* 
   for (int l = nl - 1; l >= 0; --l) {
     const int nin = L.dims[l], no = L.dims[l + 1];
     const uint16_t* prev = l > 0 ? acts.act[l - 1] : a0;
-    // dW_l [no][nin] = G^T [no x B] . A_{l-1} [B x nin]
+    // dW_l [no][nin] = G^T [no x B] . A_{l-1} [B x nin], K = B cut into
+    // kSplits ranges (partials summed in a fixed order)
+    const int64_t cnt_w = (int64_t)no * nin;
     e = gemm<kKRow, kKRow>(acts.gb[cur], no, prev, nin, no, nin, B,
-                           EpiStore{grad + L.w_off[l], nin}, s);
+                           EpiStore{acts.split, nin, cnt_w}, s, kSplits);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(col_sums, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, s, acts.g[cur],
-                       B, (int64_t)no, grad + L.b_off[l]);
+    hipLaunchKernelGGL(sum_splits, dim3((unsigned)((cnt_w + 255) / 256)), dim3(256), 0, s,
+                       acts.split, kSplits, cnt_w, grad + L.w_off[l]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // db_l = column sums of G
+    const int64_t rows_per = (B + kSplits - 1) / kSplits;
+    hipLaunchKernelGGL(col_sums, dim3((unsigned)((no + 63) / 64), (unsigned)kSplits), dim3(256), 0,
+                       s, acts.g[cur], B, (int64_t)no, rows_per, acts.split);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_splits, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, s, acts.split,
+                       kSplits, (int64_t)no, grad + L.b_off[l]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l > 0) {
       // G_{l-1} [B x nin] = (G [B x no] . W_l [no x nin]) * silu'(Z_{l-1})

@@ -40,11 +40,14 @@ constexpr int64_t kP4 = kP3 + 128 * kFrag;  // layer 4: 3 row blocks x 8 k-block
 constexpr int64_t kPTotal = kP4 + 24 * kFrag;
 constexpr int kChunkBytes = 32 * kFrag * 2;  // 4 row blocks x 8 k-blocks
 
-// LDS map (bytes)
-constexpr int kLdsW1 = 0;
+// LDS map (bytes).  The ring comes first so that every fragment of either
+// slot is a 16-bit immediate offset (< 64 KiB) from one per-lane address;
+// the per-block copies follow, reached from a second one.
+constexpr int kLdsRing = 0;
+constexpr int kLdsW1 = kLdsRing + 2 * kChunkBytes;
 constexpr int kLdsW4 = kLdsW1 + 16 * kFrag * 2;
-constexpr int kLdsRing = kLdsW4 + 24 * kFrag * 2;
-constexpr int kLdsBias = kLdsRing + 2 * kChunkBytes;
+constexpr int kLdsBias = kLdsW4 + 24 * kFrag * 2;
+static_assert(2 * kChunkBytes <= 65536, "ring fragments must be immediate offsets");
 // floats at kLdsBias: b1 [256], b2 [256], b3 [256], b4 [48], out mean [48],
 // out std [48], in mean [4], in 1/std [4]
 constexpr int kBB1 = 0, kBB2 = 256, kBB3 = 512, kBB4 = 768, kBMean = 816, kBStd = 864,
@@ -122,18 +125,33 @@ __device__ inline f32x4_t bias4(const uint8_t* lds, int idx) {
   return *reinterpret_cast<const f32x4_t*>(lds + kLdsBias + idx * 4);
 }
 
-// This wave's quarter of one 32 KiB chunk: 8 fragments, global -> LDS.
+// This wave's share of one 32 KiB chunk (32 fragments over NW waves),
+// global -> LDS.
+// The per-lane byte offset goes through an empty asm statement so that the
+// compiler rebuilds each address from the (scalar) chunk base inside the
+// loop instead of hoisting 64-bit addresses of every chunk out of the tile
+// loop, where they would occupy a hundred registers.
+template <int NW>
 __device__ inline void load_chunk(const uint16_t* src, uint8_t* slot, int wave, int lane) {
+  uint32_t voff = (uint32_t)lane * 16u;
+  asm volatile("" : "+v"(voff));
+  const int w = __builtin_amdgcn_readfirstlane(wave);
+  const char* base = reinterpret_cast<const char*>(src);
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int fi = wave * 8 + j;
+  for (int j = 0; j < 32 / NW; ++j) {
+    const int fi = w * (32 / NW) + j;
     __builtin_amdgcn_global_load_lds(
-        reinterpret_cast<const void*>(src + (int64_t)fi * kFrag + lane * 8),
+        reinterpret_cast<const void*>(base + (size_t)fi * (kFrag * 2) + voff),
         (__attribute__((address_space(3))) void*)(slot + fi * kFrag * 2), 16, 0, 0);
   }
 }
 
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+#ifndef ENS_MLP_FENCE
+#define ENS_MLP_FENCE 1
+#endif
+constexpr bool kFence = ENS_MLP_FENCE;
 
 // One 64-row chunk of a 256 x 256 layer: pairs of 16-row blocks (2c, 2c+1)
 // and (2c+2, 2c+3) of the output for every subtile.
@@ -151,6 +169,11 @@ __device__ inline void chunk_layer(const uint8_t* lds, int slot_off, int c, int 
       acc[0][s] = b0;
       acc[1][s] = b1;
     }
+    // Scheduling fences keep one pair's products and its activation epilogue
+    // in program order: left free, the scheduler overlaps neighbouring
+    // pairs and runs out of registers; the overlap of matrix-core and vector
+    // work comes instead from the second wave on each SIMD.
+    if (kFence) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kb = 0; kb < 8; ++kb) {
       const bf16x8_t a0 = frag(lds, slot_off + ((2 * pp) * 8 + kb) * kFrag * 2, lane);
@@ -161,14 +184,16 @@ __device__ inline void chunk_layer(const uint8_t* lds, int slot_off, int c, int 
         acc[1][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x[s][kb], acc[1][s], 0, 0, 0);
       }
     }
+    if (kFence) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) y[s][rb >> 1] = silu_pack(acc[0][s], acc[1][s]);
   }
 }
 
-template <int NS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+template <int NS, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 mlp_fused_fwd(const FusedArgs a) {
+  constexpr int NT = 64 * NW;
   __shared__ __attribute__((aligned(16))) uint8_t lds[kLdsBytes];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, col = lane & 15;
@@ -178,12 +203,14 @@ mlp_fused_fwd(const FusedArgs a) {
     const uint4* s4 = reinterpret_cast<const uint4*>(a.packed + kP4);
     uint4* d1 = reinterpret_cast<uint4*>(lds + kLdsW1);
     uint4* d4 = reinterpret_cast<uint4*>(lds + kLdsW4);
-    for (int i = tid; i < 16 * kFrag / 8; i += 256) d1[i] = s1[i];
-    for (int i = tid; i < 24 * kFrag / 8; i += 256) d4[i] = s4[i];
+    for (int i = tid; i < 16 * kFrag / 8; i += NT) d1[i] = s1[i];
+    for (int i = tid; i < 24 * kFrag / 8; i += NT) d4[i] = s4[i];
     float* bs = reinterpret_cast<float*>(lds + kLdsBias);
-    bs[kBB1 + tid] = a.w[a.b_off[0] + tid];
-    bs[kBB2 + tid] = a.w[a.b_off[1] + tid];
-    bs[kBB3 + tid] = a.w[a.b_off[2] + tid];
+    for (int i = tid; i < kH; i += NT) {
+      bs[kBB1 + i] = a.w[a.b_off[0] + i];
+      bs[kBB2 + i] = a.w[a.b_off[1] + i];
+      bs[kBB3 + i] = a.w[a.b_off[2] + i];
+    }
     if (tid < kNO) {
       bs[kBB4 + tid] = a.w[a.b_off[3] + tid];
       bs[kBMean + tid] = a.norm[kOutMean + tid];
@@ -194,13 +221,12 @@ mlp_fused_fwd(const FusedArgs a) {
       bs[kBInIStd + tid] = a.norm[kInIStd + tid];
     }
   }
-  load_chunk(a.packed + kP2, lds + kLdsRing, wave, lane);  // layer 2, chunk 0 -> slot 0
+  load_chunk<NW>(a.packed + kP2, lds + kLdsRing, wave, lane);  // layer 2, chunk 0 -> slot 0
   __syncthreads();
 
   const float* bs = reinterpret_cast<const float*>(lds + kLdsBias);
-  const int64_t n = a.n, tq = 64 * NS;
+  const int64_t n = a.n, tq = 16 * NS * NW;
   const int64_t ntiles = (n + tq - 1) / tq;
-  int slot = 0;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t qw = tile * tq + (int64_t)wave * 16 * NS;  // this wave's first query
     bf16x8_t xa[NS][8], xb[NS][8];
@@ -242,23 +268,22 @@ mlp_fused_fwd(const FusedArgs a) {
     }
 
     // ---- layers 2 and 3: four chunks each through the LDS ring
+    // eight chunks per tile, so chunk c of a tile always sits in slot c & 1
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       wait_vm();
       __syncthreads();
-      load_chunk(a.packed + (c < 3 ? kP2 + (c + 1) * 32 * kFrag : kP3),
-                 lds + kLdsRing + (slot ^ 1) * kChunkBytes, wave, lane);
-      chunk_layer<NS>(lds, kLdsRing + slot * kChunkBytes, c, kBB2, g, lane, xa, xb);
-      slot ^= 1;
+      load_chunk<NW>(a.packed + (c < 3 ? kP2 + (c + 1) * 32 * kFrag : kP3),
+                     lds + kLdsRing + ((c + 1) & 1) * kChunkBytes, wave, lane);
+      chunk_layer<NS>(lds, kLdsRing + (c & 1) * kChunkBytes, c, kBB2, g, lane, xa, xb);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       wait_vm();
       __syncthreads();
-      load_chunk(a.packed + (c < 3 ? kP3 + (c + 1) * 32 * kFrag : kP2),
-                 lds + kLdsRing + (slot ^ 1) * kChunkBytes, wave, lane);
-      chunk_layer<NS>(lds, kLdsRing + slot * kChunkBytes, c, kBB3, g, lane, xb, xa);
-      slot ^= 1;
+      load_chunk<NW>(a.packed + (c < 3 ? kP3 + (c + 1) * 32 * kFrag : kP2),
+                     lds + kLdsRing + ((c + 1) & 1) * kChunkBytes, wave, lane);
+      chunk_layer<NS>(lds, kLdsRing + (c & 1) * kChunkBytes, c, kBB3, g, lane, xb, xa);
     }
 
     // ---- layer 4: 48 outputs, de-normalised into out[o][q]
@@ -316,13 +341,19 @@ hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const f
   a.n = n;
   a.stride = stride;
   for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
-  const int64_t tq = 64 * (int64_t)ns;
+  // ns = NS (one wave per SIMD, 4-wave blocks) or 10 + NS (two waves per
+  // SIMD, 8-wave blocks)
+  const int NS = ns % 10, NW = ns >= 10 ? 8 : 4;
+  const int64_t tq = 16 * (int64_t)NS * NW;
   const int64_t ntiles = (n + tq - 1) / tq;
   const unsigned grid = (unsigned)(ntiles < num_cu ? ntiles : num_cu);
+  const dim3 blk(64 * NW);
   switch (ns) {
-    case 2: hipLaunchKernelGGL(mlp_fused_fwd<2>, dim3(grid), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(mlp_fused_fwd<3>, dim3(grid), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(mlp_fused_fwd<4>, dim3(grid), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((mlp_fused_fwd<2, 4>), dim3(grid), blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((mlp_fused_fwd<3, 4>), dim3(grid), blk, 0, s, a); break;
+    case 12: hipLaunchKernelGGL((mlp_fused_fwd<2, 8>), dim3(grid), blk, 0, s, a); break;
+    case 13: hipLaunchKernelGGL((mlp_fused_fwd<3, 8>), dim3(grid), blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((mlp_fused_fwd<4, 4>), dim3(grid), blk, 0, s, a); break;
   }
   return hipGetLastError();
 }

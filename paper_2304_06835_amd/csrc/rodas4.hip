@@ -102,11 +102,14 @@ struct LU {
 template <class R, class S>
 struct Rodas4Lane {
   static constexpr int N = S::N, M = S::M;
+  using Input = LaneInput<R, M, N>;
   R p[M], u[N];
   CompTime t;
   double t0, tf;
   double ts;  // next save time
   R h;
+  R hmax;    // tf - t0: no step is longer
+  R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
   R lqold;
   R* sp;        // out[j][0][col]: where the next save goes
   int j, nacc, nrej, status;
@@ -128,7 +131,6 @@ struct Rodas4Lane {
   // Starting step when none is given: Hairer-Norsett-Wanner I, II.4 with
   // the order p = 4 (two f calls), capped by the interval length.
   __device__ inline R initial_step(const LaunchArgs& a) {
-    const double hmax = tf - t0;
     double sc[N], d0 = 0, d1 = 0, f0[N], y1[N], f1[N], uu[N];
     R fr[N];
     S::f(p, u, fr);
@@ -164,15 +166,14 @@ struct Rodas4Lane {
     return (R)fmin(fmin(100.0 * h0, h1), hmax);
   }
 
-  __device__ inline void init(const LaunchArgs& a, int64_t k) {
-    const int64_t i = in_col(a, k);
-    sp = static_cast<R*>(a.out) + out_col(a, k, i);
+  __device__ inline void init(const LaunchArgs& a, int64_t k, const Input& in) {
+    sp = static_cast<R*>(a.out) + out_col(a, k, in.i);
 #pragma unroll
-    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
+    for (int r = 0; r < M; ++r) p[r] = in.p[r];
 #pragma unroll
-    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a, a.u0, c, i);
-    t0 = tspan_at(a, 0, i);
-    tf = tspan_at(a, 1, i);
+    for (int c = 0; c < N; ++c) u[c] = in.u[c];
+    t0 = in.t0;
+    tf = in.tf;
     t.set(t0);
     j = 0;
     nacc = nrej = 0;
@@ -187,7 +188,9 @@ struct Rodas4Lane {
     save_reached(a);
     if (done) return;
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
-    h = (R)fmin((double)h, tf - t0);
+    hmax = (R)(tf - t0);
+    h = fmin(h, hmax);
+    hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
     lqold = (R)kLog2QFloor;
   }
 
@@ -198,9 +201,10 @@ struct Rodas4Lane {
       done = true;
       return;
     }
-    const double rem = t.to(ts);
-    const bool clamped = (double)h >= rem;
-    const R he = clamped ? (R)rem : h;
+    // distance to the next save time; the step is cut to land on it
+    const R rem = (R)t.to(ts);
+    const bool clamped = h >= rem;
+    const R he = clamped ? rem : h;
 
     // W = I/(gamma h) - J, factored in FP64
     LU<N> W;
@@ -256,7 +260,6 @@ struct Rodas4Lane {
       return;
     }
     const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));
-    const double hmax = tf - t0;
     if (q2 <= (R)1) {
       ++nacc;
       if (clamped)
@@ -269,16 +272,19 @@ struct Rodas4Lane {
       fac = fmin((R)kFacMax, fmax((R)kFacMin, fac));
       lqold = fmax(lq, (R)kLog2QFloor);
       R hn = he * fac;
-      if (clamped) hn = fmax(hn, h);
-      h = (R)fmin((double)hn, hmax);
-      save_reached(a);
-      if (done) return;
+      if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
+      h = fmin(hn, hmax);
+      hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
+      if (clamped) {  // only a cut step lands on a save time
+        save_reached(a);
+        if (done) return;
+      }
     } else {
       ++nrej;
       const R fac = fmax((R)kFacMin, (R)kEta * F::exp2((R)(-1.0 / kK) * lq));
       h = he * fac;
     }
-    if (!((double)h > 16.0 * DBL_EPSILON * fabs(t.hi))) {
+    if (!(h > hfloor)) {
       status = ENS_ST_DTMIN;
       done = true;
     }
@@ -306,15 +312,36 @@ __global__ void __launch_bounds__(kMaxBlock) rodas4_persistent(const LaunchArgs 
   run_persistent<Rodas4Lane<R, S>>(a);
 }
 
+template <class R, class S, int B, int RR>
+__global__ void __launch_bounds__(B) rodas4_sorted(const LaunchArgs a) {
+  run_sorted<Rodas4Lane<R, S>, B, RR>(a);
+}
+
+// Sorted form: block in {256, 512, 1024} x rounds (tpl) in {1, 2, 4}.
+template <class R, class S>
+void launch_sorted(const LaunchCfg& cfg, const LaunchArgs& a, hipStream_t s) {
+  const int rr = a.tpl >= 4 ? 4 : (a.tpl >= 2 ? 2 : 1);
+  const int64_t per = (int64_t)cfg.block * rr;
+  const dim3 grid((unsigned)((a.n + per - 1) / per)), blk((unsigned)cfg.block);
+#define ENS_SORTED(BB, RRR) \
+  if (cfg.block == BB && rr == RRR) { hipLaunchKernelGGL((rodas4_sorted<R, S, BB, RRR>), grid, blk, 0, s, a); return; }
+  ENS_SORTED(256, 1) ENS_SORTED(256, 2) ENS_SORTED(256, 4)
+  ENS_SORTED(512, 1) ENS_SORTED(512, 2) ENS_SORTED(512, 4)
+  ENS_SORTED(1024, 1) ENS_SORTED(1024, 2) ENS_SORTED(1024, 4)
+#undef ENS_SORTED
+}
+
 template <class R, class S>
 hipError_t launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   if (cfg.form == 0) {
     const int64_t per_block = (int64_t)cfg.block * a.tpl;
     const int64_t grid = (a.n + per_block - 1) / per_block;
     hipLaunchKernelGGL((rodas4_plain<R, S>), dim3((unsigned)grid), dim3(cfg.block), 0, s, a);
-  } else {
+  } else if (cfg.form == 1) {
     hipLaunchKernelGGL((rodas4_persistent<R, S>), dim3((unsigned)cfg.grid), dim3(cfg.block),
                        0, s, a);
+  } else {
+    launch_sorted<R, S>(cfg, a, s);
   }
   return hipGetLastError();
 }

@@ -162,6 +162,7 @@ struct ens_surrogate {
   float* g[2] = {};
   uint16_t* gb[2] = {};
   double* partial = nullptr;
+  float* split = nullptr;  // split-K partials of the weight gradients
   // inference workspace (chunk capacity)
   int64_t cap_chunk = 0;
   uint16_t* ia0 = nullptr;
@@ -181,7 +182,7 @@ namespace {
 void free_all(ens_surrogate* s) {
   void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
                 s->act[0], s->act[1], s->act[2], s->Y, s->T, s->g[0], s->g[1], s->gb[0],
-                s->gb[1], s->partial, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
+                s->gb[1], s->partial, s->split, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
                 s->scratch, s->used, s->counts, s->words};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -190,13 +191,14 @@ void free_all(ens_surrogate* s) {
 int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   if (B <= s->cap_batch) return ENS_OK;
   void* old[] = {s->a0, s->z[0], s->z[1], s->z[2], s->act[0], s->act[1], s->act[2], s->Y, s->T,
-                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial};
+                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial, s->split};
   for (void* p : old)
     if (p) (void)hipFree(p);
   const int H = kDims[1], O = kDims[4];
   bool ok = alloc(&s->a0, B * kDims[0]) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
             alloc(&s->T, B * O) == hipSuccess &&
-            alloc(&s->partial, (B * H + 255) / 256 + 1) == hipSuccess;
+            alloc(&s->partial, (B * H + 255) / 256 + 1) == hipSuccess &&
+            alloc(&s->split, (int64_t)ens::kSplits * H * H) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
     ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
   for (int l = 0; l < 2 && ok; ++l)
@@ -277,6 +279,7 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     acts.g[l] = s->g[l];
     acts.gb[l] = s->gb[l];
   }
+  acts.split = s->split;
   hipError_t e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T,
                                  kDims[4], st);
   if (e == hipSuccess)

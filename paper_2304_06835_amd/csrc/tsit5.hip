@@ -49,11 +49,14 @@ constexpr double kEta = 0.9, kFacMin = 0.2, kFacMax = 10.0, kQFloor = 1e-4;
 template <class R, class S>
 struct Tsit5Lane {
   static constexpr int N = S::N, M = S::M;
+  using Input = LaneInput<R, M, N>;
   R p[M], u[N], k1[N];
   CompTime t;
   double t0, tf;
   double ts;  // next save time
   R h;
+  R hmax;    // tf - t0: no step is longer
+  R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
   R lqold;  // log2 of the last accepted error proportion
   R* sp;        // out[j][0][col]: where the next save goes
   int j;        // next save index
@@ -82,7 +85,7 @@ struct Tsit5Lane {
   __device__ inline R initial_step(const LaunchArgs& a) {
     using F = Num<R>;
     const R atol = (R)a.atol, rtol = (R)a.rtol;
-    const R hmax = (R)(tf - t0);
+    const R span = (R)(tf - t0);
     R isc[N], s0 = 0, s1 = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -93,7 +96,7 @@ struct Tsit5Lane {
     }
     const R small = (R)(1e-10 * N);  // d < 1e-5  <=>  s / N < 1e-10
     R h0 = (s0 < small || s1 < small) ? (R)1e-6 : (R)0.01 * F::sqrt(s0 * F::rcp(s1));
-    h0 = fmin(h0, hmax);
+    h0 = fmin(h0, span);
     R y1[N], f1[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) y1[c] = fma(h0, k1[c], u[c]);
@@ -108,18 +111,17 @@ struct Tsit5Lane {
     const R h1 = (dm2 <= (R)1e-30)
                      ? fmax((R)1e-6, h0 * (R)1e-3)
                      : F::exp2(((R)-6.643856189774724 - (R)0.5 * F::log2(dm2)) * (R)(1.0 / 6.0));
-    return fmin(fmin((R)100 * h0, h1), hmax);
+    return fmin(fmin((R)100 * h0, h1), span);
   }
 
-  __device__ inline void init(const LaunchArgs& a, int64_t k) {
-    const int64_t i = in_col(a, k);
-    sp = static_cast<R*>(a.out) + out_col(a, k, i);
+  __device__ inline void init(const LaunchArgs& a, int64_t k, const Input& in) {
+    sp = static_cast<R*>(a.out) + out_col(a, k, in.i);
 #pragma unroll
-    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
+    for (int r = 0; r < M; ++r) p[r] = in.p[r];
 #pragma unroll
-    for (int c = 0; c < N; ++c) u[c] = load_col<R>(a, a.u0, c, i);
-    t0 = tspan_at(a, 0, i);
-    tf = tspan_at(a, 1, i);
+    for (int c = 0; c < N; ++c) u[c] = in.u[c];
+    t0 = in.t0;
+    tf = in.tf;
     t.set(t0);
     j = 0;
     nacc = nrej = 0;
@@ -135,7 +137,9 @@ struct Tsit5Lane {
     if (done) return;
     S::f(p, u, k1);
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
-    h = (R)fmin((double)h, tf - t0);
+    hmax = (R)(tf - t0);
+    h = fmin(h, hmax);
+    hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
     lqold = (R)-13.287712379549449;  // log2(1e-4)
   }
 
@@ -146,9 +150,10 @@ struct Tsit5Lane {
       done = true;
       return;
     }
-    const double rem = t.to(ts);
-    const bool clamped = (double)h >= rem;
-    const R he = clamped ? (R)rem : h;
+    // distance to the next save time; the step is cut to land on it
+    const R rem = (R)t.to(ts);
+    const bool clamped = h >= rem;
+    const R he = clamped ? rem : h;
 
     R k[7][N], y[N];
 #pragma unroll
@@ -184,7 +189,6 @@ struct Tsit5Lane {
       return;
     }
     const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));  // log2 q
-    const double hmax = tf - t0;
     if (q2 <= (R)1) {
       ++nacc;
       if (clamped)
@@ -201,15 +205,18 @@ struct Tsit5Lane {
       lqold = fmax(lq, (R)-13.287712379549449);
       R hn = he * fac;
       if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
-      h = (R)fmin((double)hn, hmax);
-      save_reached(a);
-      if (done) return;
+      h = fmin(hn, hmax);
+      hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
+      if (clamped) {  // only a cut step lands on a save time
+        save_reached(a);
+        if (done) return;
+      }
     } else {
       ++nrej;
       const R fac = fmax((R)kFacMin, (R)kEta * F::exp2((R)(-1.0 / kK) * lq));
       h = he * fac;
     }
-    if (!((double)h > 16.0 * DBL_EPSILON * fabs(t.hi))) {
+    if (!(h > hfloor)) {
       status = ENS_ST_DTMIN;
       done = true;
     }
@@ -237,15 +244,36 @@ __global__ void __launch_bounds__(kMaxBlock) tsit5_persistent(const LaunchArgs a
   run_persistent<Tsit5Lane<R, S>>(a);
 }
 
+template <class R, class S, int B, int RR>
+__global__ void __launch_bounds__(B) tsit5_sorted(const LaunchArgs a) {
+  run_sorted<Tsit5Lane<R, S>, B, RR>(a);
+}
+
+// Sorted form: block in {256, 512, 1024} x rounds (tpl) in {1, 2, 4}.
+template <class R, class S>
+void launch_sorted(const LaunchCfg& cfg, const LaunchArgs& a, hipStream_t s) {
+  const int rr = a.tpl >= 4 ? 4 : (a.tpl >= 2 ? 2 : 1);
+  const int64_t per = (int64_t)cfg.block * rr;
+  const dim3 grid((unsigned)((a.n + per - 1) / per)), blk((unsigned)cfg.block);
+#define ENS_SORTED(BB, RRR) \
+  if (cfg.block == BB && rr == RRR) { hipLaunchKernelGGL((tsit5_sorted<R, S, BB, RRR>), grid, blk, 0, s, a); return; }
+  ENS_SORTED(256, 1) ENS_SORTED(256, 2) ENS_SORTED(256, 4)
+  ENS_SORTED(512, 1) ENS_SORTED(512, 2) ENS_SORTED(512, 4)
+  ENS_SORTED(1024, 1) ENS_SORTED(1024, 2) ENS_SORTED(1024, 4)
+#undef ENS_SORTED
+}
+
 template <class R, class S>
 hipError_t launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   if (cfg.form == 0) {
     const int64_t per_block = (int64_t)cfg.block * a.tpl;
     const int64_t grid = (a.n + per_block - 1) / per_block;
     hipLaunchKernelGGL((tsit5_plain<R, S>), dim3((unsigned)grid), dim3(cfg.block), 0, s, a);
-  } else {
+  } else if (cfg.form == 1) {
     hipLaunchKernelGGL((tsit5_persistent<R, S>), dim3((unsigned)cfg.grid), dim3(cfg.block),
                        0, s, a);
+  } else {
+    launch_sorted<R, S>(cfg, a, s);
   }
   return hipGetLastError();
 }

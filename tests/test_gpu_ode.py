@@ -96,7 +96,9 @@ def test_tsit5_forms_and_launch_shapes_bitwise_equal(ens, precision):
     base, st0, s0 = run(ens, e, precision)
     for opts in ({"block": 64}, {"block": 128, "tpl": 2}, {"tpl": 4},
                  {"form": 1}, {"form": 1, "block": 64, "refill": 1},
-                 {"form": 1, "block": 128, "refill": 32}, {"form": 1, "grid": 3}):
+                 {"form": 1, "block": 128, "refill": 32}, {"form": 1, "grid": 3},
+                 {"form": 2}, {"form": 2, "block": 256}, {"form": 2, "block": 512, "tpl": 2},
+                 {"form": 2, "block": 256, "tpl": 4}):
         out, st, s = run(ens, e, precision, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(st, st0) and np.array_equal(s, s0), opts
@@ -136,7 +138,8 @@ def test_rodas4_forms_bitwise_equal(ens, precision):
     e = W.robertson(N=3001, dtype=np.float32 if precision == 32 else np.float64)
     banner(f"rodas4 forms fp{precision}")
     base, st0, s0 = run(ens, e, precision)
-    for opts in ({"block": 64, "tpl": 3}, {"form": 1}, {"form": 1, "refill": 4, "block": 128}):
+    for opts in ({"block": 64, "tpl": 3}, {"form": 1}, {"form": 1, "refill": 4, "block": 128},
+                 {"form": 2}, {"form": 2, "block": 256, "tpl": 2}):
         out, st, s = run(ens, e, precision, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(s, s0), opts
