@@ -75,7 +75,22 @@ def parse():
     ap.add_argument("--surrogate-epochs", type=int, default=120)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU-baseline sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy five times (the "
+                         "reference kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 28  # 2^28 floats = 1 GiB read + 1 GiB written per copy
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 4 * n, "bytes_written": 4 * n,
+                                           "launches": 5}}), flush=True)
 
 
 def make_workload(name, n):
@@ -325,6 +340,9 @@ def surrogate_variant(epochs, plain_ms_2p24):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(trajectories are independent: N GPUs would each solve their own slice)",
