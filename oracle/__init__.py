@@ -52,8 +52,13 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, dp, ctypes.c_int, dp,
                                 ip, i64p, i64p, ctypes.c_double, ctypes.c_int64,
                                 ctypes.c_int]
+        L.orc_solve_mode.argtypes = L.orc_solve.argtypes + [ctypes.c_int]
         L.orc_fixed.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double,
                                 ctypes.c_int, dp, dp]
+        L.orc_fixed_dense.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_double, dp]
+        L.orc_tsit5_dense_table.argtypes = [dp]
+        L.orc_tsit5_dense_table.restype = None
         L.orc_rhs.argtypes = [ctypes.c_int, dp, dp, dp]
         L.orc_jac.argtypes = [ctypes.c_int, dp, dp, dp]
         L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
@@ -85,8 +90,10 @@ def default_threads() -> int:
 
 
 def solve(system, alg, params, u0, tspan, atol, rtol, theta, h0=0.0,
-          maxiters=10**6, nthreads=None):
+          maxiters=10**6, nthreads=None, save_mode=0):
     """Adaptive ensemble solve.  params [m][N], u0 [n][N], tspan [2][N] or [2].
+    save_mode 0: steps land on every save time; 1 (Tsit5): steps land on the
+    last save time only and the others come from the dense output.
 
     Returns (out [n_save][n][N], status [N], naccept [N], nreject [N]).
     """
@@ -102,10 +109,10 @@ def solve(system, alg, params, u0, tspan, atol, rtol, theta, h0=0.0,
     st = np.empty(N, dtype=np.int32)
     na = np.empty(N, dtype=np.int64)
     nr = np.empty(N, dtype=np.int64)
-    rc = lib().orc_solve(system, alg, N, _p(params), _p(u0), _p(tspan), atol, rtol,
-                         _p(theta), len(theta), _p(out), _p(st, ctypes.c_int),
-                         _p(na, ctypes.c_int64), _p(nr, ctypes.c_int64), h0,
-                         maxiters, nthreads or default_threads())
+    rc = lib().orc_solve_mode(system, alg, N, _p(params), _p(u0), _p(tspan), atol, rtol,
+                              _p(theta), len(theta), _p(out), _p(st, ctypes.c_int),
+                              _p(na, ctypes.c_int64), _p(nr, ctypes.c_int64), h0,
+                              maxiters, nthreads or default_threads(), save_mode)
     if rc != 0:
         raise ValueError("orc_solve rejected its arguments")
     return out, st, na, nr
@@ -120,6 +127,24 @@ def fixed(system, alg, p, u0, h, n_steps):
     if lib().orc_fixed(system, alg, _p(p), _p(u0), h, n_steps, _p(u), _p(uh)) != 0:
         raise ValueError("orc_fixed rejected its arguments")
     return u, uh
+
+
+def fixed_dense(system, p, u0, h, n_steps, theta):
+    """n_steps fixed Tsit5 steps, the last read at its dense output:
+    u(t0 + (n_steps - 1 + theta) h) for one trajectory."""
+    n, _ = DIMS[system]
+    p, u0 = _f64(p), _f64(u0)
+    u = np.empty(n)
+    if lib().orc_fixed_dense(system, _p(p), _p(u0), h, n_steps, theta, _p(u)) != 0:
+        raise ValueError("orc_fixed_dense rejected its arguments")
+    return u
+
+
+def tsit5_dense_table():
+    """B [7][4]: b_i(theta) = sum_m B[i][m] theta^(m+1)."""
+    B = np.empty(28)
+    lib().orc_tsit5_dense_table(_p(B))
+    return B.reshape(7, 4)
 
 
 def rhs(system, p, u):

@@ -127,6 +127,23 @@ static const double TS_BT[7] = {
     -0.1447110071732629,     0.5823571654525552,     -0.45808210592918697,
     0.015151515151515152};
 
+/* Dense output (the "free" 4th-order interpolation of section 5.2.1, not
+ * printed there): u(t + theta h) = u + h sum_i b_i(theta) k_i with
+ * b_i(theta) = sum_m TS_DENSE[i][m-1] theta^m.  Derived from the order
+ * conditions: every order-<=4 condition holds for every theta, b(1) = b,
+ * b'(0) = e_1 and b'(1) = e_7 (C1 across steps), and the remaining free
+ * parameter minimises the integral over theta of the squared order-5
+ * defects.  The coefficients satisfy those conditions to ~1e-14, as closely
+ * as the tableau's published digits allow.                                 */
+static const double TS_DENSE[7][4] = {
+    {1.0, -2.7697190860447156, 2.925281239361705, -1.059101386498926},
+    {0.0, 0.12894207915150258, -0.2178841583029839, 0.09894207915151598},
+    {0.0, 3.95691789344045, -5.994277185222965, 2.517248942196988},
+    {0.0, -12.89991187880857, 31.315858054031978, -17.036937601119686},
+    {0.0, 39.47651966255469, -92.1133173868537, 49.346728208862906},
+    {0.0, -29.443930585810573, 68.18670326802032, -36.41806215810994},
+    {0.0, 1.5511819155171473, -4.102363831034384, 2.55118191551721}};
+
 /* RODAS4 of Hairer & Wanner, "Solving ODEs II", section IV.7, in the
  * transformed variables U_i = sum_j gamma_ij k_j, for which one stage reads
  *   (I/(gamma h) - J) U_i = f(u + sum_{j<i} a_ij U_j) + sum_{j<i} (C_ij / h) U_j.
@@ -168,6 +185,27 @@ void orc_tsit5_tableau(double c[7], double a[49], double b[7],
   }
 }
 
+void orc_tsit5_dense_table(double B[28]) {
+  for (int i = 0; i < 7; i++)
+    for (int m = 0; m < 4; m++) B[4 * i + m] = TS_DENSE[i][m];
+}
+
+/* u + h sum_i b_i(theta) k_i for the stages k of one Tsit5 step. */
+static void tsit5_dense(int n, const double *u, double k[7][NMAX], double h,
+                        double theta, double *out) {
+  double bt[7];
+  for (int i = 0; i < 7; i++) {
+    double b = 0.0;
+    for (int m = 3; m >= 0; m--) b = (b + TS_DENSE[i][m]) * theta;
+    bt[i] = b;
+  }
+  for (int c = 0; c < n; c++) {
+    double s = 0.0;
+    for (int i = 0; i < 7; i++) s += bt[i] * k[i][c];
+    out[c] = u[c] + h * s;
+  }
+}
+
 void orc_rodas4_tableau(double *gamma, double a[36], double C[36],
                         double m[6], double mhat[6]) {
   *gamma = RO_GAMMA;
@@ -190,7 +228,7 @@ void orc_rodas4_tableau(double *gamma, double a[36], double C[36],
  * (= unew - uhat) and k7 = f(unew).                                          */
 static void tsit5_step(int sys, const double *p, int n, const double *u,
                        const double *k1, double h, double *unew, double *err,
-                       double *k7) {
+                       double *k7, double kall[7][NMAX]) {
   double k[7][NMAX], y[NMAX];
   for (int c = 0; c < n; c++) k[0][c] = k1[c];
   for (int i = 1; i < 7; i++) {
@@ -208,6 +246,9 @@ static void tsit5_step(int sys, const double *p, int n, const double *u,
     err[c] = h * s;
     k7[c] = k[6][c];
   }
+  if (kall)
+    for (int i = 0; i < 7; i++)
+      for (int c = 0; c < n; c++) kall[i][c] = k[i][c];
 }
 
 /* LU factorisation with partial pivoting of the n x n row-major matrix W. */
@@ -332,15 +373,20 @@ static double initial_step(int sys, const double *pp, int n, const double *u0,
 #define PI_FMIN 0.2
 #define PI_FMAX 10.0
 #define PI_QFLOOR 1e-4
+#define STRETCH 1.1 /* steps within 10% of the next save time land on it */
 
+/* save_mode 0: every save time is a step end (steps land on it);
+ * save_mode 1 (Tsit5 only): steps land only on the last save time and the
+ * earlier ones are read off the dense output of the step that covers them. */
 static void solve_one(int sys, int alg, int n, const double *p,
                       const double *u0, double t0, double tf, double atol,
                       double rtol, const double *theta, int n_save,
                       double *outcol /* [n_save][n] */, int *status,
                       int64_t *nacc, int64_t *nrej, double h0,
-                      int64_t maxiters) {
+                      int64_t maxiters, int save_mode) {
   const double kexp = (alg == ORC_TSIT5) ? 5.0 : 4.0;
-  double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX];
+  const int dense = save_mode == 1 && alg == ORC_TSIT5;
+  double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX], kall[7][NMAX];
   double hmax = tf - t0;
   int j = 0;
   int64_t acc = 0, rej = 0;
@@ -369,19 +415,31 @@ static void solve_one(int sys, int alg, int n, const double *p,
   double qold = PI_QFLOOR;
   while (j < n_save) {
     if (acc + rej >= maxiters) { *status = ORC_MAXITERS; break; }
-    double ts = t0 + theta[j] * (tf - t0);
+    /* the time the step may not pass: the next save time, or with dense
+     * output the last one */
+    double ts = t0 + theta[dense ? n_save - 1 : j] * (tf - t0);
     double rem = ts - t;
-    int clamped = (h >= rem);
+    /* a step that would end within 10% short of the save time is stretched
+     * onto it (no spurious short step before the save); after a rejected
+     * stretched step h <= 0.9 rem, so the stretch cannot repeat a rejection */
+    int clamped = (h * STRETCH >= rem);
     double he = clamped ? rem : h;
     if (alg == ORC_TSIT5)
-      tsit5_step(sys, p, n, u, k1, he, unew, err, k7);
+      tsit5_step(sys, p, n, u, k1, he, unew, err, k7, kall);
     else
       rodas4_step(sys, p, n, u, he, unew, err);
     double q = error_q(n, err, u, unew, atol, rtol);
     if (!isfinite(q)) { *status = ORC_NONFINITE; break; }
     if (q <= 1.0) {
       acc++;
-      t = clamped ? ts : t + he;
+      double tn = clamped ? ts : t + he;
+      if (dense) /* save times inside the step, read off its dense output */
+        for (; j < n_save; j++) {
+          double tj = t0 + theta[j] * (tf - t0);
+          if (!(tj <= tn) || (clamped && j == n_save - 1)) break;
+          tsit5_dense(n, u, kall, he, (tj - t) / he, outcol + j * n);
+        }
+      t = tn;
       for (int c = 0; c < n; c++) u[c] = unew[c];
       if (alg == ORC_TSIT5)
         for (int c = 0; c < n; c++) k1[c] = k7[c];
@@ -413,16 +471,17 @@ static void solve_one(int sys, int alg, int n, const double *p,
   *nrej = rej;
 }
 
-int orc_solve(int sys, int alg, int64_t N, const double *params,
-              const double *u0, const double *tspan, double atol,
-              double rtol, const double *theta, int n_save, double *out,
-              int *status, int64_t *naccept, int64_t *nreject, double h0,
-              int64_t maxiters, int nthreads) {
+int orc_solve_mode(int sys, int alg, int64_t N, const double *params,
+                   const double *u0, const double *tspan, double atol,
+                   double rtol, const double *theta, int n_save, double *out,
+                   int *status, int64_t *naccept, int64_t *nreject, double h0,
+                   int64_t maxiters, int nthreads, int save_mode) {
   int n, m;
   if (orc_dims(sys, &n, &m) != 0 || sys == ORC_GBM4) return -1;
   if (alg != ORC_TSIT5 && alg != ORC_RODAS4) return -1;
   if (N < 0 || n_save < 1 || !params || !u0 || !tspan || !theta || !out)
     return -1;
+  if (save_mode != 0 && save_mode != 1) return -1;
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
   for (int64_t i = 0; i < N; i++) {
@@ -433,13 +492,46 @@ int orc_solve(int sys, int alg, int64_t N, const double *params,
     int64_t a, rj;
     double *colp = (n_save <= 64) ? col : (double *)malloc(sizeof(double) * n_save * n);
     solve_one(sys, alg, n, p, uu, tspan[i], tspan[N + i], atol, rtol, theta,
-              n_save, colp, &st, &a, &rj, h0, maxiters);
+              n_save, colp, &st, &a, &rj, h0, maxiters, save_mode);
     for (int s = 0; s < n_save; s++)
       for (int c = 0; c < n; c++) out[((int64_t)s * n + c) * N + i] = colp[s * n + c];
     if (colp != col) free(colp);
     if (status) status[i] = st;
     if (naccept) naccept[i] = a;
     if (nreject) nreject[i] = rj;
+  }
+  return 0;
+}
+
+int orc_solve(int sys, int alg, int64_t N, const double *params,
+              const double *u0, const double *tspan, double atol,
+              double rtol, const double *theta, int n_save, double *out,
+              int *status, int64_t *naccept, int64_t *nreject, double h0,
+              int64_t maxiters, int nthreads) {
+  return orc_solve_mode(sys, alg, N, params, u0, tspan, atol, rtol, theta,
+                        n_save, out, status, naccept, nreject, h0, maxiters,
+                        nthreads, 0);
+}
+
+/* n_steps fixed Tsit5 steps of size h from u0, the last one read at its
+ * dense output: u(t0 + (n_steps - 1 + theta) h).                           */
+int orc_fixed_dense(int sys, const double *p, const double *u0, double h,
+                    int n_steps, double theta, double *u_out) {
+  int n, m;
+  if (orc_dims(sys, &n, &m) != 0 || sys == ORC_GBM4 || n_steps < 1) return -1;
+  double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX], kall[7][NMAX];
+  for (int c = 0; c < n; c++) u[c] = u0[c];
+  orc_rhs(sys, p, u, k1);
+  for (int s = 0; s < n_steps; s++) {
+    tsit5_step(sys, p, n, u, k1, h, unew, err, k7, kall);
+    if (s == n_steps - 1) {
+      tsit5_dense(n, u, kall, h, theta, u_out);
+      return 0;
+    }
+    for (int c = 0; c < n; c++) {
+      u[c] = unew[c];
+      k1[c] = k7[c];
+    }
   }
   return 0;
 }
@@ -453,7 +545,7 @@ int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,
   orc_rhs(sys, p, u, k1);
   for (int s = 0; s < n_steps; s++) {
     if (alg == ORC_TSIT5)
-      tsit5_step(sys, p, n, u, k1, h, unew, err, k7);
+      tsit5_step(sys, p, n, u, k1, h, unew, err, k7, NULL);
     else
       rodas4_step(sys, p, n, u, h, unew, err);
     if (s == n_steps - 1)

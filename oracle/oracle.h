@@ -50,6 +50,23 @@ int orc_solve(int sys, int alg, int64_t N, const double *params,
               int *status, int64_t *naccept, int64_t *nreject, double h0,
               int64_t maxiters, int nthreads);
 
+/* orc_solve with a save mode: 0 as orc_solve (steps land on every save
+ * time); 1 (Tsit5) steps land only on the last save time and the others are
+ * read off the dense output of the step covering them.                     */
+int orc_solve_mode(int sys, int alg, int64_t N, const double *params,
+                   const double *u0, const double *tspan, double atol,
+                   double rtol, const double *theta, int n_save, double *out,
+                   int *status, int64_t *naccept, int64_t *nreject, double h0,
+                   int64_t maxiters, int nthreads, int save_mode);
+
+/* Tsit5 dense-output coefficients B[i][m] (b_i(theta) = sum_m B[i][m] theta^(m+1)). */
+void orc_tsit5_dense_table(double B[28]);
+
+/* n_steps fixed Tsit5 steps of size h, the last one read at theta:
+ * u(t0 + (n_steps - 1 + theta) h).                                          */
+int orc_fixed_dense(int sys, const double *p, const double *u0, double h,
+                    int n_steps, double theta, double *u_out);
+
 /* n_steps fixed steps of size h from u0 for one trajectory.  u_out gets the
  * propagated solution, uhat_out the embedded (lower-order) one.            */
 int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,

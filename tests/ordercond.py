@@ -103,3 +103,67 @@ def rosenbrock_residuals(alpha, beta, b, gamma, p):
         (4, b @ beta @ beta @ bp - (1.0 / 24.0 - g / 2.0 + 1.5 * g * g - g**3)),
     ]
     return np.array([r for (q, r) in conds if q <= p])
+
+
+def continuous_extension(A, b, c, p=4):
+    """Coefficients B [s][p] of a dense output u(t + theta h) = u + h sum_i
+    b_i(theta) k_i with b_i(theta) = sum_m B[i][m-1] theta^m, chosen as:
+    order conditions through order p for every theta (b(theta)^T Phi(t) =
+    theta^|t| / gamma(t)), b(1) = b, b'(0) = e_1 and b'(1) = e_s (C1 across
+    steps of a first-same-as-last pair), and among those the one minimising
+    the integral over theta in [0, 1] of the squared order-(p+1) defects.
+    Equality-constrained least squares solved exactly through its KKT
+    system (the integrals of polynomial products are exact)."""
+    s = A.shape[0]
+    nv = s * p
+    rows, rhs = [], []
+    for q in range(1, p + 1):
+        for t in trees(q):
+            phi = elementary_weight(t, A, c)
+            for m in range(1, p + 1):
+                r = np.zeros(nv)
+                r[np.arange(s) * p + (m - 1)] = phi
+                rows.append(r)
+                rhs.append(1.0 / density(t) if m == q else 0.0)
+    for i in range(s):
+        r = np.zeros(nv)
+        r[i * p:(i + 1) * p] = 1.0
+        rows.append(r)
+        rhs.append(b[i])
+        r = np.zeros(nv)
+        r[i * p] = 1.0
+        rows.append(r)
+        rhs.append(1.0 if i == 0 else 0.0)
+        r = np.zeros(nv)
+        r[i * p:(i + 1) * p] = np.arange(1, p + 1)
+        rows.append(r)
+        rhs.append(1.0 if i == s - 1 else 0.0)
+    C = np.array(rows)
+    d = np.array(rhs)
+    # objective: sum over order-(p+1) trees of int_0^1 (sum_m theta^m w_m . x - theta^(p+1)/g)^2
+    H = np.zeros((nv, nv))
+    f = np.zeros(nv)
+    for t in trees(p + 1):
+        phi = elementary_weight(t, A, c)
+        g = 1.0 / density(t)
+        V = np.zeros((p, nv))  # coefficient of theta^m (m = 1..p) as a row over unknowns
+        for m in range(1, p + 1):
+            V[m - 1, np.arange(s) * p + (m - 1)] = phi
+        M = np.array([[1.0 / (a + bb + 1) for bb in range(1, p + 1)] for a in range(1, p + 1)])
+        H += V.T @ M @ V
+        f += g * (V.T @ np.array([1.0 / (m + p + 2) for m in range(1, p + 1)]))
+    # KKT: [2H C^T; C 0] [x; lam] = [2f; d]; C has dependent rows, so lstsq
+    K = np.block([[2 * H, C.T], [C, np.zeros((C.shape[0], C.shape[0]))]])
+    sol = np.linalg.lstsq(K, np.concatenate([2 * f, d]), rcond=1e-13)[0]
+    return sol[:nv].reshape(s, p)
+
+
+def dense_residuals(A, c, B, thetas, p=4):
+    """max over theta and trees of order <= p of |b(theta)^T Phi(t) - theta^|t|/gamma(t)|."""
+    worst = 0.0
+    for th in thetas:
+        bt = B @ np.array([th ** m for m in range(1, B.shape[1] + 1)])
+        for q in range(1, p + 1):
+            for t in trees(q):
+                worst = max(worst, abs(bt @ elementary_weight(t, A, c) - th ** q / density(t)))
+    return worst
