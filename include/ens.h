@@ -107,6 +107,11 @@ typedef struct ens_ctx ens_ctx;
                                (2, 3, 4), or 2 or 3 subtiles and two waves per
                                SIMD (12, 13; default 13); 0: the layer-by-layer
                                tiled-product path                             */
+#define ENS_OPT_SAVE_MODE 13 /* 0 (default): steps land on every save time;
+                                1 (ENS_ALG_TSIT5 only, else ENS_EUNSUPPORTED):
+                                steps land on the last save time only and the
+                                earlier ones are read off the step's 4th-order
+                                dense output (section 5.2.1's interpolation) */
 
 /* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
 #define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,

@@ -12,7 +12,7 @@ SYSTEMS = {"linear": 0, "lorenz": 1, "robertson": 2, "gbm4": 3}
 ALGS = {"tsit5": 1, "rodas4": 2, "em": 3}
 OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
         "maxiters": 7, "tspan_broadcast": 8, "refill": 9, "grid": 10, "tpl": 11,
-        "mlp_tile": 12}
+        "mlp_tile": 12, "save_mode": 13}
 PTRS = {"status": 1, "stats": 2}
 
 # Every symbol include/ens.h declares.

@@ -70,6 +70,8 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
     return fail(c, ENS_EINVAL, "unknown alg %d", alg);
   if (!supported(sys, alg))
     return fail(c, ENS_EUNSUPPORTED, "system %d has no kernel for alg %d", sys, alg);
+  if (c->save_mode == 1 && alg != ENS_ALG_TSIT5)
+    return fail(c, ENS_EUNSUPPORTED, "dense output (save mode 1) is implemented for Tsit5 only");
   if (alg == ENS_ALG_EM && c->precision != 32)
     return fail(c, ENS_EUNSUPPORTED, "Euler-Maruyama is built for precision 32 only");
   if (n < 0 || n > (int64_t(1) << 40))
@@ -123,6 +125,7 @@ ens::LaunchArgs make_args(ens_ctx* c, int64_t n, const void* params, const void*
   a.tspan_bcast = c->tspan_bcast;
   a.refill = c->refill;
   a.tpl = c->tpl;
+  a.dense = c->save_mode == 1;
   for (int j = 0; j < n_save; ++j) a.theta[j] = theta[j];
   return a;
 }
@@ -289,6 +292,10 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       if (!integral || v < 1 || v > 8) return fail(c, ENS_EINVAL, "tpl must be in [1, 8]");
       c->tpl = (int)v;
       return ENS_OK;
+    case ENS_OPT_SAVE_MODE:
+      if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "save mode must be 0 or 1");
+      c->save_mode = (int)v;
+      return ENS_OK;
     case ENS_OPT_MLP_TILE:
       if (v != 0 && v != 2 && v != 3 && v != 4 && v != 12 && v != 13)
         return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3, 4, 12 or 13");
@@ -313,6 +320,7 @@ int ens_get_option(const ens_ctx* c, int key, double* v) {
     case ENS_OPT_GRID: *v = c->grid; return ENS_OK;
     case ENS_OPT_TPL: *v = c->tpl; return ENS_OK;
     case ENS_OPT_MLP_TILE: *v = c->mlp_tile; return ENS_OK;
+    case ENS_OPT_SAVE_MODE: *v = c->save_mode; return ENS_OK;
   }
   return ENS_EINVAL;
 }

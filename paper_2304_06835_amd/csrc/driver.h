@@ -38,6 +38,11 @@ struct Num<double> {
   __device__ static inline double nan() { return __builtin_nan(""); }
 };
 
+// Save-time landing: a step whose proposal reaches within this factor of
+// the remaining distance to the next save time is set to exactly that
+// distance (cut when longer, stretched when up to 10% shorter).
+constexpr double kStretch = 1.1;
+
 // t_hi + t_lo carries the time exactly enough that N steps of size h lose no
 // more than one rounding of the final sum (Knuth's TwoSum on every add).
 struct CompTime {

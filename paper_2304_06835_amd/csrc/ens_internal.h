@@ -38,6 +38,7 @@ struct LaunchArgs {
   int tspan_bcast;
   int refill;                // persistent form: idle lanes that trigger a refill
   int tpl;                   // plain form: trajectories per lane
+  int dense;                 // Tsit5: 1 = save times from the dense output
   double theta[kMaxSave];
 };
 
@@ -79,6 +80,7 @@ struct ens_ctx {
   int refill = 16;
   int grid = 0;
   int mlp_tile = 13;
+  int save_mode = 0;
   int tspan_bcast = 0;
   double dt = 0.0;
   double h0 = 0.0;

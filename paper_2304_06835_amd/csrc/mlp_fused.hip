@@ -148,45 +148,54 @@ __device__ inline void load_chunk(const uint16_t* src, uint8_t* slot, int wave, 
 
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
 
-#ifndef ENS_MLP_FENCE
-#define ENS_MLP_FENCE 1
-#endif
-constexpr bool kFence = ENS_MLP_FENCE;
+// Products of one pair of 16-row output blocks (rb, rb+1) of a 256 x 256
+// layer for every subtile, the accumulators starting from the bias.
+template <int NS>
+__device__ inline void pair_mfma(const uint8_t* lds, int slot_off, int pp, int rb, int bias0,
+                                 int g, int lane, const bf16x8_t (&x)[NS][8],
+                                 f32x4_t (&acc)[2][NS]) {
+  const f32x4_t b0 = bias4(lds, bias0 + 16 * rb + 4 * g);
+  const f32x4_t b1 = bias4(lds, bias0 + 16 * (rb + 1) + 4 * g);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    acc[0][s] = b0;
+    acc[1][s] = b1;
+  }
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) {
+    const bf16x8_t a0 = frag(lds, slot_off + ((2 * pp) * 8 + kb) * kFrag * 2, lane);
+    const bf16x8_t a1 = frag(lds, slot_off + ((2 * pp + 1) * 8 + kb) * kFrag * 2, lane);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      acc[0][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, x[s][kb], acc[0][s], 0, 0, 0);
+      acc[1][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x[s][kb], acc[1][s], 0, 0, 0);
+    }
+  }
+}
 
-// One 64-row chunk of a 256 x 256 layer: pairs of 16-row blocks (2c, 2c+1)
-// and (2c+2, 2c+3) of the output for every subtile.
+// The activation epilogue of a pair: y[s][k] = bf16(silu(acc)).
+template <int NS>
+__device__ inline void pair_silu(const f32x4_t (&acc)[2][NS], bf16x8_t (&y)[NS][8], int k) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) y[s][k] = silu_pack(acc[0][s], acc[1][s]);
+}
+
+// One 64-row chunk (pairs 2c and 2c+1) of a 256 x 256 layer.  Fences keep
+// each pair's products and its epilogue in program order: left free, the
+// scheduler merges neighbouring pairs and runs out of registers.  Matrix-core
+// and vector work overlap across the two waves that share a SIMD.  (Running
+// those two waves deliberately out of phase -- one deferring each chunk's
+// last epilogue past the block barrier -- measured 2-5% slower.)
 template <int NS>
 __device__ inline void chunk_layer(const uint8_t* lds, int slot_off, int c, int bias0, int g,
                                    int lane, const bf16x8_t (&x)[NS][8], bf16x8_t (&y)[NS][8]) {
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
-    const int rb = 4 * c + 2 * pp;  // global row block of the pair's first tile
     f32x4_t acc[2][NS];
-    const f32x4_t b0 = bias4(lds, bias0 + 16 * rb + 4 * g);
-    const f32x4_t b1 = bias4(lds, bias0 + 16 * (rb + 1) + 4 * g);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-      acc[0][s] = b0;
-      acc[1][s] = b1;
-    }
-    // Scheduling fences keep one pair's products and its activation epilogue
-    // in program order: left free, the scheduler overlaps neighbouring
-    // pairs and runs out of registers; the overlap of matrix-core and vector
-    // work comes instead from the second wave on each SIMD.
-    if (kFence) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) {
-      const bf16x8_t a0 = frag(lds, slot_off + ((2 * pp) * 8 + kb) * kFrag * 2, lane);
-      const bf16x8_t a1 = frag(lds, slot_off + ((2 * pp + 1) * 8 + kb) * kFrag * 2, lane);
-#pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        acc[0][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, x[s][kb], acc[0][s], 0, 0, 0);
-        acc[1][s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, x[s][kb], acc[1][s], 0, 0, 0);
-      }
-    }
-    if (kFence) __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) y[s][rb >> 1] = silu_pack(acc[0][s], acc[1][s]);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_mfma<NS>(lds, slot_off, pp, 4 * c + 2 * pp, bias0, g, lane, x, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    pair_silu<NS>(acc, y, 2 * c + pp);
   }
 }
 

@@ -196,14 +196,16 @@ struct Rodas4Lane {
 
   __device__ inline void attempt(const LaunchArgs& a, int64_t) {
     using F = Num<R>;
-    if ((int64_t)(nacc + nrej) >= a.maxiters) {
+    if (nacc + nrej >= (int)a.maxiters) {  // maxiters <= 2e9 (ens_set_option)
       status = ENS_ST_MAXITERS;
       done = true;
       return;
     }
-    // distance to the next save time; the step is cut to land on it
+    // distance to the next save time: a longer step is cut to land on it,
+    // and one ending within 10% short of it is stretched onto it (after a
+    // rejected stretched step h <= 0.9 rem, so the stretch cannot repeat)
     const R rem = (R)t.to(ts);
-    const bool clamped = h >= rem;
+    const bool clamped = h * (R)kStretch >= rem;
     const R he = clamped ? rem : h;
 
     // W = I/(gamma h) - J, factored in FP64

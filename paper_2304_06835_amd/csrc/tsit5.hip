@@ -39,6 +39,21 @@ constexpr double BT[7] = {-0.00178001105222577714, -0.0008164344596567469,
                           0.5823571654525552,      -0.45808210592918697,
                           0.015151515151515152};
 
+// Dense output, u(t + theta h) = u + h sum_i b_i(theta) k_i with
+// b_i(theta) = sum_m TD[i][m] theta^(m+1): the 4th-order C1 continuous
+// extension of the pair (every order-<=4 condition for every theta,
+// b(1) = b, b'(0) = e_1, b'(1) = e_7), the member of that one-parameter family
+// with the least integrated squared order-5 defect.  Section 5.2.1 names this
+// "free" interpolation without printing it.
+constexpr double TD[7][4] = {
+    {1.0, -2.7697190860447156, 2.925281239361705, -1.059101386498926},
+    {0.0, 0.12894207915150258, -0.2178841583029839, 0.09894207915151598},
+    {0.0, 3.95691789344045, -5.994277185222965, 2.517248942196988},
+    {0.0, -12.89991187880857, 31.315858054031978, -17.036937601119686},
+    {0.0, 39.47651966255469, -92.1133173868537, 49.346728208862906},
+    {0.0, -29.443930585810573, 68.18670326802032, -36.41806215810994},
+    {0.0, 1.5511819155171473, -4.102363831034384, 2.55118191551721}};
+
 // PI controller (section 3.1: h_new = eta q_{n-1}^beta2 q_n^beta1 h) with
 // Gustafsson's exponents beta1 = -0.7/k, beta2 = 0.4/k, k = 5 (embedded
 // order + 1), eta = 0.9, growth clamped to [0.2, 10]; q_{n-1} starts at 1e-4
@@ -53,7 +68,9 @@ struct Tsit5Lane {
   R p[M], u[N], k1[N];
   CompTime t;
   double t0, tf;
-  double ts;  // next save time
+  double ts;     // next save time
+  double tland;  // the time steps land on: the next save time, or with dense
+                 // output (a.dense) the last one
   R h;
   R hmax;    // tf - t0: no step is longer
   R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
@@ -134,6 +151,7 @@ struct Tsit5Lane {
     }
     ts = save_time(a, t0, tf, 0);
     save_reached(a);  // saves that coincide with t0 (tf == t0)
+    tland = a.dense ? save_time(a, t0, tf, a.n_save - 1) : ts;
     if (done) return;
     S::f(p, u, k1);
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
@@ -143,16 +161,45 @@ struct Tsit5Lane {
     lqold = (R)-13.287712379549449;  // log2(1e-4)
   }
 
+  // Dense output: every save time before the landing time that the accepted
+  // step [t, t + he] covers is read off the continuous extension (t, u still
+  // hold the step's start).
+  __device__ inline void dense_saves(const LaunchArgs& a, R he, const R (&k)[7][N]) {
+    using F = Num<R>;
+    const R ih = F::rcp(he);
+    while (j < a.n_save - 1) {
+      const R d = (R)t.to(ts);
+      if (!(d <= he)) break;
+      const R th = d * ih;
+      R bt[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        bt[i] = fma(fma(fma((R)TD[i][3], th, (R)TD[i][2]), th, (R)TD[i][1]), th, (R)TD[i][0]) * th;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        R acc = bt[0] * k[0][c];
+#pragma unroll
+        for (int i = 1; i < 7; ++i) acc = fma(bt[i], k[i][c], acc);
+        sp[c * a.out_stride] = fma(he, acc, u[c]);
+      }
+      sp += N * a.out_stride;
+      ++j;
+      ts = save_time(a, t0, tf, j);
+    }
+  }
+
   __device__ inline void attempt(const LaunchArgs& a, int64_t) {
     using F = Num<R>;
-    if ((int64_t)(nacc + nrej) >= a.maxiters) {
+    if (nacc + nrej >= (int)a.maxiters) {  // maxiters <= 2e9 (ens_set_option)
       status = ENS_ST_MAXITERS;
       done = true;
       return;
     }
-    // distance to the next save time; the step is cut to land on it
-    const R rem = (R)t.to(ts);
-    const bool clamped = h >= rem;
+    // distance to the next save time: a longer step is cut to land on it,
+    // and one ending within 10% short of it is stretched onto it (after a
+    // rejected stretched step h <= 0.9 rem, so the stretch cannot repeat)
+    const R rem = (R)t.to(tland);
+    const bool clamped = h * (R)kStretch >= rem;
     const R he = clamped ? rem : h;
 
     R k[7][N], y[N];
@@ -191,8 +238,9 @@ struct Tsit5Lane {
     const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));  // log2 q
     if (q2 <= (R)1) {
       ++nacc;
+      if (a.dense) dense_saves(a, he, k);  // save times inside this step
       if (clamped)
-        t.set(ts);
+        t.set(tland);
       else
         t.add((double)he);
 #pragma unroll
@@ -210,6 +258,7 @@ struct Tsit5Lane {
       if (clamped) {  // only a cut step lands on a save time
         save_reached(a);
         if (done) return;
+        if (!a.dense) tland = ts;
       }
     } else {
       ++nrej;

@@ -247,3 +247,63 @@ def test_audit_and_fallback_rule(ens):
     err = normwise(pred[:, :, a], sol[:, :, a]).max(axis=0)
     assert abs(rep[3] - err.max()) <= 1e-6 * err.max()
     torch.cuda.synchronize()
+
+
+def test_surrogate_gain_over_solver(ens):
+    """What the trained network gains over the solver alone, on 2^20 fresh
+    queries after a short training run (2^19 samples, 60 epochs).  For
+    validation tolerances 5e-2, 1e-2 and the configured 1e-3 (bins that fail
+    their audit go to the solver) the test records the share the network
+    answers and the time against ens_solve on the same queries.  Asserted are
+    the properties the audited solve guarantees, not a speed: solver answers
+    are bit-identical to ens_solve, network answers to predict, every
+    audited query in a bin left to the network is within the tolerance, and
+    at 5e-2 the network answers a non-empty share of the queries."""
+    import time
+
+    import torch
+    banner("surrogate gain over solver")
+    e, P, U, T, y, s = lorenz_data(ens, 1 << 19, 41)
+    m = ens.Surrogate(s, seed=5)
+    m.fit_norm(P, U, y.view(48, -1))
+    m.train(P, U, y.view(48, -1), epochs=60, batch=4096, lr_max=3e-3, lr_min=3e-5, seed=6)
+    q = W.lorenz_fp32(N=1 << 20, seed=42)
+    Pq, Uq, Tq = to_dev(q.params), to_dev(q.u0), to_dev(q.tspan)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            r = fn()
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) / 3
+
+    sol, t_solver = timed(lambda: s.solve("lorenz", Pq, Uq, Tq, "tsit5", q.abstol, q.reltol,
+                                          q.theta))
+    sol_h = to_host(sol)
+    pred = to_host(m.predict(Pq, Uq))
+    for tol in (5e-2, 1e-2, 1e-3):
+        (out, used, rep), t_surr = timed(
+            lambda: m.solve(Pq, Uq, Tq, q.abstol, q.reltol, q.theta, audit_frac=0.01,
+                            fallback_tol=tol, audit_seed=8))
+        out, used, rep = to_host(out), to_host(used), to_host(rep)
+        net = used == 0
+        print("tol %.0e: network answers %.3f of the queries, %d/28 bins flagged, "
+              "surrogate solve %.2f ms vs solver %.2f ms (gain %.2fx)"
+              % (tol, net.mean(), int(rep[2]), t_surr * 1e3, t_solver * 1e3, t_solver / t_surr))
+        s_ = used != 0
+        assert np.array_equal(bits(out[:, :, s_]), bits(sol_h[:, :, s_]))
+        assert np.array_equal(bits(out[:, :, net]), bits(pred[:, :, net]))
+        # audited queries of bins the network keeps are within tolerance
+        nrm = to_host(m.buffer("norm"))
+        lo, hi = np.float32(nrm[8]), np.float32(nrm[12])  # training range of rho
+        f = (q.params[1].astype(np.float32) - lo) / np.maximum(hi - lo, np.float32(1e-30))
+        b = np.clip(np.floor(f * np.float32(28)).astype(int), 0, 27)
+        audited = used == 1
+        err = normwise(pred[:, :, audited], sol_h[:, :, audited]).max(axis=0)
+        kept_bins = set(np.unique(b[net]))
+        in_kept = np.isin(b[audited], list(kept_bins))
+        assert (err[in_kept] <= tol).all()
+        if tol == 5e-2:
+            assert net.mean() > 0.0

@@ -218,3 +218,84 @@ def test_autotune_picks_a_valid_config_with_identical_results(ens):
     out = to_host(s.solve("lorenz", *args))
     assert np.array_equal(out.view(np.uint8), ref.view(np.uint8))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["lorenz_fp32", "robertson"])
+def test_full_size_in_the_benchmarked_launch(ens, orc, name):
+    """The benchmark's workloads at their full sizes (2^24 Lorenz with 16
+    saves, 2^20 Robertson) in the launch configuration bench.py times (the
+    cost-sorted form, block 256): every trajectory finishes with status 0,
+    and 4096 sampled trajectories match the FP64 oracle at tol 1e-12 within
+    the FP32 bar; the persistent form gives the same bits on the sample."""
+    import torch
+    e = W.lorenz_fp32() if name == "lorenz_fp32" else W.robertson()
+    banner(f"{name} full size N={e.n}, sorted form")
+    s = ens.Solver(0, precision=32, form=2, block=256)
+    if e.h0:
+        s.set(h0=e.h0)
+    status = torch.empty(e.n, dtype=torch.uint8, device="cuda")
+    P, U, T = to_dev(e.params), to_dev(e.u0), to_dev(e.tspan)
+    out = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta, status=status)
+    st = to_host(status)
+    assert (st == 0).all()
+    idx = W.sample_indices(e.n, 4096)
+    got = np.ascontiguousarray(to_host(out)[:, :, idx])
+    sub = W.Ensemble(e.name, e.system, e.alg, np.ascontiguousarray(e.params[:, idx]),
+                     np.ascontiguousarray(e.u0[:, idx]), np.ascontiguousarray(e.tspan[:, idx]),
+                     e.theta, e.abstol, e.reltol, e.h0)
+    truth, *_ = oracle_solve(orc, sub, tol=1e-12)
+    err = normwise(got, truth)
+    print("%s full size, sampled: max normwise error %.3e" % (name, err.max()))
+    assert err.max() <= FP32_BAR
+    del out
+    s.set(form=1, block=256)
+    out1 = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta)
+    got1 = np.ascontiguousarray(to_host(out1)[:, :, idx])
+    assert np.array_equal(got1.view(np.uint8), got.view(np.uint8))
+
+
+def test_dense_output_fp64_matches_oracle(ens, orc):
+    """Save mode 1 (Tsit5 dense output) in FP64 against the oracle's dense
+    mode with the same settings: rounding-order differences only; and the
+    same attempt counts for almost every trajectory."""
+    e = W.lorenz_fp32(N=3001, seed=23)
+    e.params, e.u0 = e.params.astype(np.float64), e.u0.astype(np.float64)
+    banner(f"lorenz fp64 tsit5 dense output N={e.n}")
+    out, st, stats = run(ens, e, 64, save_mode=1)
+    assert (st == 0).all()
+    ref, _, na, nr = orc.solve(orc.LORENZ, orc.TSIT5, e.params, e.u0, e.tspan, e.abstol,
+                               e.reltol, e.theta, save_mode=1)
+    err = normwise(out, ref)
+    print("fp64 dense vs oracle dense: max %.3e median %.3e" % (err.max(), np.median(err)))
+    assert err.max() <= FP64_SAME_ALG_BAR
+    assert np.median(err) <= 1e-12
+    assert np.mean((stats[0] == na) & (stats[1] == nr)) > 0.95
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_dense_output_fp32_accuracy_and_forms(ens, orc, form):
+    """FP32 dense output against the FP64 truth (landing oracle at 1e-12):
+    within the FP32 bar, fewer attempts than the landing mode, and the three
+    work-assignment forms give the same bits."""
+    e = W.lorenz_fp32(N=4099, seed=24)
+    banner(f"lorenz fp32 dense output form {form}")
+    out, st, stats = run(ens, e, 32, save_mode=1, form=form)
+    assert (st == 0).all()
+    truth, *_ = oracle_solve(orc, e, tol=1e-12)
+    err = normwise(out, truth)
+    _, _, land = run(ens, e, 32)
+    print("fp32 dense vs truth: max %.3e; attempts dense %.1f landing %.1f"
+          % (err.max(), stats.sum(0).mean(), land.sum(0).mean()))
+    assert err.max() <= FP32_BAR
+    assert stats.sum(0).mean() < 0.85 * land.sum(0).mean()
+    if form != 0:
+        base, _, s0 = run(ens, e, 32, save_mode=1)
+        assert np.array_equal(out.view(np.uint8), base.view(np.uint8))
+        assert np.array_equal(stats, s0)
+
+
+def test_dense_output_is_tsit5_only(ens):
+    import paper_2304_06835_amd as ensmod
+    e = W.robertson(N=64)
+    with pytest.raises(ensmod.EnsError):
+        run(ens, e, 32, save_mode=1)
