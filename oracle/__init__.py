@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 LINEAR, LORENZ, ROBERTSON, GBM4 = 0, 1, 2, 3
-TSIT5, RODAS4 = 1, 2
+TSIT5, RODAS4, ROS23 = 1, 2, 3
 DIMS = {LINEAR: (3, 9), LORENZ: (3, 3), ROBERTSON: (3, 3), GBM4: (4, 2)}
 
 

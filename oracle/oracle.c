@@ -13,8 +13,8 @@
  *     control h_new = eta q_{n-1}^{beta2} q_n^{beta1} h: section 3.1, eq. 4.
  *   - Tsitouras 5(4) pair (GPUTsit5): section 5.2.1.
  *   - Rosenbrock s-stage method: section 3.2.1, eqs. 5-8; 4th-order stiffly
- *     stable variant (GPURodas4): section 5.2.1; LU of W per system:
- *     section 5.1.3, eq. 16.
+ *     stable variant (GPURodas4) and the 2(3) pair (GPURosenbrock23):
+ *     section 5.2.1; LU of W per system: section 5.1.3, eq. 16.
  *   - SDE definition dX = a dt + b dW, dW ~ N(0, dt): section 3.3, eq. 11;
  *     Euler-Maruyama (GPUEM): section 5.2.2.
  *   - Models: appendix (Lorenz, Robertson, linear SDE).
@@ -327,6 +327,46 @@ static void rodas4_step(int sys, const double *p, int n, const double *u,
 /* Adaptive driver                                                           */
 /* ------------------------------------------------------------------------ */
 
+/* Rosenbrock23 (GPURosenbrock23 of section 5.2.1): the modified Rosenbrock
+ * pair of Shampine & Reichelt (SIAM J. Sci. Comput. 18, 1997, the ode23s
+ * formulas), written in its own variables.  With d = 1/(2 + sqrt 2),
+ * e32 = 6 + sqrt 2, W = I - h d J and F0 = f(u):
+ *   k1 = W^-1 F0
+ *   F1 = f(u + h k1 / 2),      k2 = W^-1 (F1 - k1) + k1
+ *   unew = u + h k2            (order 2, L-stable)
+ *   F2 = f(unew),              k3 = W^-1 (F2 - e32 (k2 - F1) - 2 (k1 - F0))
+ * and unew + h (k1 - 2 k2 + k3) / 6 is the order-3 companion.  err is unew
+ * minus that companion, so the embedded solution is unew - err as for the
+ * other methods.  Autonomous systems only (no df/dt terms).                */
+static void ros23_step(int sys, const double *p, int n, const double *u,
+                       double h, double *unew, double *err) {
+  const double d = 1.0 / (2.0 + sqrt(2.0)), e32 = 6.0 + sqrt(2.0);
+  double J[NMAX * NMAX], W[NMAX * NMAX], F0[NMAX], F1[NMAX], F2[NMAX];
+  double k1[NMAX], k2[NMAX], k3[NMAX], y[NMAX];
+  int piv[NMAX];
+  orc_jac(sys, p, u, J);
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++)
+      W[i * n + j] = (i == j ? 1.0 : 0.0) - h * d * J[i * n + j];
+  lu_factor(n, W, piv);
+  orc_rhs(sys, p, u, F0);
+  for (int c = 0; c < n; c++) k1[c] = F0[c];
+  lu_solve(n, W, piv, k1);
+  for (int c = 0; c < n; c++) y[c] = u[c] + 0.5 * h * k1[c];
+  orc_rhs(sys, p, y, F1);
+  for (int c = 0; c < n; c++) k2[c] = F1[c] - k1[c];
+  lu_solve(n, W, piv, k2);
+  for (int c = 0; c < n; c++) {
+    k2[c] += k1[c];
+    unew[c] = u[c] + h * k2[c];
+  }
+  orc_rhs(sys, p, unew, F2);
+  for (int c = 0; c < n; c++)
+    k3[c] = F2[c] - e32 * (k2[c] - F1[c]) - 2.0 * (k1[c] - F0[c]);
+  lu_solve(n, W, piv, k3);
+  for (int c = 0; c < n; c++) err[c] = -h / 6.0 * (k1[c] - 2.0 * k2[c] + k3[c]);
+}
+
 /* Scaled error proportion q of eq. 4, taking the norm as the root mean square
  * over the n components (Hairer, Norsett & Wanner I, section II.4).        */
 static double error_q(int n, const double *err, const double *u,
@@ -384,7 +424,10 @@ static void solve_one(int sys, int alg, int n, const double *p,
                       double *outcol /* [n_save][n] */, int *status,
                       int64_t *nacc, int64_t *nrej, double h0,
                       int64_t maxiters, int save_mode) {
-  const double kexp = (alg == ORC_TSIT5) ? 5.0 : 4.0;
+  /* PI exponent k = embedded order + 1; p = order of the propagated
+   * solution (starting-step heuristic) */
+  const double kexp = (alg == ORC_TSIT5) ? 5.0 : (alg == ORC_RODAS4 ? 4.0 : 3.0);
+  const int porder = (alg == ORC_TSIT5) ? 5 : (alg == ORC_RODAS4 ? 4 : 2);
   const int dense = save_mode == 1 && alg == ORC_TSIT5;
   double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX], kall[7][NMAX];
   double hmax = tf - t0;
@@ -409,8 +452,7 @@ static void solve_one(int sys, int alg, int n, const double *p,
   orc_rhs(sys, p, u, k1);
   double h = h0;
   if (j < n_save && !(h0 > 0.0))
-    h = initial_step(sys, p, n, u, k1, atol, rtol, alg == ORC_TSIT5 ? 5 : 4,
-                     hmax);
+    h = initial_step(sys, p, n, u, k1, atol, rtol, porder, hmax);
   h = fmin(h, hmax);
   double qold = PI_QFLOOR;
   while (j < n_save) {
@@ -426,8 +468,10 @@ static void solve_one(int sys, int alg, int n, const double *p,
     double he = clamped ? rem : h;
     if (alg == ORC_TSIT5)
       tsit5_step(sys, p, n, u, k1, he, unew, err, k7, kall);
-    else
+    else if (alg == ORC_RODAS4)
       rodas4_step(sys, p, n, u, he, unew, err);
+    else
+      ros23_step(sys, p, n, u, he, unew, err);
     double q = error_q(n, err, u, unew, atol, rtol);
     if (!isfinite(q)) { *status = ORC_NONFINITE; break; }
     if (q <= 1.0) {
@@ -478,7 +522,7 @@ int orc_solve_mode(int sys, int alg, int64_t N, const double *params,
                    int64_t maxiters, int nthreads, int save_mode) {
   int n, m;
   if (orc_dims(sys, &n, &m) != 0 || sys == ORC_GBM4) return -1;
-  if (alg != ORC_TSIT5 && alg != ORC_RODAS4) return -1;
+  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23) return -1;
   if (N < 0 || n_save < 1 || !params || !u0 || !tspan || !theta || !out)
     return -1;
   if (save_mode != 0 && save_mode != 1) return -1;
@@ -540,14 +584,17 @@ int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,
               int n_steps, double *u_out, double *uhat_out) {
   int n, m;
   if (orc_dims(sys, &n, &m) != 0) return -1;
+  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23) return -1;
   double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX];
   for (int c = 0; c < n; c++) u[c] = u0[c];
   orc_rhs(sys, p, u, k1);
   for (int s = 0; s < n_steps; s++) {
     if (alg == ORC_TSIT5)
       tsit5_step(sys, p, n, u, k1, h, unew, err, k7, NULL);
-    else
+    else if (alg == ORC_RODAS4)
       rodas4_step(sys, p, n, u, h, unew, err);
+    else
+      ros23_step(sys, p, n, u, h, unew, err);
     if (s == n_steps - 1)
       for (int c = 0; c < n; c++) uhat_out[c] = unew[c] - err[c];
     for (int c = 0; c < n; c++) u[c] = unew[c];

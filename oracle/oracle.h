@@ -27,7 +27,7 @@ enum {
   ORC_ROBERTSON = 2, /* appendix, Robertson equation: p = (k1, k2, k3), n = 3     */
   ORC_GBM4 = 3       /* appendix, linear SDE with 4 components: p = (mu, sigma)   */
 };
-enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2 };
+enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3 };
 enum { ORC_OK = 0, ORC_MAXITERS = 1, ORC_DTMIN = 2, ORC_NONFINITE = 3 };
 
 int orc_dims(int sys, int *n, int *m);
