@@ -70,10 +70,14 @@ typedef struct ens_ctx ens_ctx;
                             FP64 LU and solves              sec. 3.2.1, 5.1.3, 5.2.1 */
 #define ENS_ALG_EM 3     /* fixed-step Euler-Maruyama, Philox4x32-10 normals
                                                             sec. 3.3, 5.2.2     */
+#define ENS_ALG_ROS23 4  /* adaptive Rosenbrock23: the L-stable 2(3) modified
+                            Rosenbrock pair of Shampine & Reichelt, W = I - d h J
+                            with d = 1/(2 + sqrt 2), FP64 LU, solves and stage
+                            vectors, FSAL                    sec. 3.2.1, 5.2.1 */
 
 /* ---- scalar options (ens_set_option) ------------------------------------ */
 #define ENS_OPT_PRECISION 1 /* 32 (default): FP32 state, FP64 compensated time
-                               (and FP64 W/LU/solves for RODAS4);
+                               (and FP64 W/LU/solves for RODAS4 and ROS23);
                                64: FP64 throughout.  Also the dtype of params,
                                u0 and out.                                      */
 #define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;
@@ -156,8 +160,8 @@ int ens_system_dims(int system_id, int *n, int *m);
  *   tspan      device, float64: [2][n_traj] (row 0 t0, row 1 tf, tf >= t0),
  *              or [2] with ENS_OPT_TSPAN_BROADCAST = 1
  *   alg        ENS_ALG_*; (system, alg) must be one of
- *              {LINEAR, LORENZ} x TSIT5, {LINEAR, LORENZ, ROBERTSON} x RODAS4,
- *              GBM4 x EM
+ *              {LINEAR, LORENZ} x TSIT5,
+ *              {LINEAR, LORENZ, ROBERTSON} x {RODAS4, ROS23}, GBM4 x EM
  *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM)
  *   save_times HOST, [n_save] fractions theta_j, 0 < theta_0 < ... <= 1; save
  *              j of trajectory i is at t0_i + theta_j (tf_i - t0_i).  Adaptive

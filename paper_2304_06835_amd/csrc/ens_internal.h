@@ -43,7 +43,7 @@ struct LaunchArgs {
 };
 
 struct LaunchCfg {
-  int form;   // 0 plain, 1 persistent
+  int form;   // 0 plain, 1 persistent, 2 cost-sorted
   int block;  // threads per block
   int grid;   // persistent: blocks (0: occupancy-derived)
 };
@@ -53,6 +53,8 @@ hipError_t launch_tsit5(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                         hipStream_t s);
 hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                          hipStream_t s);
+hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                        hipStream_t s);
 hipError_t launch_em(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                      hipStream_t s);
 

@@ -39,7 +39,7 @@ FULL_N = {"lorenz_fp64": 8192, "lorenz_fp32": 1 << 24, "robertson": 1 << 20,
 class Ensemble:
     name: str
     system: str            # "lorenz" | "robertson" | "gbm4" | "linear"
-    alg: str               # "tsit5" | "rodas4" | "em"
+    alg: str               # "tsit5" | "rodas4" | "ros23" | "em"
     params: np.ndarray     # [m][N]
     u0: np.ndarray         # [n][N]
     tspan: np.ndarray      # [2][N] float64 (t0 row, tf row)
@@ -91,7 +91,7 @@ def lorenz_fp32(N: int = FULL_N["lorenz_fp32"], seed: int = SEEDS["lorenz_fp32"]
 
 
 def robertson(N: int = FULL_N["robertson"], seed: int = SEEDS["robertson"],
-              dtype=np.float32):
+              dtype=np.float32, alg: str = "rodas4"):
     rng = np.random.Generator(np.random.PCG64(seed))
     scale = np.exp(rng.uniform(np.log(0.5), np.log(2.0), (3, N)))
     k = np.array([[0.04], [3e7], [1e4]]) * scale
@@ -99,7 +99,7 @@ def robertson(N: int = FULL_N["robertson"], seed: int = SEEDS["robertson"],
     params = np.ascontiguousarray(k, dtype=dtype)
     u0 = _rows(np.ones(N), np.zeros(N), np.zeros(N), dtype=dtype)
     tspan = _rows(np.zeros(N), tf, dtype=np.float64)
-    return Ensemble("robertson", "robertson", "rodas4", params, u0, tspan,
+    return Ensemble("robertson", "robertson", alg, params, u0, tspan,
                     np.array([1.0]), abstol=1e-8, reltol=1e-6, h0=1e-4)
 
 
