@@ -6,7 +6,9 @@ Tsit5 at reltol = abstol = 1e-6, 16 evenly spaced saves on t in [0, 1].
 One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
     python bench.py [--steps K] [--warmup W] [--workload lorenz_fp32|lorenz_fp64|
-                     robertson|gbm] [--form plain|persistent|sorted|auto]
+                     robertson|gbm] [--alg rodas4|ros23]
+                    [--form plain|persistent|sorted|sorted_b512_r2|auto]
+                    [--save-mode landing|dense]
                     [--no-cpu-baseline] [--no-variants] [--no-surrogate]
 
 Prints one JSON line.  `roofline` reports the solver kernel's algorithmic
@@ -41,9 +43,17 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 #    + RHS + solve-rhs + triangular solves) = 6 x 69 = 414 minus the
 #    empty first-stage combinations 18 -> 396, u_new 3, error norm 19,
 #    control 7  -> 466.
+#  Rosenbrock23, Robertson (n = 3): Jacobian 6, W 12, LU 26, three solves
+#    3 x 15, two RHS 2 x 8, stage right-hand sides and points 3 + 3 + 18 + 7
+#    + 6, error estimate 13, error norm 19, control 7  -> 181.
 #  EM, GBM4: per step 4 x (2 flops for the increment + 2 for the update) +
 #    Box-Muller 2 x 8  -> 32 (Philox is integer work, counted separately).
-FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("em", "gbm4"): 32}
+FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("ros23", "robertson"): 181,
+         ("em", "gbm4"): 32}
+# Tsit5 dense output, per save time read off a step (save mode 1; every save
+# but the last, which a step lands on): theta 2, the seven weight polynomials
+# b_i(theta) by Horner 7 x 7, and u + h sum_i b_i k_i for n = 3: 3 x 15 -> 96.
+DENSE_FLOPS_PER_SAVE = 96
 MLP_FLOPS_PER_QUERY = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 48)  # 288,768
 
 # MI355X published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s, FP64
@@ -56,6 +66,8 @@ PEAK_BF16_MFMA = 2500.0
 
 FORMS = {"plain": {"form": 0}, "persistent": {"form": 1},
          "sorted": {"form": 2, "block": 256}}
+# the stiff ensemble also at a sort over 1024 items in 512-thread blocks
+STIFF_FORMS = dict(FORMS, sorted_b512_r2={"form": 2, "block": 512, "tpl": 2})
 DEFAULT_FORM = {"lorenz_fp32": "sorted", "lorenz_fp64": "plain", "robertson": "sorted",
                 "gbm": "plain"}
 # save times: "landing" (steps end on every save time) or "dense" (Tsit5's
@@ -73,7 +85,10 @@ def parse():
     ap.add_argument("--workload", default="lorenz_fp32",
                     choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm"])
     ap.add_argument("--n", type=int, default=0, help="override the ensemble size")
-    ap.add_argument("--form", default="", choices=["", "plain", "persistent", "sorted", "auto"])
+    ap.add_argument("--alg", default="", choices=["", "rodas4", "ros23"],
+                    help="stiff method of the Robertson workload (default rodas4)")
+    ap.add_argument("--form", default="",
+                    choices=["", "plain", "persistent", "sorted", "sorted_b512_r2", "auto"])
     ap.add_argument("--save-mode", default="", choices=["", "landing", "dense"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -108,11 +123,12 @@ def copy_calibration():
         flush=True)
 
 
-def make_workload(name, n):
+def make_workload(name, n, alg=""):
     from paper_2304_06835_amd import workloads as W
     f = {"lorenz_fp32": W.lorenz_fp32, "lorenz_fp64": W.lorenz_fp64,
          "robertson": W.robertson, "gbm": W.gbm}[name]
-    return f(N=n) if n else f()
+    kw = {"alg": alg} if (alg and name == "robertson") else {}
+    return f(N=n, **kw) if n else f(**kw)
 
 
 def describe(e):
@@ -123,7 +139,8 @@ def describe(e):
         return "Lorenz 8192-ensemble, rho~U[0,21], FP64, Tsit5 rtol=atol=1e-8, final state"
     if e.name == "robertson":
         return ("Robertson 2^20-ensemble, rates x logU[0.5,2], tf~logU[1,1e5], FP32 state + "
-                "FP64 W/LU, Rodas4 rtol=1e-6 atol=1e-8, final state")
+                f"FP64 W/LU, {'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 "
+                "atol=1e-8, final state")
     return "GBM 4-component 2^22-ensemble, Euler-Maruyama dt=1/256, Philox4x32-10, FP32"
 
 
@@ -192,14 +209,16 @@ class Runner:
         return self.out.cpu().numpy()
 
 
-def kernel_source_hash():
-    """Hash of the solver sources a recorded traffic measurement refers to."""
+def kernel_source_hash(files=None):
+    """Hash of the sources a recorded traffic measurement refers to: the
+    named files of the kernel's translation unit, or every solver source."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2304_06835_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    names = sorted(files) if files else sorted(
+        f for f in os.listdir(csrc) if f.endswith((".hip", ".h")))
+    for f in names:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
@@ -212,7 +231,7 @@ def recorded_traffic(name, form, launches_units):
     with open(path) as fh:
         rec = json.load(fh)
     r = rec.get(f"{name}/{form}")
-    if not r or r.get("source_hash") != kernel_source_hash():
+    if not r or r.get("source_hash") != kernel_source_hash(r.get("sources")):
         return None
     return r.get("hbm_bytes_per_launch")
 
@@ -274,10 +293,10 @@ def cpu_baseline(e, gpu_out, seconds):
     return res, {"max_rel_err": err, "subsample": len(idx), "kind": kind}
 
 
-def form_variants(e, precision, steps, base_out, plain_ms, save_mode=0):
+def form_variants(e, precision, steps, base_out, plain_ms, save_mode=0, forms=None):
     """Every work-assignment form on the same inputs: time and bitwise check."""
     out = {}
-    for name, opts in FORMS.items():
+    for name, opts in (forms or FORMS).items():
         r = Runner(e, precision, save_mode=save_mode, **opts)
         _, ms, _ = r.time(max(3, steps // 2), 1)
         same = bool((r.host_out().view("u1") == base_out.view("u1")).all())
@@ -286,6 +305,42 @@ def form_variants(e, precision, steps, base_out, plain_ms, save_mode=0):
                      "bitwise_equal_to_headline": same}
         del r
     return out
+
+
+def stiff_ros23_variant(rob, steps, rodas4_forms):
+    """The Robertson ensemble with Rosenbrock23 instead of Rodas4: every form
+    (bitwise check against its own plain form), attempts, the algorithmic
+    rate of the fastest form, its speedup over the fastest Rodas4 form, and
+    the error of a 4096 subsample against the FP64 truth (Rodas4 oracle at
+    tol 1e-12)."""
+    import numpy as np
+
+    import oracle
+    from paper_2304_06835_amd import workloads as W
+    e = W.robertson(alg="ros23")
+    base = _plain_out(e)
+    fv = form_variants(e, 32, steps, base, None, forms=STIFF_FORMS)
+    pm = fv["plain"]["kernel_ms"]
+    for v in fv.values():
+        v["speedup_vs_plain"] = pm / v["kernel_ms"]
+    best = min(fv, key=lambda k: fv[k]["kernel_ms"])
+    r = Runner(e, 32, **STIFF_FORMS[best])
+    attempts, stats = r.attempts()
+    del r
+    ms = fv[best]["kernel_ms"]
+    fl = FLOPS[("ros23", "robertson")] * attempts / (ms * 1e-3) / 1e12
+    idx = W.sample_indices(e.n, 4096)
+    truth = oracle.solve(oracle.ROBERTSON, oracle.RODAS4, np.ascontiguousarray(e.params[:, idx]),
+                         np.ascontiguousarray(e.u0[:, idx]), np.ascontiguousarray(e.tspan[:, idx]),
+                         1e-12, 1e-12, e.theta, h0=e.h0)[0]
+    got = base[:, :, idx].astype(np.float64)
+    err = np.abs(got - truth).max(axis=1) / np.abs(truth).max(axis=1)
+    r4 = min(v["kernel_ms"] for v in rodas4_forms.values())
+    st = stats.cpu().numpy().sum(axis=0)
+    return {"forms": fv, "fastest_form": best, "attempts_per_traj_mean": float(st.mean()),
+            "attempts_per_traj_max": int(st.max()), "achieved_tflops": fl,
+            "frac_of_fp32_peak": fl / PEAK[32], "speedup_vs_fastest_rodas4": r4 / ms,
+            "max_rel_err_vs_truth_4096": float(err.max())}
 
 
 def config_variant(name, precision, steps):
@@ -402,7 +457,7 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    e = make_workload(args.workload, args.n)
+    e = make_workload(args.workload, args.n, args.alg)
     precision = 64 if args.workload == "lorenz_fp64" else 32
     form = args.form or DEFAULT_FORM[args.workload]
     save = args.save_mode or DEFAULT_SAVE[args.workload]
@@ -415,7 +470,7 @@ def main():
         from paper_2304_06835_amd import workloads as W
         k = min(e.n, 1 << 18)
         idx = W.sample_indices(e.n, k)
-        pe = make_workload(args.workload, 0)
+        pe = make_workload(args.workload, 0, args.alg)
         pe.params, pe.u0, pe.tspan = (e.params[:, idx].copy(), e.u0[:, idx].copy(),
                                       e.tspan[:, idx].copy())
         probe = Runner(pe, precision)
@@ -423,7 +478,7 @@ def main():
                                     pe.abstol, pe.reltol, pe.theta)
         opts = dict(tuned)
     else:
-        opts = dict(FORMS[form])
+        opts = dict(STIFF_FORMS[form])
     opts["save_mode"] = SAVE_MODES[save]
     r = Runner(e, precision, **opts)
     print(f"[bench] {e.name} N={e.n} precision={precision} form={form} save={save}",
@@ -435,17 +490,19 @@ def main():
     value = e.n * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
     fpa = FLOPS[(e.alg, e.system)]
-    flops = fpa * attempts
+    dense_saves = e.n * (len(e.theta) - 1) if save == "dense" else 0
+    flops = fpa * attempts + DENSE_FLOPS_PER_SAVE * dense_saves
     peak = PEAK[precision]
     achieved = flops / (ker_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": recorded_traffic(e.name, form + ("/dense" if save == "dense" else ""), 1),
-            "kernel": {"tsit5": "tsit5", "rodas4": "rodas4", "em": "em_gbm4"}[e.alg]
+            "kernel": {"tsit5": "tsit5", "rodas4": "ros", "ros23": "ros", "em": "em_gbm4"}[e.alg]
                       + {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
-                         "auto": ""}[form] + f"<{'double' if precision == 64 else 'float'}>",
+                         "sorted_b512_r2": "_sorted", "auto": ""}[form] + f"<{'double' if precision == 64 else 'float'}>",
             "kernel_ms_avg": ker_ms, "kernel_ms_min": ker_min,
-            "flops_per_launch": flops, "attempted_steps": attempts, "flops_per_attempt": fpa}
+            "flops_per_launch": flops, "attempted_steps": attempts, "flops_per_attempt": fpa,
+            "dense_output_saves": dense_saves, "flops_per_dense_save": DENSE_FLOPS_PER_SAVE}
     st = stats.cpu().numpy()
     steps_per = st.sum(axis=0)
     config = {"workload": describe(e), "name": e.name, "n_traj": e.n, "alg": e.alg,
@@ -483,11 +540,12 @@ def main():
                                       "fp32_headline_speedup": k3 / ker_ms}
             del r64
             rob = make_workload("robertson", 0)
-            rv = form_variants(rob, 32, args.steps, _plain_out(rob), None)
+            rv = form_variants(rob, 32, args.steps, _plain_out(rob), None, forms=STIFF_FORMS)
             rp = rv["plain"]["kernel_ms"]
             for v in rv.values():
                 v["speedup_vs_plain"] = rp / v["kernel_ms"]
             variants["robertson_2p20_forms"] = rv
+            variants["robertson_2p20_ros23"] = stiff_ros23_variant(rob, args.steps, rv)
             variants["lorenz_fp64_8192"] = config_variant("lorenz_fp64", 64, args.steps)
             variants["gbm_em_2p22"] = config_variant("gbm", 32, args.steps)
             if not args.no_surrogate:

@@ -391,8 +391,10 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
     if (alg != ENS_ALG_EM)
       for (int rf : {4, 16, 32}) cands[nc++] = {1, b, 1, rf};
   }
-  if (alg != ENS_ALG_EM)
+  if (alg != ENS_ALG_EM) {
     for (int b : {256, 512, 1024}) cands[nc++] = {2, b, 1, 64};
+    for (int b : {256, 512}) cands[nc++] = {2, b, 2, 64};  // sort over 2 * block items
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(c, ENS_EDEVICE, "hipEventCreate failed");
