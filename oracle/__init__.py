@@ -18,9 +18,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LINEAR, LORENZ, ROBERTSON, GBM4 = 0, 1, 2, 3
+LINEAR, LORENZ, ROBERTSON, GBM4, OREGO, HIRES, POLLU = 0, 1, 2, 3, 4, 5, 6
 TSIT5, RODAS4, ROS23 = 1, 2, 3
-DIMS = {LINEAR: (3, 9), LORENZ: (3, 3), ROBERTSON: (3, 3), GBM4: (4, 2)}
+DIMS = {LINEAR: (3, 9), LORENZ: (3, 3), ROBERTSON: (3, 3), GBM4: (4, 2), OREGO: (3, 3),
+        HIRES: (8, 12), POLLU: (20, 25)}
 
 
 def build(verbose: bool = False) -> str:

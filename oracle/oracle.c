@@ -17,7 +17,8 @@
  *     section 5.2.1; LU of W per system: section 5.1.3, eq. 16.
  *   - SDE definition dX = a dt + b dW, dW ~ N(0, dt): section 3.3, eq. 11;
  *     Euler-Maruyama (GPUEM): section 5.2.2.
- *   - Models: appendix (Lorenz, Robertson, linear SDE).
+ *   - Models: appendix (Lorenz, Robertson, linear SDE); stiff test problems
+ *     OREGO, HIRES and POLLU of appendix B.1.
  */
 #include "oracle.h"
 
@@ -26,7 +27,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NMAX 4
+#define NMAX 20 /* largest system: POLLU */
+#define MMAX 32 /* most parameters: POLLU's 25 rate constants */
 
 /* ------------------------------------------------------------------------ */
 /* Systems                                                                   */
@@ -38,8 +40,55 @@ int orc_dims(int sys, int *n, int *m) {
   case ORC_LORENZ: *n = 3; *m = 3; return 0;
   case ORC_ROBERTSON: *n = 3; *m = 3; return 0;
   case ORC_GBM4: *n = 4; *m = 2; return 0;
+  case ORC_OREGO: *n = 3; *m = 3; return 0;
+  case ORC_HIRES: *n = 8; *m = 12; return 0;
+  case ORC_POLLU: *n = 20; *m = 25; return 0;
   }
   return -1;
+}
+
+/* POLLU (appendix B.1 of the paper, after Verwer 1994) as 25 reactions.
+ * Reaction j runs at r_j = k_j * y[A_j] (* y[B_j] when B_j >= 0); its
+ * effect on dy/dt is the column of the stoichiometric table: species
+ * POLLU_S[j][0..] gain (positive) or lose (negative) r_j.  The table is the
+ * paper's 20 equations read term by term (u_9 and u_16 in the equations for
+ * dy5 and dy6 read as y9 and y16).  Indices are 0-based.                  */
+static const int POLLU_A[25] = {0, 1, 4, 6, 6, 6, 8, 8, 10, 10, 12, 9, 13,
+                                0, 2, 3, 3, 15, 15, 16, 18, 18, 0, 18, 19};
+static const int POLLU_B[25] = {-1, 3, 1, -1, -1, 5, -1, 5, 1, 0, -1, 1, -1,
+                                5, -1, -1, -1, -1, -1, 5, -1, -1, 3, 0, -1};
+/* (species, coefficient) pairs per reaction, terminated by coefficient 0 */
+static const int POLLU_S[25][6][2] = {
+    {{0, -1}, {1, 1}, {2, 1}},                  /* r1:  y1 -> y2 + y3        */
+    {{1, -1}, {3, -1}, {0, 1}},                 /* r2:  y2 + y4 -> y1        */
+    {{4, -1}, {1, -1}, {0, 1}, {5, 1}},         /* r3:  y5 + y2 -> y1 + y6   */
+    {{6, -1}, {4, 2}, {7, 1}},                  /* r4:  y7 -> 2 y5 + y8      */
+    {{6, -1}, {7, 1}},                          /* r5:  y7 -> y8             */
+    {{6, -1}, {5, -1}, {4, 1}, {7, 1}},         /* r6:  y7 + y6 -> y5 + y8   */
+    {{8, -1}, {4, 1}, {7, 1}, {9, 1}},          /* r7:  y9 -> y5 + y8 + y10  */
+    {{8, -1}, {5, -1}, {10, 1}},                /* r8:  y9 + y6 -> y11       */
+    {{10, -1}, {1, -1}, {0, 1}, {9, 1}, {11, 1}},  /* r9: y11 + y2 -> y1 + y10 + y12 */
+    {{10, -1}, {0, -1}, {12, 1}},               /* r10: y11 + y1 -> y13      */
+    {{12, -1}, {0, 1}, {10, 1}},                /* r11: y13 -> y1 + y11      */
+    {{9, -1}, {1, -1}, {0, 1}, {13, 1}},        /* r12: y10 + y2 -> y1 + y14 */
+    {{13, -1}, {4, 1}, {6, 1}},                 /* r13: y14 -> y5 + y7       */
+    {{0, -1}, {5, -1}, {14, 1}},                /* r14: y1 + y6 -> y15       */
+    {{2, -1}, {3, 1}},                          /* r15: y3 -> y4             */
+    {{3, -1}, {15, 1}},                         /* r16: y4 -> y16            */
+    {{3, -1}, {2, 1}},                          /* r17: y4 -> y3             */
+    {{15, -1}, {5, 2}},                         /* r18: y16 -> 2 y6          */
+    {{15, -1}, {2, 1}},                         /* r19: y16 -> y3            */
+    {{16, -1}, {5, -1}, {4, 1}, {17, 1}},       /* r20: y17 + y6 -> y5 + y18 */
+    {{18, -1}, {1, 1}},                         /* r21: y19 -> y2            */
+    {{18, -1}, {0, 1}, {2, 1}},                 /* r22: y19 -> y1 + y3       */
+    {{0, -1}, {3, -1}, {18, 1}},                /* r23: y1 + y4 -> y19       */
+    {{18, -1}, {0, -1}, {19, 1}},               /* r24: y19 + y1 -> y20      */
+    {{19, -1}, {0, 1}, {18, 1}},                /* r25: y20 -> y1 + y19      */
+};
+
+static double pollu_rate(const double *k, const double *y, int j) {
+  double r = k[j] * y[POLLU_A[j]];
+  return POLLU_B[j] >= 0 ? r * y[POLLU_B[j]] : r;
 }
 
 /* Appendix, Lorenz problem: dy1 = sigma (y2 - y1), dy2 = rho y1 - y2 - y1 y3,
@@ -70,6 +119,39 @@ int orc_rhs(int sys, const double *p, const double *u, double *du) {
   case ORC_GBM4:
     for (int i = 0; i < 4; i++) du[i] = p[0] * u[i];
     return 0;
+  case ORC_OREGO: {
+    /* appendix B.1 (OREGO) with the textbook sign of dy1 (see oracle.h) */
+    double k1 = p[0], k2 = p[1], k3 = p[2];
+    du[0] = k1 * (u[1] + u[0] * (1.0 - k2 * u[0] - u[1]));
+    du[1] = (u[2] - (1.0 + u[0]) * u[1]) / k1;
+    du[2] = k3 * (u[0] - u[2]);
+    return 0;
+  }
+  case ORC_HIRES: {
+    /* appendix B.1 (HIRES); p = the 12 distinct rate constants in the order
+     * (1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280,
+     * 0.69, 1.81), each standing for every occurrence of its value */
+    const double *k = p;
+    const double *y = u;
+    du[0] = -k[0] * y[0] + k[1] * y[1] + k[2] * y[2] + k[3];
+    du[1] = k[0] * y[0] - k[4] * y[1];
+    du[2] = -k[5] * y[2] + k[1] * y[3] + k[6] * y[4];
+    du[3] = k[2] * y[1] + k[0] * y[2] - k[7] * y[3];
+    du[4] = -k[8] * y[4] + k[1] * y[5] + k[1] * y[6];
+    du[5] = -k[9] * y[5] * y[7] + k[10] * y[3] + k[0] * y[4] - k[1] * y[5] +
+            k[10] * y[6];
+    du[6] = k[9] * y[5] * y[7] - k[11] * y[6];
+    du[7] = -k[9] * y[5] * y[7] + k[11] * y[6];
+    return 0;
+  }
+  case ORC_POLLU:
+    for (int i = 0; i < 20; i++) du[i] = 0.0;
+    for (int j = 0; j < 25; j++) {
+      double r = pollu_rate(p, u, j);
+      for (int e = 0; e < 6 && POLLU_S[j][e][1] != 0; e++)
+        du[POLLU_S[j][e][0]] += POLLU_S[j][e][1] * r;
+    }
+    return 0;
   }
   return -1;
 }
@@ -97,6 +179,51 @@ int orc_jac(int sys, const double *p, const double *u, double *J) {
   case ORC_GBM4:
     memset(J, 0, 16 * sizeof(double));
     for (int i = 0; i < 4; i++) J[5 * i] = p[0];
+    return 0;
+  case ORC_OREGO: {
+    double k1 = p[0], k2 = p[1], k3 = p[2];
+    J[0] = k1 * (1.0 - 2.0 * k2 * u[0] - u[1]);
+    J[1] = k1 * (1.0 - u[0]);
+    J[2] = 0.0;
+    J[3] = -u[1] / k1;
+    J[4] = -(1.0 + u[0]) / k1;
+    J[5] = 1.0 / k1;
+    J[6] = k3;
+    J[7] = 0.0;
+    J[8] = -k3;
+    return 0;
+  }
+  case ORC_HIRES: {
+    const double *k = p;
+    const double *y = u;
+    memset(J, 0, 64 * sizeof(double));
+    J[0 * 8 + 0] = -k[0]; J[0 * 8 + 1] = k[1]; J[0 * 8 + 2] = k[2];
+    J[1 * 8 + 0] = k[0];  J[1 * 8 + 1] = -k[4];
+    J[2 * 8 + 2] = -k[5]; J[2 * 8 + 3] = k[1]; J[2 * 8 + 4] = k[6];
+    J[3 * 8 + 1] = k[2];  J[3 * 8 + 2] = k[0]; J[3 * 8 + 3] = -k[7];
+    J[4 * 8 + 4] = -k[8]; J[4 * 8 + 5] = k[1]; J[4 * 8 + 6] = k[1];
+    J[5 * 8 + 3] = k[10]; J[5 * 8 + 4] = k[0];
+    J[5 * 8 + 5] = -k[9] * y[7] - k[1];
+    J[5 * 8 + 6] = k[10]; J[5 * 8 + 7] = -k[9] * y[5];
+    J[6 * 8 + 5] = k[9] * y[7]; J[6 * 8 + 6] = -k[11]; J[6 * 8 + 7] = k[9] * y[5];
+    J[7 * 8 + 5] = -k[9] * y[7]; J[7 * 8 + 6] = k[11]; J[7 * 8 + 7] = -k[9] * y[5];
+    return 0;
+  }
+  case ORC_POLLU:
+    /* J = S dr/dy: reaction j contributes S[:, j] times the gradient of
+     * r_j, which has one or two non-zeros */
+    memset(J, 0, 400 * sizeof(double));
+    for (int j = 0; j < 25; j++) {
+      int a = POLLU_A[j], b = POLLU_B[j];
+      double da = b >= 0 ? p[j] * u[b] : p[j]; /* d r_j / d y_a */
+      double db = b >= 0 ? p[j] * u[a] : 0.0;  /* d r_j / d y_b */
+      for (int e = 0; e < 6 && POLLU_S[j][e][1] != 0; e++) {
+        int i = POLLU_S[j][e][0];
+        double c = POLLU_S[j][e][1];
+        J[i * 20 + a] += c * da;
+        if (b >= 0) J[i * 20 + b] += c * db;
+      }
+    }
     return 0;
   }
   return -1;
@@ -529,7 +656,7 @@ int orc_solve_mode(int sys, int alg, int64_t N, const double *params,
   if (nthreads < 1) nthreads = 1;
 #pragma omp parallel for num_threads(nthreads) schedule(dynamic, 16)
   for (int64_t i = 0; i < N; i++) {
-    double p[16], uu[NMAX], col[64 * NMAX];
+    double p[MMAX], uu[NMAX], col[64 * NMAX];
     for (int r = 0; r < m; r++) p[r] = params[r * N + i];
     for (int c = 0; c < n; c++) uu[c] = u0[c * N + i];
     int st;

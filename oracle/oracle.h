@@ -25,7 +25,13 @@ enum {
   ORC_LINEAR = 0,    /* du/dt = A u, n = 3, p = A row-major (m = 9)              */
   ORC_LORENZ = 1,    /* appendix, Lorenz problem: p = (sigma, rho, beta), n = 3   */
   ORC_ROBERTSON = 2, /* appendix, Robertson equation: p = (k1, k2, k3), n = 3     */
-  ORC_GBM4 = 3       /* appendix, linear SDE with 4 components: p = (mu, sigma)   */
+  ORC_GBM4 = 3,      /* appendix, linear SDE with 4 components: p = (mu, sigma)   */
+  ORC_OREGO = 4,     /* appendix B.1 (OREGO), Oregonator: p = (k1, k2, k3), n = 3;
+                        dy1 = k1 (y2 + y1 (1 - k2 y1 - y2)) -- the textbook
+                        (Field-Noyes) sign: the leading minus printed in the
+                        paper makes the solution from y = (1, 2, 3) blow up   */
+  ORC_HIRES = 5,     /* appendix B.1 (HIRES), n = 8, p = 12 distinct rate constants   */
+  ORC_POLLU = 6      /* appendix B.1 (POLLU), n = 20, p = (k1 .. k25)                 */
 };
 enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3 };
 enum { ORC_OK = 0, ORC_MAXITERS = 1, ORC_DTMIN = 2, ORC_NONFINITE = 3 };

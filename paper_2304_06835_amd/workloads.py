@@ -21,6 +21,17 @@ Workloads (the paper's models, appendix, with per-trajectory draws):
   surrogate     (rho, u0) draws from lorenz_fp32's distribution: training set
                 2^20 (seed 5), validation 2^16 (seed 6), queries 2^24 (seed 7),
                 audit sample seed 8.
+  orego, hires, pollu
+                the stiff test problems of appendix B.1 at the paper's 8192
+                trajectories: OREGO's and POLLU's rate constants each scaled
+                by its own exp(U[ln 0.5, ln 2]) per trajectory; HIRES's by one
+                common factor exp(U[ln 0.5, ln 2]) per trajectory (its printed
+                constants are tied sums of one another -- 10.03 = 8.32 + 1.71
+                and the like -- and scaling them apart makes the solution grow
+                without bound; a common factor c is a change of time scale,
+                y(t; c k) = y(c t; k)); the printed initial state and time
+                span, saves at 1/4, 1/2, 3/4 and 1 of the span, rtol=1e-6
+                atol=1e-8, starting-step heuristic; seeds 9, 10, 11.
 """
 from __future__ import annotations
 
@@ -29,16 +40,31 @@ from dataclasses import dataclass, field
 import numpy as np
 
 SEEDS = {"lorenz_fp64": 1, "lorenz_fp32": 2, "robertson": 3, "gbm": 4,
-         "surr_train": 5, "surr_val": 6, "surr_query": 7, "surr_audit": 8}
+         "surr_train": 5, "surr_val": 6, "surr_query": 7, "surr_audit": 8,
+         "orego": 9, "hires": 10, "pollu": 11}
 
 FULL_N = {"lorenz_fp64": 8192, "lorenz_fp32": 1 << 24, "robertson": 1 << 20,
-          "gbm": 1 << 22}
+          "gbm": 1 << 22, "orego": 8192, "hires": 8192, "pollu": 8192}
+
+# The stiff test problems of appendix B.1: printed rate constants, initial
+# state and final time.  HIRES lists its 12 distinct constants (each stands
+# for every occurrence of its value in the equations); POLLU k1..k25.
+STIFF = {
+    "orego": ([77.27, 8.375e-6, 0.161], [1.0, 2.0, 3.0], 30.0),
+    "hires": ([1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280.0, 0.69, 1.81],
+              [1.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0057], 321.8122),
+    "pollu": ([0.35, 26.6, 12300.0, 0.00086, 0.00082, 15000.0, 0.00013, 24000.0, 16500.0,
+               9000.0, 0.022, 12000.0, 1.88, 16300.0, 4.8e6, 0.00035, 0.0175, 1.0e8, 4.44e11,
+               1240.0, 2.1, 5.78, 0.0474, 1780.0, 3.12],
+              [0.0, 0.2, 0.0, 0.04, 0.0, 0.0, 0.1, 0.3, 0.017, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0,
+               0.007, 0.0, 0.0, 0.0], 60.0),
+}
 
 
 @dataclass
 class Ensemble:
     name: str
-    system: str            # "lorenz" | "robertson" | "gbm4" | "linear"
+    system: str            # "lorenz" | "robertson" | "gbm4" | "linear" | "orego" | ...
     alg: str               # "tsit5" | "rodas4" | "ros23" | "em"
     params: np.ndarray     # [m][N]
     u0: np.ndarray         # [n][N]
@@ -112,6 +138,21 @@ def gbm(N: int = FULL_N["gbm"], seed: int = SEEDS["gbm"]):
     tspan = _rows(np.zeros(N), np.ones(N), dtype=np.float64)
     return Ensemble("gbm", "gbm4", "em", params, u0, tspan, np.array([1.0]),
                     dt=1.0 / 256.0, n_steps=256, seed=seed)
+
+
+def stiff(name: str, N: int = 0, seed: int = 0, dtype=np.float32, alg: str = "rodas4"):
+    """One of the appendix-B.1 stiff problems (orego, hires, pollu) as an
+    ensemble: per-trajectory rate constants k * exp(U[ln 0.5, ln 2]), one
+    factor per constant (OREGO, POLLU) or one per trajectory (HIRES)."""
+    k, y0, tf = STIFF[name]
+    N = N or FULL_N[name]
+    rng = np.random.Generator(np.random.PCG64(seed or SEEDS[name]))
+    scale = np.exp(rng.uniform(np.log(0.5), np.log(2.0), (1 if name == "hires" else len(k), N)))
+    params = np.ascontiguousarray(np.array(k)[:, None] * scale, dtype=dtype)
+    u0 = np.ascontiguousarray(np.repeat(np.array(y0)[:, None], N, axis=1), dtype=dtype)
+    tspan = _rows(np.zeros(N), np.full(N, tf), dtype=np.float64)
+    return Ensemble(name, name, alg, params, u0, tspan, np.array([0.25, 0.5, 0.75, 1.0]),
+                    abstol=1e-8, reltol=1e-6)
 
 
 def sample_indices(N: int, k: int) -> np.ndarray:
