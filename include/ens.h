@@ -58,11 +58,25 @@ typedef struct ens_ctx ens_ctx;
  *                                                         appendix, Robertson
  * ENS_SYS_GBM4            4  2   (mu, sigma): dX_c = mu X_c dt + sigma X_c dW_c
  *                                                         appendix, linear SDE
+ * ENS_SYS_OREGO           3  3   (k1, k2, k3): dy1 = k1 (y2 + y1 (1 - k2 y1 - y2)),
+ *                                dy2 = (y3 - (1 + y1) y2) / k1, dy3 = k3 (y1 - y3)
+ *                                (textbook sign of dy1)    appendix B.1, OREGO
+ * ENS_SYS_HIRES           8  12  the distinct rate constants (1.71, 0.43, 8.32,
+ *                                0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280,
+ *                                0.69, 1.81), each for every occurrence of
+ *                                its value                 appendix B.1, HIRES
+ * ENS_SYS_POLLU           20 25  (k1 .. k25); one trajectory per 32-lane group
+ *                                (plain form only: ENS_OPT_FORM, ENS_OPT_TPL
+ *                                and ENS_OPT_GRID are ignored; block 64, 128
+ *                                or 256 holds 2, 4 or 8)   appendix B.1, POLLU
  */
 #define ENS_SYS_LINEAR 0
 #define ENS_SYS_LORENZ 1
 #define ENS_SYS_ROBERTSON 2
 #define ENS_SYS_GBM4 3
+#define ENS_SYS_OREGO 4
+#define ENS_SYS_HIRES 5
+#define ENS_SYS_POLLU 6
 
 /* ---- algorithms -------------------------------------------------------- */
 #define ENS_ALG_TSIT5 1  /* adaptive Tsitouras 5(4), PI control   sec. 3.1, 5.2.1 */
@@ -161,7 +175,8 @@ int ens_system_dims(int system_id, int *n, int *m);
  *              or [2] with ENS_OPT_TSPAN_BROADCAST = 1
  *   alg        ENS_ALG_*; (system, alg) must be one of
  *              {LINEAR, LORENZ} x TSIT5,
- *              {LINEAR, LORENZ, ROBERTSON} x {RODAS4, ROS23}, GBM4 x EM
+ *              {LINEAR, LORENZ, ROBERTSON, OREGO, HIRES, POLLU} x {RODAS4,
+ *              ROS23}, GBM4 x EM
  *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM)
  *   save_times HOST, [n_save] fractions theta_j, 0 < theta_0 < ... <= 1; save
  *              j of trajectory i is at t0_i + theta_j (tf_i - t0_i).  Adaptive

@@ -57,7 +57,8 @@ bool supported(int sys, int alg) {
     case ENS_ALG_TSIT5: return sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR;
     case ENS_ALG_RODAS4:
     case ENS_ALG_ROS23:
-      return sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR;
+      return sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR ||
+             sys == ENS_SYS_OREGO || sys == ENS_SYS_HIRES || sys == ENS_SYS_POLLU;
     case ENS_ALG_EM: return sys == ENS_SYS_GBM4;
   }
   return false;
@@ -145,6 +146,10 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
                       const ens::LaunchCfg& cfg0, hipStream_t s) {
   ens::LaunchCfg cfg = cfg0;
   hipError_t e;
+  if (sys == ENS_SYS_POLLU) {  // grouped system: plain form only, at most 8 groups a block
+    cfg.form = 0;
+    if (cfg.block > ens::kMaxBlock) cfg.block = ens::kMaxBlock;
+  }
   if (alg != ENS_ALG_EM) {
     // blocks of 512 or 1024 threads exist only for the sorted form, which
     // needs a power of two of at least 256
@@ -199,6 +204,9 @@ int ens_system_dims(int system_id, int* n, int* m) {
     case ENS_SYS_LORENZ: nn = 3; mm = 3; break;
     case ENS_SYS_ROBERTSON: nn = 3; mm = 3; break;
     case ENS_SYS_GBM4: nn = 4; mm = 2; break;
+    case ENS_SYS_OREGO: nn = 3; mm = 3; break;
+    case ENS_SYS_HIRES: nn = 8; mm = 12; break;
+    case ENS_SYS_POLLU: nn = 20; mm = 25; break;
     default: return ENS_EINVAL;
   }
   if (n) *n = nn;

@@ -12,6 +12,7 @@
 // its LU factorisation with partial pivoting (select-based, no branches) and
 // the six triangular solves run in FP64 -- the per-system block-diagonal LU
 // of section 5.1.3 (eq. 16), held in registers.
+#include "pollu.h"
 #include "rosenbrock.h"
 #include "systems.h"
 
@@ -45,17 +46,8 @@ struct Rodas4 {
                                      R*) {
     constexpr int N = S::N;
     // W = I/(gamma h) - J, factored in FP64
-    LU<N> W;
-    {
-      double J[N * N];
-      S::jac(p, u, J);
-      const double d = recip(kGamma * (double)he);
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < N; ++c) W.a[r][c] = (r == c ? d : 0.0) - J[r * N + c];
-    }
-    W.factor();
+    typename WOf<S>::type W;
+    W.build(p, u, recip(kGamma * (double)he), 1.0);
 
     const R inv_h = (R)1 / he;
     with_pivoting(W, [&](auto piv) {
@@ -100,6 +92,9 @@ hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, 
     case ENS_SYS_ROBERTSON: return ros_launch_prec<Robertson, Rodas4>(prec, cfg, a, s);
     case ENS_SYS_LORENZ: return ros_launch_prec<Lorenz, Rodas4>(prec, cfg, a, s);
     case ENS_SYS_LINEAR: return ros_launch_prec<Linear, Rodas4>(prec, cfg, a, s);
+    case ENS_SYS_OREGO: return ros_launch_prec<Orego, Rodas4>(prec, cfg, a, s);
+    case ENS_SYS_HIRES: return ros_launch_prec<Hires, Rodas4>(prec, cfg, a, s);
+    case ENS_SYS_POLLU: return ros_launch_grouped<Pollu, Rodas4>(prec, cfg, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -108,6 +103,8 @@ int rodas4_blocks_per_cu(int sys, int prec, int block) {
   switch (sys) {
     case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Rodas4>(prec, block);
     case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Rodas4>(prec, block);
+    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Rodas4>(prec, block);
+    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Rodas4>(prec, block);
     default: return ros_occ_prec<Linear, Rodas4>(prec, block);
   }
 }

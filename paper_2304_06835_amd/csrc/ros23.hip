@@ -15,6 +15,7 @@
 // its LU (partial pivoting, select-based), the three solves, the stage
 // vectors k_i and the error combination run in FP64 (k1 - 2 k2 + k3 cancels
 // to O(h^2) of |k|, which FP32 stage vectors would swamp at tight rtol).
+#include "pollu.h"
 #include "rosenbrock.h"
 #include "systems.h"
 
@@ -33,17 +34,8 @@ struct Ros23 {
                                      R* fnew) {
     constexpr int N = S::N;
     const double hd = (double)he;
-    LU<N> W;
-    {
-      double J[N * N];
-      S::jac(p, u, J);
-      const double hdd = hd * kD;
-#pragma unroll
-      for (int r = 0; r < N; ++r)
-#pragma unroll
-        for (int c = 0; c < N; ++c) W.a[r][c] = (r == c ? 1.0 : 0.0) - hdd * J[r * N + c];
-    }
-    W.factor();
+    typename WOf<S>::type W;  // I - h d J
+    W.build(p, u, 1.0, hd * kD);
 
     with_pivoting(W, [&](auto piv) {
       constexpr bool P = decltype(piv)::value;
@@ -84,6 +76,9 @@ hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, h
     case ENS_SYS_ROBERTSON: return ros_launch_prec<Robertson, Ros23>(prec, cfg, a, s);
     case ENS_SYS_LORENZ: return ros_launch_prec<Lorenz, Ros23>(prec, cfg, a, s);
     case ENS_SYS_LINEAR: return ros_launch_prec<Linear, Ros23>(prec, cfg, a, s);
+    case ENS_SYS_OREGO: return ros_launch_prec<Orego, Ros23>(prec, cfg, a, s);
+    case ENS_SYS_HIRES: return ros_launch_prec<Hires, Ros23>(prec, cfg, a, s);
+    case ENS_SYS_POLLU: return ros_launch_grouped<Pollu, Ros23>(prec, cfg, a, s);
   }
   return hipErrorInvalidValue;
 }
@@ -92,6 +87,8 @@ int ros23_blocks_per_cu(int sys, int prec, int block) {
   switch (sys) {
     case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Ros23>(prec, block);
     case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Ros23>(prec, block);
+    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Ros23>(prec, block);
+    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Ros23>(prec, block);
     default: return ros_occ_prec<Linear, Ros23>(prec, block);
   }
 }

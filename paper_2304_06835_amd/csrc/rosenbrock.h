@@ -39,8 +39,8 @@ __device__ inline double recip(double x) {
 // the two when row r has the larger entry, so row k ends up holding the
 // largest.  The swaps are selects (no per-lane branches) recorded in `swp`
 // for solve() to replay on the right-hand side.  A swap no lane of the wave
-// makes is skipped as a whole (wave-uniform branch on a ballot; `any` keeps
-// one bit per swap made), and when no lane swapped at all the solves take
+// makes is skipped as a whole (wave-uniform branch on a ballot), and when no
+// lane swapped at all (`any` false) the solves take
 // their swap-free form -- for the column-diagonally-dominant W of many
 // stiff systems (Robertson's among them) that is every factorisation.
 template <int N>
@@ -48,11 +48,10 @@ struct LU {
   double a[N][N];
   double inv_piv[N];
   bool swp[N][N];
-  uint32_t any;
+  bool any;  // some lane of the wave swapped rows (wave-uniform)
 
   __device__ inline void factor() {
-    static_assert(N * N <= 32, "swap mask holds N*N bits");
-    any = 0;
+    any = false;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
 #pragma unroll
@@ -60,7 +59,7 @@ struct LU {
         const bool s = fabs(a[r][k]) > fabs(a[k][k]);
         swp[k][r] = s;
         if (__ballot(s) != 0ull) {
-          any |= 1u << (k * N + r);
+          any = true;
 #pragma unroll
           for (int c = 0; c < N; ++c) {
             const double x = a[k][c], y = a[r][c];
@@ -108,16 +107,80 @@ struct LU {
   }
 };
 
+// W = alpha I - beta J of a system held whole by each lane: analytic FP64
+// Jacobian, LU in registers.  Methods build it through this interface
+// (build, then solve<Pivoted>), so a system can substitute its own
+// (cooperative) matrix type with WOf.
+template <class S>
+struct LaneW {
+  static constexpr int N = S::N;
+  LU<N> lu;
+  template <class R>
+  __device__ inline void build(const R* p, const R* u, double alpha, double beta) {
+    double J[N * N];
+    S::jac(p, u, J);
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int c = 0; c < N; ++c) lu.a[r][c] = (r == c ? alpha : 0.0) - beta * J[r * N + c];
+    lu.factor();
+  }
+  __device__ inline bool pivoted() const { return lu.any; }
+  template <bool Pivoted>
+  __device__ inline void solve(double* x) const {
+    lu.template solve<Pivoted>(x);
+  }
+};
+
+// The matrix type a method builds for system S (LaneW unless S names one).
+template <class S, class = void>
+struct WOf {
+  using type = LaneW<S>;
+};
+template <class S>
+struct WOf<S, std::void_t<typename S::Matrix>> {
+  using type = typename S::Matrix;
+};
+
 // Runs body(std::true_type) when some lane of the wave pivoted, else
 // body(std::false_type) -- a wave-uniform choice between two copies of a
 // method's stage code, with and without the row swaps in its solves.
-template <int N, class Body>
-__device__ inline void with_pivoting(const LU<N>& W, Body&& body) {
-  if (W.any)
+template <class WT, class Body>
+__device__ inline void with_pivoting(const WT& W, Body&& body) {
+  if (W.pivoted())
     body(std::true_type{});
   else
     body(std::false_type{});
 }
+
+// How a lane sees its system.  By default a lane holds a whole trajectory
+// (all N components).  A grouped system (kGrouped) spreads one trajectory
+// over a group of lanes, one component per lane (comp() of them, kDim real
+// components, the rest padding): its sums over components are group
+// reductions, each lane stores its own component, and one lane of the group
+// writes status and counters.
+template <class S, class = void>
+struct View {
+  static constexpr int kDim = S::N;
+  template <class R>
+  using Input = LaneInput<R, S::M, S::N>;
+  __device__ static inline int comp() { return 0; }
+  __device__ static inline bool writes() { return true; }
+  __device__ static inline bool leader() { return true; }
+  template <class T>
+  __device__ static inline T sum(T x) { return x; }
+};
+template <class S>
+struct View<S, std::enable_if_t<S::kGrouped>> {
+  static constexpr int kDim = S::kDim;
+  template <class R>
+  using Input = typename S::template Input<R>;
+  __device__ static inline int comp() { return S::comp(); }
+  __device__ static inline bool writes() { return S::comp() < S::kDim; }
+  __device__ static inline bool leader() { return S::comp() == 0; }
+  template <class T>
+  __device__ static inline T sum(T x) { return S::sum(x); }
+};
 
 // PI control (section 3.1, eq. 4) with Hairer & Wanner's constants.
 constexpr double kRosEta = 0.9, kRosFacMin = 0.2, kRosFacMax = 10.0;
@@ -126,7 +189,8 @@ constexpr double kLog2QFloor = -13.287712379549449;  // log2(1e-4)
 template <class R, class S, class M>
 struct RosLane {
   static constexpr int N = S::N, NP = S::M;
-  using Input = LaneInput<R, NP, N>;
+  using V = View<S>;
+  using Input = typename V::template Input<R>;
   R p[NP], u[N];
   R f0[M::kFsal ? N : 1];  // f(u), carried from step to step by FSAL methods
   CompTime t;
@@ -140,13 +204,15 @@ struct RosLane {
   int j, nacc, nrej, status;
   bool done;
 
-  // Store u at every save time reached; sp walks the [n_save][N][stride]
+  // Store u at every save time reached; sp walks the [n_save][n][stride]
   // output one save at a time, so a save costs N stores and an add.
   __device__ inline void save_reached(const LaunchArgs& a) {
     while (j < a.n_save && ts <= t.hi + t.lo) {
+      if (V::writes()) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
-      sp += N * a.out_stride;
+        for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
+      }
+      sp += V::kDim * a.out_stride;
       ++j;
       if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
@@ -167,8 +233,8 @@ struct RosLane {
       d0 += (uu[c] / sc[c]) * (uu[c] / sc[c]);
       d1 += (f0d[c] / sc[c]) * (f0d[c] / sc[c]);
     }
-    d0 = ::sqrt(d0 / N);
-    d1 = ::sqrt(d1 / N);
+    d0 = ::sqrt(V::sum(d0) / V::kDim);
+    d1 = ::sqrt(V::sum(d1) / V::kDim);
     double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     h0 = fmin(h0, hmax);
     R yr[N];
@@ -185,7 +251,7 @@ struct RosLane {
       const double z = (f1[c] - f0d[c]) / sc[c];
       d2 += z * z;
     }
-    d2 = ::sqrt(d2 / N) / h0;
+    d2 = ::sqrt(V::sum(d2) / V::kDim) / h0;
     const double dm = fmax(d1, d2);
     const double h1 =
         (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : ::exp2(::log2(0.01 / dm) / (M::kP + 1.0));
@@ -193,7 +259,8 @@ struct RosLane {
   }
 
   __device__ inline void init(const LaunchArgs& a, int64_t k, const Input& in) {
-    sp = static_cast<R*>(a.out) + out_col(a, k, in.i);
+    sp = static_cast<R*>(a.out) + out_col(a, k, in.i) +
+         (V::writes() ? (int64_t)V::comp() * a.out_stride : 0);
 #pragma unroll
     for (int r = 0; r < NP; ++r) p[r] = in.p[r];
 #pragma unroll
@@ -245,7 +312,7 @@ struct RosLane {
       const R r = err[c] * F::rcp(sc);
       q2 = fma(r, r, q2);
     }
-    q2 = q2 * (R)(1.0 / N);
+    q2 = V::sum(q2) * (R)(1.0 / V::kDim);
     if (!(q2 <= (R)3.0e38)) {
       status = ENS_ST_NONFINITE;
       done = true;
@@ -287,9 +354,11 @@ struct RosLane {
   }
 
   __device__ inline void finish(const LaunchArgs& a, int64_t k) {
-    for (int jj = j; jj < a.n_save; ++jj, sp += N * a.out_stride)
+    if (V::writes())
+      for (int jj = j; jj < a.n_save; ++jj, sp += V::kDim * a.out_stride)
 #pragma unroll
-      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = Num<R>::nan();
+        for (int c = 0; c < N; ++c) sp[c * a.out_stride] = Num<R>::nan();
+    if (!V::leader()) return;
     if (a.status) a.status[k] = (uint8_t)status;
     if (a.stats) {
       a.stats[k] = nacc;
