@@ -83,7 +83,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lorenz_fp32",
-                    choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm"])
+                    choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm", "orego", "hires",
+                             "pollu"])
     ap.add_argument("--n", type=int, default=0, help="override the ensemble size")
     ap.add_argument("--alg", default="", choices=["", "rodas4", "ros23"],
                     help="stiff method of the Robertson workload (default rodas4)")
@@ -125,6 +126,8 @@ def copy_calibration():
 
 def make_workload(name, n, alg=""):
     from paper_2304_06835_amd import workloads as W
+    if name in W.STIFF:
+        return W.stiff(name, N=n, alg=alg or "rodas4")
     f = {"lorenz_fp32": W.lorenz_fp32, "lorenz_fp64": W.lorenz_fp64,
          "robertson": W.robertson, "gbm": W.gbm}[name]
     kw = {"alg": alg} if (alg and name == "robertson") else {}
@@ -137,6 +140,10 @@ def describe(e):
                 "compensated time, Tsit5 rtol=atol=1e-6, 16 saves on [0,1]")
     if e.name == "lorenz_fp64":
         return "Lorenz 8192-ensemble, rho~U[0,21], FP64, Tsit5 rtol=atol=1e-8, final state"
+    if e.name in ("orego", "hires", "pollu"):
+        return (f"{e.name.upper()} 8192-ensemble (appendix B.1), rate constants x logU[0.5,2], "
+                f"{'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 atol=1e-8, "
+                "4 saves")
     if e.name == "robertson":
         return ("Robertson 2^20-ensemble, rates x logU[0.5,2], tf~logU[1,1e5], FP32 state + "
                 f"FP64 W/LU, {'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 "
@@ -245,7 +252,8 @@ def cpu_baseline(e, gpu_out, seconds):
     import oracle
     from paper_2304_06835_amd import workloads as W
     nth = oracle.default_threads()
-    sysid = {"lorenz": oracle.LORENZ, "robertson": oracle.ROBERTSON}.get(e.system)
+    sysid = {"lorenz": oracle.LORENZ, "robertson": oracle.ROBERTSON, "orego": oracle.OREGO,
+             "hires": oracle.HIRES, "pollu": oracle.POLLU}.get(e.system)
 
     def sub(idx):
         return (np.ascontiguousarray(e.params[:, idx]), np.ascontiguousarray(e.u0[:, idx]),
@@ -255,7 +263,9 @@ def cpu_baseline(e, gpu_out, seconds):
         p, u, ts = sub(idx)
         if e.alg == "em":
             return oracle.em(p, u, e.dt, e.n_steps, e.seed, ids=idx, nthreads=nth)[None]
-        alg = oracle.TSIT5 if e.alg == "tsit5" else oracle.RODAS4
+        alg = {"tsit5": oracle.TSIT5, "rodas4": oracle.RODAS4, "ros23": oracle.ROS23}[e.alg]
+        if tol is not None and alg == oracle.ROS23:  # the truth comes from the 4th-order method
+            alg = oracle.RODAS4
         at = e.abstol if tol is None else tol
         rt = e.reltol if tol is None else tol
         return oracle.solve(sysid, alg, p, u, ts, at, rt, e.theta, h0=e.h0, nthreads=nth)[0]
@@ -341,6 +351,46 @@ def stiff_ros23_variant(rob, steps, rodas4_forms):
             "attempts_per_traj_max": int(st.max()), "achieved_tflops": fl,
             "frac_of_fp32_peak": fl / PEAK[32], "speedup_vs_fastest_rodas4": r4 / ms,
             "max_rel_err_vs_truth_4096": float(err.max())}
+
+
+def stiff_variant(steps):
+    """The stiff test problems of appendix B.1 at the paper's 8192
+    trajectories: Rodas4 and Rosenbrock23 in FP32 and FP64 (fastest of the
+    plain and sorted forms for the one-lane-per-trajectory OREGO and HIRES;
+    POLLU runs one trajectory per 32-lane group), against the FP64 oracle
+    solving all 8192 on the host cores with the same method and tolerance."""
+    import numpy as np
+
+    import oracle
+    from paper_2304_06835_amd import workloads as W
+    res = {}
+    for name in ("orego", "hires", "pollu"):
+        for alg in ("rodas4", "ros23"):
+            e = W.stiff(name, alg=alg)
+            sid = {"orego": oracle.OREGO, "hires": oracle.HIRES, "pollu": oracle.POLLU}[name]
+            oalg = oracle.RODAS4 if alg == "rodas4" else oracle.ROS23
+            t0 = time.perf_counter()
+            oracle.solve(sid, oalg, e.params, e.u0, e.tspan, e.abstol, e.reltol, e.theta)
+            cpu_s = time.perf_counter() - t0
+            row = {"cpu_oracle_ms": cpu_s * 1e3, "cpu_cores": oracle.default_threads()}
+            for prec in (32, 64):
+                ep = e if prec == 32 else W.stiff(name, alg=alg, dtype=np.float64)
+                forms = {"plain": {"form": 0}} if name == "pollu" else {
+                    "plain": {"form": 0}, "sorted": {"form": 2, "block": 256}}
+                best = None
+                for fname, opts in forms.items():
+                    r = Runner(ep, prec, **opts)
+                    _, ms, _ = r.time(max(3, steps // 3), 1)
+                    if best is None or ms < best[1]:
+                        attempts, _ = r.attempts()
+                        best = (fname, ms, attempts)
+                    del r
+                fname, ms, attempts = best
+                row[f"fp{prec}"] = {"form": fname, "kernel_ms": ms, "traj_per_s": e.n / (ms * 1e-3),
+                                    "attempts_per_traj": attempts / e.n,
+                                    "speedup_vs_cpu_oracle": cpu_s * 1e3 / ms}
+            res[f"{name}_{alg}"] = row
+    return res
 
 
 def config_variant(name, precision, steps):
@@ -489,13 +539,13 @@ def main():
     out_host = r.host_out()
     value = e.n * args.steps / wall
     ms_per_step = wall / args.steps * 1e3
-    fpa = FLOPS[(e.alg, e.system)]
+    fpa = FLOPS.get((e.alg, e.system))  # not counted for the appendix-B.1 problems
     dense_saves = e.n * (len(e.theta) - 1) if save == "dense" else 0
-    flops = fpa * attempts + DENSE_FLOPS_PER_SAVE * dense_saves
+    flops = fpa * attempts + DENSE_FLOPS_PER_SAVE * dense_saves if fpa else None
     peak = PEAK[precision]
-    achieved = flops / (ker_ms * 1e-3) / 1e12
+    achieved = flops / (ker_ms * 1e-3) / 1e12 if flops else None
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak,
+            "frac": achieved / peak if achieved else None,
             "traffic": recorded_traffic(e.name, form + ("/dense" if save == "dense" else ""), 1),
             "kernel": {"tsit5": "tsit5", "rodas4": "ros", "ros23": "ros", "em": "em_gbm4"}[e.alg]
                       + {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
@@ -548,6 +598,7 @@ def main():
             variants["robertson_2p20_ros23"] = stiff_ros23_variant(rob, args.steps, rv)
             variants["lorenz_fp64_8192"] = config_variant("lorenz_fp64", 64, args.steps)
             variants["gbm_em_2p22"] = config_variant("gbm", 32, args.steps)
+            variants["stiff_appendix_b1_8192"] = stiff_variant(args.steps)
             if not args.no_surrogate:
                 variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms)
 
