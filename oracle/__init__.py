@@ -18,10 +18,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-LINEAR, LORENZ, ROBERTSON, GBM4, OREGO, HIRES, POLLU = 0, 1, 2, 3, 4, 5, 6
-TSIT5, RODAS4, ROS23 = 1, 2, 3
+LINEAR, LORENZ, ROBERTSON, GBM4, OREGO, HIRES, POLLU, CRN = 0, 1, 2, 3, 4, 5, 6, 7
+TSIT5, RODAS4, ROS23, EM, SIEA = 1, 2, 3, 4, 5
 DIMS = {LINEAR: (3, 9), LORENZ: (3, 3), ROBERTSON: (3, 3), GBM4: (4, 2), OREGO: (3, 3),
-        HIRES: (8, 12), POLLU: (20, 25)}
+        HIRES: (8, 12), POLLU: (20, 25), CRN: (4, 6)}
+NOISES = {GBM4: 4, CRN: 8}
 
 
 def build(verbose: bool = False) -> str:
@@ -70,6 +71,10 @@ def lib():
         L.orc_box_muller.restype = None
         L.orc_em.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, ctypes.c_double,
                              ctypes.c_int, ctypes.c_uint64, i64p, dp, ctypes.c_int]
+        L.orc_sde.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, dp, dp,
+                              ctypes.c_double, ctypes.c_int, ctypes.c_uint64, i64p, dp,
+                              ctypes.c_int]
+        L.orc_sde_step.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double, dp, dp]
         L.orc_tsit5_tableau.argtypes = [dp, dp, dp, dp]
         L.orc_tsit5_tableau.restype = None
         L.orc_rodas4_tableau.argtypes = [dp, dp, dp, dp, dp]
@@ -200,6 +205,37 @@ def em(params, u0, dt, n_steps, seed, ids=None, nthreads=None):
                       nthreads or default_threads())
     if rc != 0:
         raise ValueError("orc_em rejected its arguments")
+    return out
+
+
+def sde(system, alg, params, u0, dt, n_steps, seed, ids=None, nthreads=None):
+    """Fixed-step SDE ensemble (EM for GBM4 and CRN, SIEA for GBM4); returns
+    the final state [n][N].  ids: Philox trajectory ids of the columns."""
+    params, u0 = _f64(params), _f64(u0)
+    n, m = DIMS[system]
+    N = u0.shape[1]
+    assert params.shape == (m, N) and u0.shape == (n, N)
+    out = np.empty((n, N))
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        assert ids.shape == (N,)
+        idp = _p(ids, ctypes.c_int64)
+    rc = lib().orc_sde(system, alg, N, _p(params), _p(u0), dt, n_steps, seed, idp, _p(out),
+                       nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("orc_sde rejected its arguments")
+    return out
+
+
+def sde_step(system, alg, p, x, h, dW):
+    """One SDE step of size h from x with Wiener increments dW."""
+    n, _ = DIMS[system]
+    p, x, dW = _f64(p), _f64(x), _f64(dW)
+    assert dW.shape == (NOISES[system],)
+    out = np.empty(n)
+    if lib().orc_sde_step(system, alg, _p(p), _p(x), h, _p(dW), _p(out)) != 0:
+        raise ValueError("orc_sde_step rejected its arguments")
     return out
 
 

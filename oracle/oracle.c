@@ -16,7 +16,8 @@
  *     stable variant (GPURodas4) and the 2(3) pair (GPURosenbrock23):
  *     section 5.2.1; LU of W per system: section 5.1.3, eq. 16.
  *   - SDE definition dX = a dt + b dW, dW ~ N(0, dt): section 3.3, eq. 11;
- *     Euler-Maruyama (GPUEM): section 5.2.2.
+ *     Euler-Maruyama (GPUEM) and a weak order-2 scheme (GPUSIEA): section
+ *     5.2.2; the sigma-factor CRN SDE: appendix.
  *   - Models: appendix (Lorenz, Robertson, linear SDE); stiff test problems
  *     OREGO, HIRES and POLLU of appendix B.1.
  */
@@ -43,6 +44,7 @@ int orc_dims(int sys, int *n, int *m) {
   case ORC_OREGO: *n = 3; *m = 3; return 0;
   case ORC_HIRES: *n = 8; *m = 12; return 0;
   case ORC_POLLU: *n = 20; *m = 25; return 0;
+  case ORC_CRN: *n = 4; *m = 6; return 0;
   }
   return -1;
 }
@@ -774,32 +776,161 @@ void orc_box_muller(uint32_t x0, uint32_t x1, double *z0, double *z1) {
   *z1 = r * sin(two_pi * v);
 }
 
-int orc_em(int sys, int64_t N, const double *params, const double *u0,
-           double dt, int n_steps, uint64_t seed, const int64_t *ids,
-           double *out, int nthreads) {
-  if (sys != ORC_GBM4 || N < 0 || n_steps < 0 || !(dt > 0.0)) return -1;
+/* ------------------------------------------------------------------------ */
+/* SDEs (section 3.3, eq. 11): drift a(X) and noise matrix b(X) [n][m]       */
+/* ------------------------------------------------------------------------ */
+
+static int sde_dims(int sys, int *n, int *m) {
+  switch (sys) {
+  case ORC_GBM4: *n = 4; *m = 4; return 0;
+  case ORC_CRN: *n = 4; *m = 8; return 0;
+  }
+  return -1;
+}
+
+/* Appendix, linear SDE: four GBMs dX_c = mu X_c dt + sigma X_c dW_c.
+ * Appendix, sigma-factor CRN (chemical Langevin equation), X = (s, A1, A2,
+ * A3), p = (S, D, tau, nu0, n, eta), with the Hill input
+ * H = (S s)^n / ((S s)^n + (D A3)^n + 1):
+ *   ds  = (nu0 + H - s) dt + eta sqrt(nu0 + H) dW1 - eta sqrt(s) dW2
+ *   dA1 = (s - A1)/tau dt + eta sqrt(s/tau) dW3 - eta sqrt(A1/tau) dW4
+ *   dA2 = (A1 - A2)/tau dt + eta sqrt(A1/tau) dW5 - eta sqrt(A2/tau) dW6
+ *   dA3 = (A2 - A3)/tau dt + eta sqrt(A2/tau) dW7 - eta sqrt(A3/tau) dW8
+ * Reading (the paper is silent): a concentration that an increment drives
+ * below zero enters the Hill function and the square roots as 0.          */
+static void sde_coeffs(int sys, const double *p, const double *x, double *a,
+                       double *b /* [n][m] */) {
+  if (sys == ORC_GBM4) {
+    double mu = p[0], sigma = p[1];
+    memset(b, 0, 16 * sizeof(double));
+    for (int c = 0; c < 4; c++) {
+      a[c] = mu * x[c];
+      b[c * 4 + c] = sigma * x[c];
+    }
+    return;
+  }
+  /* ORC_CRN */
+  double S = p[0], D = p[1], tau = p[2], nu0 = p[3], n = p[4], eta = p[5];
+  double s = fmax(x[0], 0.0), a1 = fmax(x[1], 0.0), a2 = fmax(x[2], 0.0),
+         a3 = fmax(x[3], 0.0);
+  double hs = pow(S * s, n), hd = pow(D * a3, n);
+  double H = hs / (hs + hd + 1.0);
+  a[0] = nu0 + H - x[0];
+  a[1] = (x[0] - x[1]) / tau;
+  a[2] = (x[1] - x[2]) / tau;
+  a[3] = (x[2] - x[3]) / tau;
+  memset(b, 0, 32 * sizeof(double));
+  b[0 * 8 + 0] = eta * sqrt(nu0 + H);
+  b[0 * 8 + 1] = -eta * sqrt(s);
+  b[1 * 8 + 2] = eta * sqrt(s / tau);
+  b[1 * 8 + 3] = -eta * sqrt(a1 / tau);
+  b[2 * 8 + 4] = eta * sqrt(a1 / tau);
+  b[2 * 8 + 5] = -eta * sqrt(a2 / tau);
+  b[3 * 8 + 6] = eta * sqrt(a2 / tau);
+  b[3 * 8 + 7] = -eta * sqrt(a3 / tau);
+}
+
+/* The diagonal of b for a diagonal-noise system (m = n, b[c][c]). */
+static void sde_bdiag(int sys, const double *p, const double *x, double *bd) {
+  double a[8], b[64];
+  sde_coeffs(sys, p, x, a, b);
+  for (int c = 0; c < 4; c++) bd[c] = b[c * 4 + c];
+}
+
+/* Euler-Maruyama (GPUEM, section 5.2.2): X + a h + b dW. */
+static void em_step(int sys, const double *p, int n, int m, const double *x,
+                    double h, const double *dW, double *xo) {
+  double a[8], b[64];
+  sde_coeffs(sys, p, x, a, b);
+  for (int c = 0; c < n; c++) {
+    double s = x[c] + a[c] * h;
+    for (int j = 0; j < m; j++) s += b[c * m + j] * dW[j];
+    xo[c] = s;
+  }
+}
+
+/* Weak order-2 explicit scheme for diagonal noise (GPUSIEA of section
+ * 5.2.2; the paper cites Tocino & Vigo-Aguiar for it but prints no
+ * coefficients).  Reading: the explicit order-2.0 weak scheme of Kloeden &
+ * Platen (1992, eq. 15.1.1), a member of the stochastic Runge-Kutta family
+ * of section 3.3 with stages Y, Ybar = Y + a h + b dW, Y+- = Y + a h +- b
+ * sqrt(h) and fit term R = (b(Y+) - b(Y-)) (dW^2 - h) / (4 sqrt h):
+ *   Y' = Y + (a(Ybar) + a) h / 2 + (b(Y+) + b(Y-) + 2 b) dW / 4 + R,
+ * componentwise (each b_c depends on X_c alone for the diagonal systems). */
+static void siea_step(int sys, const double *p, int n, const double *x,
+                      double h, const double *dW, double *xo) {
+  double a[8], b[64], bd[8], yb[8], yp[8], ym[8], ab[8], bb[64], bp[8], bm[8];
+  sde_coeffs(sys, p, x, a, b);
+  for (int c = 0; c < n; c++) bd[c] = b[c * n + c];
+  double sq = sqrt(h);
+  for (int c = 0; c < n; c++) {
+    yb[c] = x[c] + a[c] * h + bd[c] * dW[c];
+    yp[c] = x[c] + a[c] * h + bd[c] * sq;
+    ym[c] = x[c] + a[c] * h - bd[c] * sq;
+  }
+  sde_coeffs(sys, p, yb, ab, bb);
+  sde_bdiag(sys, p, yp, bp);
+  sde_bdiag(sys, p, ym, bm);
+  for (int c = 0; c < n; c++)
+    xo[c] = x[c] + 0.5 * (ab[c] + a[c]) * h +
+            0.25 * (bp[c] + bm[c] + 2.0 * bd[c]) * dW[c] +
+            0.25 * (bp[c] - bm[c]) * (dW[c] * dW[c] - h) / sq;
+}
+
+int orc_sde_step(int sys, int alg, const double *p, const double *x, double h,
+                 const double *dW, double *xout) {
+  int n, m;
+  if (sde_dims(sys, &n, &m) != 0) return -1;
+  if (alg == ORC_EM)
+    em_step(sys, p, n, m, x, h, dW, xout);
+  else if (alg == ORC_SIEA && sys == ORC_GBM4)
+    siea_step(sys, p, n, x, h, dW, xout);
+  else
+    return -1;
+  return 0;
+}
+
+int orc_sde(int sys, int alg, int64_t N, const double *params,
+            const double *u0, double dt, int n_steps, uint64_t seed,
+            const int64_t *ids, double *out, int nthreads) {
+  int n, m, np_;
+  if (sde_dims(sys, &n, &m) != 0 || orc_dims(sys, &n, &np_) != 0) return -1;
+  if (alg != ORC_EM && !(alg == ORC_SIEA && sys == ORC_GBM4)) return -1;
+  if (N < 0 || n_steps < 0 || !(dt > 0.0)) return -1;
   if (nthreads < 1) nthreads = 1;
   const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
   const double sqdt = sqrt(dt);
 #pragma omp parallel for num_threads(nthreads) schedule(static)
   for (int64_t i = 0; i < N; i++) {
-    double mu = params[i], sigma = params[N + i];
-    double X[4];
-    for (int c = 0; c < 4; c++) X[c] = u0[c * N + i];
+    double p[8], X[8], Xn[8], dW[8];
+    for (int r = 0; r < np_; r++) p[r] = params[r * N + i];
+    for (int c = 0; c < n; c++) X[c] = u0[c * N + i];
+    uint64_t id = ids ? (uint64_t)ids[i] : (uint64_t)i;
     for (int s = 0; s < n_steps; s++) {
-      uint64_t id = ids ? (uint64_t)ids[i] : (uint64_t)i;
-      uint32_t ctr[4] = {(uint32_t)s, (uint32_t)id, (uint32_t)(id >> 32), 0u};
-      uint32_t r[4];
-      double z[4];
-      orc_philox4x32_10(ctr, key, r);
-      orc_box_muller(r[0], r[1], &z[0], &z[1]);
-      orc_box_muller(r[2], r[3], &z[2], &z[3]);
-      for (int c = 0; c < 4; c++) {
-        double dW = sqdt * z[c];
-        X[c] = X[c] + mu * X[c] * dt + sigma * X[c] * dW;
+      for (int call = 0; call * 4 < m; call++) {
+        uint32_t ctr[4] = {(uint32_t)s, (uint32_t)id, (uint32_t)(id >> 32), (uint32_t)call};
+        uint32_t r[4];
+        double z[4];
+        orc_philox4x32_10(ctr, key, r);
+        orc_box_muller(r[0], r[1], &z[0], &z[1]);
+        orc_box_muller(r[2], r[3], &z[2], &z[3]);
+        for (int q = 0; q < 4; q++) dW[4 * call + q] = sqdt * z[q];
       }
+      if (alg == ORC_EM)
+        em_step(sys, p, n, m, X, dt, dW, Xn);
+      else
+        siea_step(sys, p, n, X, dt, dW, Xn);
+      for (int c = 0; c < n; c++) X[c] = Xn[c];
     }
-    for (int c = 0; c < 4; c++) out[c * N + i] = X[c];
+    for (int c = 0; c < n; c++) out[c * N + i] = X[c];
   }
   return 0;
+}
+
+int orc_em(int sys, int64_t N, const double *params, const double *u0,
+           double dt, int n_steps, uint64_t seed, const int64_t *ids,
+           double *out, int nthreads) {
+  if (sys != ORC_GBM4) return -1;
+  return orc_sde(sys, ORC_EM, N, params, u0, dt, n_steps, seed, ids, out,
+                 nthreads);
 }

@@ -31,9 +31,11 @@ enum {
                         (Field-Noyes) sign: the leading minus printed in the
                         paper makes the solution from y = (1, 2, 3) blow up   */
   ORC_HIRES = 5,     /* appendix B.1 (HIRES), n = 8, p = 12 distinct rate constants   */
-  ORC_POLLU = 6      /* appendix B.1 (POLLU), n = 20, p = (k1 .. k25)                 */
+  ORC_POLLU = 6,     /* appendix B.1 (POLLU), n = 20, p = (k1 .. k25)                 */
+  ORC_CRN = 7        /* appendix, sigma-factor CRN SDE (chemical Langevin), n = 4,
+                        p = (S, D, tau, nu0, n, eta), 8 Wiener processes         */
 };
-enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3 };
+enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3, ORC_EM = 4, ORC_SIEA = 5 };
 enum { ORC_OK = 0, ORC_MAXITERS = 1, ORC_DTMIN = 2, ORC_NONFINITE = 3 };
 
 int orc_dims(int sys, int *n, int *m);
@@ -96,6 +98,21 @@ void orc_box_muller(uint32_t x0, uint32_t x1, double *z0, double *z1);
 int orc_em(int sys, int64_t N, const double *params, const double *u0,
            double dt, int n_steps, uint64_t seed, const int64_t *ids,
            double *out, int nthreads);
+
+/*
+ * Fixed-step SDE ensemble: alg ORC_EM (any system: ORC_GBM4, ORC_CRN) or
+ * ORC_SIEA (diagonal noise: ORC_GBM4).  The m Wiener increments of step s of
+ * trajectory id are sqrt(dt) z_j, z_0..z_3 from Philox counter
+ * (s, id_lo, id_hi, 0) and z_4..z_7 from (s, id_lo, id_hi, 1), each word
+ * pair through Box-Muller.  Arguments as orc_em.
+ */
+int orc_sde(int sys, int alg, int64_t N, const double *params,
+            const double *u0, double dt, int n_steps, uint64_t seed,
+            const int64_t *ids, double *out, int nthreads);
+
+/* One step of size h from x with the given Wiener increments dW[m]. */
+int orc_sde_step(int sys, int alg, const double *p, const double *x, double h,
+                 const double *dW, double *xout);
 
 /* Coefficient export for the order-condition tests. */
 void orc_tsit5_tableau(double c[7], double a[49], double b[7],

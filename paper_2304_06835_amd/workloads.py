@@ -32,6 +32,15 @@ Workloads (the paper's models, appendix, with per-trajectory draws):
                 y(t; c k) = y(c t; k)); the printed initial state and time
                 span, saves at 1/4, 1/2, 3/4 and 1 of the span, rtol=1e-6
                 atol=1e-8, starting-step heuristic; seeds 9, 10, 11.
+  crn           the sigma-factor CRN SDE (appendix): 10 values of each of the six
+                parameters drawn uniformly from the appendix table's ranges
+                (S, D, tau in [0.1, 100], nu0 in [0.01, 0.2], n in [2, 4], eta
+                in [0.001, 0.1] -- the table's garbled rows read as one
+                parameter each) and their Cartesian product, 10^6 trajectories;
+                u0 = (nu0, nu0, nu0, nu0), t in [0, 1000], Euler-Maruyama
+                dt = 0.1 (10^4 steps), 10 evenly spaced saves; Philox key 13;
+                seed 12.
+  gbm(alg="siea") the gbm ensemble under the weak order-2 scheme.
 """
 from __future__ import annotations
 
@@ -41,10 +50,13 @@ import numpy as np
 
 SEEDS = {"lorenz_fp64": 1, "lorenz_fp32": 2, "robertson": 3, "gbm": 4,
          "surr_train": 5, "surr_val": 6, "surr_query": 7, "surr_audit": 8,
-         "orego": 9, "hires": 10, "pollu": 11}
+         "orego": 9, "hires": 10, "pollu": 11, "crn": 12}
 
 FULL_N = {"lorenz_fp64": 8192, "lorenz_fp32": 1 << 24, "robertson": 1 << 20,
-          "gbm": 1 << 22, "orego": 8192, "hires": 8192, "pollu": 8192}
+          "gbm": 1 << 22, "orego": 8192, "hires": 8192, "pollu": 8192, "crn": 10 ** 6}
+
+# Ranges of the CRN parameters (S, D, tau, nu0, n, eta), appendix table.
+CRN_RANGES = [(0.1, 100.0), (0.1, 100.0), (0.1, 100.0), (0.01, 0.2), (2.0, 4.0), (0.001, 0.1)]
 
 # The stiff test problems of appendix B.1: printed rate constants, initial
 # state and final time.  HIRES lists its 12 distinct constants (each stands
@@ -129,14 +141,14 @@ def robertson(N: int = FULL_N["robertson"], seed: int = SEEDS["robertson"],
                     np.array([1.0]), abstol=1e-8, reltol=1e-6, h0=1e-4)
 
 
-def gbm(N: int = FULL_N["gbm"], seed: int = SEEDS["gbm"]):
+def gbm(N: int = FULL_N["gbm"], seed: int = SEEDS["gbm"], alg: str = "em"):
     rng = np.random.Generator(np.random.PCG64(seed))
     mu = rng.uniform(-0.5, 0.5, N)
     sigma = rng.uniform(0.05, 0.5, N)
     params = _rows(mu, sigma, dtype=np.float32)
     u0 = np.ones((4, N), dtype=np.float32)
     tspan = _rows(np.zeros(N), np.ones(N), dtype=np.float64)
-    return Ensemble("gbm", "gbm4", "em", params, u0, tspan, np.array([1.0]),
+    return Ensemble("gbm", "gbm4", alg, params, u0, tspan, np.array([1.0]),
                     dt=1.0 / 256.0, n_steps=256, seed=seed)
 
 
@@ -153,6 +165,24 @@ def stiff(name: str, N: int = 0, seed: int = 0, dtype=np.float32, alg: str = "ro
     tspan = _rows(np.zeros(N), np.full(N, tf), dtype=np.float64)
     return Ensemble(name, name, alg, params, u0, tspan, np.array([0.25, 0.5, 0.75, 1.0]),
                     abstol=1e-8, reltol=1e-6)
+
+
+def crn(values_per_param: int = 10, seed: int = SEEDS["crn"], t_end: float = 1000.0,
+        dt: float = 0.1, n_save: int = 10):
+    """The CRN parameter sweep: values_per_param uniform draws per parameter,
+    all combinations (values_per_param^6 trajectories, parameter 0 varying
+    slowest), u0 = nu0 in every species."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    axes = [np.sort(rng.uniform(lo, hi, values_per_param)) for lo, hi in CRN_RANGES]
+    grid = np.meshgrid(*axes, indexing="ij")
+    params = np.ascontiguousarray(np.stack([g.reshape(-1) for g in grid]), dtype=np.float32)
+    N = params.shape[1]
+    u0 = np.ascontiguousarray(np.repeat(params[3:4], 4, axis=0))
+    tspan = _rows(np.zeros(N), np.full(N, t_end), dtype=np.float64)
+    n_steps = int(round(t_end / dt))
+    theta = (np.arange(n_save, dtype=np.float64) + 1.0) / n_save
+    return Ensemble("crn", "crn", "em", params, u0, tspan, theta, dt=dt, n_steps=n_steps,
+                    seed=13)
 
 
 def sample_indices(N: int, k: int) -> np.ndarray:
