@@ -69,6 +69,11 @@ typedef struct ens_ctx ens_ctx;
  *                                (plain form only: ENS_OPT_FORM, ENS_OPT_TPL
  *                                and ENS_OPT_GRID are ignored; block 64, 128
  *                                or 256 holds 2, 4 or 8)   appendix B.1, POLLU
+ * ENS_SYS_CRN             4  6   (S, D, tau, nu0, n, eta): the sigma-factor
+ *                                chemical Langevin SDE, state (s, A1, A2, A3),
+ *                                8 Wiener processes; concentrations driven
+ *                                below zero enter the Hill term and the
+ *                                square roots as 0          appendix, CRN SDE
  */
 #define ENS_SYS_LINEAR 0
 #define ENS_SYS_LORENZ 1
@@ -77,12 +82,17 @@ typedef struct ens_ctx ens_ctx;
 #define ENS_SYS_OREGO 4
 #define ENS_SYS_HIRES 5
 #define ENS_SYS_POLLU 6
+#define ENS_SYS_CRN 7
 
 /* ---- algorithms -------------------------------------------------------- */
 #define ENS_ALG_TSIT5 1  /* adaptive Tsitouras 5(4), PI control   sec. 3.1, 5.2.1 */
 #define ENS_ALG_RODAS4 2 /* adaptive Rosenbrock RODAS4, W = I - gamma h J,
                             FP64 LU and solves              sec. 3.2.1, 5.1.3, 5.2.1 */
 #define ENS_ALG_EM 3     /* fixed-step Euler-Maruyama, Philox4x32-10 normals
+                                                            sec. 3.3, 5.2.2     */
+#define ENS_ALG_SIEA 5   /* fixed-step weak order-2 scheme for diagonal noise
+                            (Kloeden-Platen explicit order-2.0 weak scheme, the
+                            reading of GPUSIEA), Philox4x32-10 normals as for EM
                                                             sec. 3.3, 5.2.2     */
 #define ENS_ALG_ROS23 4  /* adaptive Rosenbrock23: the L-stable 2(3) modified
                             Rosenbrock pair of Shampine & Reichelt, W = I - d h J
@@ -102,8 +112,8 @@ typedef struct ens_ctx ens_ctx;
 #define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256 (forms 0, 1);
                                256, 512 or 1024 (form 2, the sorting group);
                                0 (default): 256, or 1024 for form 2            */
-#define ENS_OPT_DT 4        /* fixed step of ENS_ALG_EM (> 0)                    */
-#define ENS_OPT_SEED 5      /* 64-bit Philox key of ENS_ALG_EM (integer value,
+#define ENS_OPT_DT 4        /* fixed step of ENS_ALG_EM / SIEA (> 0)             */
+#define ENS_OPT_SEED 5      /* 64-bit Philox key of ENS_ALG_EM / SIEA (integer value,
                                exact below 2^53)                                */
 #define ENS_OPT_H0 6        /* first step of adaptive solves; 0 (default):
                                Hairer-Norsett-Wanner starting-step heuristic    */
@@ -176,11 +186,11 @@ int ens_system_dims(int system_id, int *n, int *m);
  *   alg        ENS_ALG_*; (system, alg) must be one of
  *              {LINEAR, LORENZ} x TSIT5,
  *              {LINEAR, LORENZ, ROBERTSON, OREGO, HIRES, POLLU} x {RODAS4,
- *              ROS23}, GBM4 x EM
- *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM)
+ *              ROS23}, {GBM4, CRN} x EM, GBM4 x SIEA
+ *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM and SIEA)
  *   save_times HOST, [n_save] fractions theta_j, 0 < theta_0 < ... <= 1; save
  *              j of trajectory i is at t0_i + theta_j (tf_i - t0_i).  Adaptive
- *              solvers step exactly onto every save time.  For EM every
+ *              solvers step exactly onto every save time.  For EM and SIEA every
  *              theta_j * round((tf - t0)/dt) must be an integer step count.
  *              The array is copied into the launch; it may be freed on return.
  *   n_save     1..64
@@ -198,7 +208,9 @@ int ens_solve(ens_ctx *ctx, int system_id, int64_t n_traj, const void *params,
 /*
  * The raw Philox4x32-10 words the ENS_ALG_EM kernel draws at step `step`:
  * out[k][i] (k = 0..3, uint32, device, [4][n_traj]) = word k of
- * Philox4x32-10(counter = (step, i mod 2^32, i >> 32, 0), key = seed), the
+ * Philox4x32-10(counter = (step, i mod 2^32, i >> 32, 0), key = seed) (the
+ * CRN's Wiener increments 5..8 come from a second call with last counter
+ * word 1), the
  * generator of Salmon et al. (SC'11) that the paper's SDE kernels leave
  * unnamed (section 6.8.1).  Same device function as the solver kernel.
  */

@@ -59,10 +59,14 @@ bool supported(int sys, int alg) {
     case ENS_ALG_ROS23:
       return sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR ||
              sys == ENS_SYS_OREGO || sys == ENS_SYS_HIRES || sys == ENS_SYS_POLLU;
-    case ENS_ALG_EM: return sys == ENS_SYS_GBM4;
+    case ENS_ALG_EM: return sys == ENS_SYS_GBM4 || sys == ENS_SYS_CRN;
+    case ENS_ALG_SIEA: return sys == ENS_SYS_GBM4;
   }
   return false;
 }
+
+// fixed-step SDE algorithms (ENS_OPT_DT, Philox key, FP32 only)
+bool is_sde(int alg) { return alg == ENS_ALG_EM || alg == ENS_ALG_SIEA; }
 
 int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void* u0,
                   const double* tspan, int alg, double atol, double rtol,
@@ -71,14 +75,14 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
   if (ens_system_dims(sys, &nn, &mm) != ENS_OK)
     return fail(c, ENS_EINVAL, "unknown system_id %d", sys);
   if (alg != ENS_ALG_TSIT5 && alg != ENS_ALG_RODAS4 && alg != ENS_ALG_EM &&
-      alg != ENS_ALG_ROS23)
+      alg != ENS_ALG_ROS23 && alg != ENS_ALG_SIEA)
     return fail(c, ENS_EINVAL, "unknown alg %d", alg);
   if (!supported(sys, alg))
     return fail(c, ENS_EUNSUPPORTED, "system %d has no kernel for alg %d", sys, alg);
   if (c->save_mode == 1 && alg != ENS_ALG_TSIT5)
     return fail(c, ENS_EUNSUPPORTED, "dense output (save mode 1) is implemented for Tsit5 only");
-  if (alg == ENS_ALG_EM && c->precision != 32)
-    return fail(c, ENS_EUNSUPPORTED, "Euler-Maruyama is built for precision 32 only");
+  if (is_sde(alg) && c->precision != 32)
+    return fail(c, ENS_EUNSUPPORTED, "the SDE kernels are built for precision 32 only");
   if (n < 0 || n > (int64_t(1) << 40))
     return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
   if (n_save < 1 || n_save > ens::kMaxSave)
@@ -96,11 +100,11 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
                   j, theta[j]);
     prev = theta[j];
   }
-  if (alg != ENS_ALG_EM) {
+  if (!is_sde(alg)) {
     if (!(atol > 0.0) || !std::isfinite(atol) || !(rtol > 0.0) || !std::isfinite(rtol))
       return fail(c, ENS_EINVAL, "abstol and reltol must be finite and > 0");
   } else if (!(c->dt > 0.0) || !std::isfinite(c->dt)) {
-    return fail(c, ENS_EINVAL, "Euler-Maruyama needs ENS_OPT_DT > 0");
+    return fail(c, ENS_EINVAL, "the fixed-step SDE algorithms need ENS_OPT_DT > 0");
   }
   return ENS_OK;
 }
@@ -150,7 +154,7 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
     cfg.form = 0;
     if (cfg.block > ens::kMaxBlock) cfg.block = ens::kMaxBlock;
   }
-  if (alg != ENS_ALG_EM) {
+  if (!is_sde(alg)) {
     // blocks of 512 or 1024 threads exist only for the sorted form, which
     // needs a power of two of at least 256
     if (cfg.form == 2 && cfg.block != 256 && cfg.block != 512 && cfg.block != 1024)
@@ -161,9 +165,10 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
   } else if (cfg.block > ens::kMaxBlock) {
     cfg.block = ens::kMaxBlock;
   }
-  if (alg == ENS_ALG_EM) {
+  if (is_sde(alg)) {
     cfg.form = 0;
-    e = ens::launch_em(sys, c->precision, cfg, a, s);
+    e = alg == ENS_ALG_EM ? ens::launch_em(sys, c->precision, cfg, a, s)
+                          : ens::launch_siea(sys, c->precision, cfg, a, s);
   } else {
     if (cfg.form == 1) {
       if (cfg.grid <= 0) cfg.grid = ens::persistent_grid(alg, sys, c->precision, cfg.block, c->num_cu);
@@ -207,6 +212,7 @@ int ens_system_dims(int system_id, int* n, int* m) {
     case ENS_SYS_OREGO: nn = 3; mm = 3; break;
     case ENS_SYS_HIRES: nn = 8; mm = 12; break;
     case ENS_SYS_POLLU: nn = 20; mm = 25; break;
+    case ENS_SYS_CRN: nn = 4; mm = 6; break;
     default: return ENS_EINVAL;
   }
   if (n) *n = nn;
@@ -396,10 +402,10 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
   const int blocks[3] = {64, 128, 256};
   for (int b : blocks) {
     for (int tpl : {1, 2, 4}) cands[nc++] = {0, b, tpl, 64};
-    if (alg != ENS_ALG_EM)
+    if (!is_sde(alg))
       for (int rf : {4, 16, 32}) cands[nc++] = {1, b, 1, rf};
   }
-  if (alg != ENS_ALG_EM) {
+  if (!is_sde(alg)) {
     for (int b : {256, 512, 1024}) cands[nc++] = {2, b, 1, 64};
     for (int b : {256, 512}) cands[nc++] = {2, b, 2, 64};  // sort over 2 * block items
   }

@@ -58,6 +58,9 @@ hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
 hipError_t launch_em(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                      hipStream_t s);
 
+hipError_t launch_siea(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                       hipStream_t s);
+
 hipError_t launch_philox_fill(uint64_t seed, int64_t n, uint32_t step, uint32_t* out,
                               hipStream_t s);
 

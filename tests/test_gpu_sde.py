@@ -1,0 +1,130 @@
+"""GPU parity of the weak order-2 GBM kernel (ENS_ALG_SIEA) and the CRN
+Euler-Maruyama kernel (ENS_SYS_CRN, 8 Wiener processes, two Philox calls
+per step) against the FP64 oracle on the same Philox words, through the C
+ABI.
+
+Bars: the weak order-2 step evaluates a(X), b(X) at three extra points and
+adds four terms, about twice the FP32 operations of an EM step, so its
+multiplicative path error over 256 steps is bounded by about twice the EM
+bar (2 x 1.2e-4).  The CRN couples a Hill function (hardware log2/exp2)
+and square roots to a contracting linear chain: most paths agree to ~1e-6,
+but a path whose concentration an increment takes through zero clamps in
+one precision and not the other and then follows a different (equally
+valid) path; so the bar is on the median path (1e-5), on 99% of paths
+(1e-3) and on the ensemble mean at every save (1e-4 relative), the
+statistic the paper computes SDE ensembles for.
+"""
+import numpy as np
+import pytest
+
+from paper_2304_06835_amd import workloads as W
+from tests.gpu_util import banner, to_dev, to_host
+from tests.test_oracle_sde import step_moments
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ens():
+    import torch
+    import paper_2304_06835_amd as e
+    assert torch.cuda.is_available()
+    return e
+
+
+def run_sde(ens, e, **opts):
+    import torch
+    s = ens.Solver(0, precision=32, dt=e.dt, seed=e.seed, **opts)
+    out = s.solve(e.system, to_dev(e.params), to_dev(e.u0), to_dev(e.tspan), e.alg, 0.0, 0.0,
+                  e.theta)
+    torch.cuda.synchronize()
+    r = to_host(out)
+    s.close()
+    return r
+
+
+def test_siea_paths_match_oracle(ens, orc):
+    e = W.gbm(N=3001, alg="siea")
+    banner(f"siea gbm4 N={e.n}")
+    out = run_sde(ens, e)
+    ref = orc.sde(orc.GBM4, orc.SIEA, e.params, e.u0, e.dt, e.n_steps, e.seed)
+    rel = np.abs(out[0] - ref) / np.abs(ref)
+    print("siea path rel err: max %.3e median %.3e" % (rel.max(), np.median(rel)))
+    assert rel.max() <= 2.4e-4
+    assert np.median(rel) <= 1e-5
+
+
+def test_siea_weak_order_two_on_the_gpu(ens, orc):
+    """2^22 GPU paths of one GBM: the sample mean of X(1) is within 4
+    standard errors of the scheme's exact mean (E[M])^N (quadrature over the
+    oracle's step), and that mean is within O(h^2) of e^{mu}: with h = 1/16
+    the scheme's bias is 30x below the Euler-Maruyama one's."""
+    mu, sigma, h, n = 0.8, 0.6, 1.0 / 16, 16
+    N = 1 << 20
+    e = W.gbm(N=N, alg="siea")
+    e.params = np.ascontiguousarray(np.tile(np.array([[mu], [sigma]], np.float32), N))
+    e.dt, e.n_steps = h, n
+    banner("siea weak order N=%d x 4 components" % N)
+    x = run_sde(ens, e)[0].astype(np.float64).reshape(-1)
+    m_siea = step_moments(orc, orc.SIEA, mu, sigma, h)[0] ** n
+    m_em = step_moments(orc, orc.EM, mu, sigma, h)[0] ** n
+    se = x.std() / np.sqrt(x.size)
+    print("siea mean %.6f exact-scheme %.6f (se %.1e); bias siea %.2e em %.2e"
+          % (x.mean(), m_siea, se, m_siea - np.exp(mu), m_em - np.exp(mu)))
+    assert abs(x.mean() - m_siea) < 4 * se
+    assert abs(m_siea - np.exp(mu)) * 30 < abs(m_em - np.exp(mu))
+
+
+def test_siea_block_shapes_bitwise_equal(ens):
+    e = W.gbm(N=5000, alg="siea")
+    base = run_sde(ens, e)
+    for b in (64, 128):
+        assert np.array_equal(run_sde(ens, e, block=b).view(np.uint8), base.view(np.uint8))
+
+
+def crn_small(t_end=50.0, vals=5):
+    return W.crn(values_per_param=vals, t_end=t_end)   # 5^6 = 15625 trajectories, 500 steps
+
+
+def test_crn_paths_match_oracle(ens, orc):
+    e = crn_small()
+    banner(f"crn em N={e.n} steps={e.n_steps}")
+    out = run_sde(ens, e)
+    idx = W.sample_indices(e.n, 3000)
+    P = np.ascontiguousarray(e.params[:, idx])
+    U = np.ascontiguousarray(e.u0[:, idx])
+    for j, th in enumerate(e.theta):
+        ref = orc.sde(orc.CRN, orc.EM, P, U, e.dt, int(round(th * e.n_steps)), e.seed, ids=idx)
+        got = out[j][:, idx].astype(np.float64)
+        rel = np.abs(got - ref).max(axis=0) / np.abs(ref).max(axis=0)
+        mean_rel = np.abs(got.mean(axis=1) - ref.mean(axis=1)) / np.abs(ref.mean(axis=1))
+        if j in (0, len(e.theta) - 1):
+            print("crn save %d: path rel err median %.2e p99 %.2e max %.2e; mean rel err %.2e"
+                  % (j, np.median(rel), np.quantile(rel, 0.99), rel.max(), mean_rel.max()))
+        assert np.median(rel) <= 1e-5
+        assert np.quantile(rel, 0.99) <= 1e-3
+        assert mean_rel.max() <= 1e-4
+
+
+def test_crn_block_shapes_bitwise_equal_and_finite(ens):
+    e = crn_small(t_end=20.0, vals=4)
+    base = run_sde(ens, e)
+    assert np.isfinite(base).all()
+    for b in (64, 128):
+        assert np.array_equal(run_sde(ens, e, block=b).view(np.uint8), base.view(np.uint8))
+
+
+def test_sde_argument_errors(ens):
+    import paper_2304_06835_amd as ensmod
+    e = W.gbm(N=16, alg="siea")
+    s = ens.Solver(0, precision=32, dt=e.dt, seed=e.seed)
+    c = crn_small(t_end=1.0, vals=2)
+    with pytest.raises(ensmod.EnsError):   # the weak order-2 scheme needs diagonal noise
+        s.solve("crn", to_dev(c.params), to_dev(c.u0), to_dev(c.tspan), "siea", 0.0, 0.0,
+                c.theta)
+    s.close()
+    s = ens.Solver(0, precision=64, dt=e.dt, seed=e.seed)
+    with pytest.raises(ensmod.EnsError):   # FP32 only
+        s.solve("gbm4", to_dev(e.params.astype(np.float64)), to_dev(e.u0.astype(np.float64)),
+                to_dev(e.tspan), "siea", 0.0, 0.0, e.theta)
+    s.close()
