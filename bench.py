@@ -48,8 +48,12 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 #    + 6, error estimate 13, error norm 19, control 7  -> 181.
 #  EM, GBM4: per step 4 x (2 flops for the increment + 2 for the update) +
 #    Box-Muller 2 x 8  -> 32 (Philox is integer work, counted separately).
+#  Weak order-2 scheme, GBM4: per step 4 x 29 (drift and diffusion at four
+#    points, the three combinations) + Box-Muller 16 -> 132.
+#  EM, CRN: per step drift 14 + Hill term 10 (two powers as exp2/log2 counted
+#    as 1 each) + 8 noise terms 24 + updates 8, + Box-Muller 4 x 8 -> 88.
 FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("ros23", "robertson"): 181,
-         ("em", "gbm4"): 32}
+         ("em", "gbm4"): 32, ("siea", "gbm4"): 132, ("em", "crn"): 88}
 # Tsit5 dense output, per save time read off a step (save mode 1; every save
 # but the last, which a step lands on): theta 2, the seven weight polynomials
 # b_i(theta) by Horner 7 x 7, and u + h sum_i b_i k_i for n = 3: 3 x 15 -> 96.
@@ -69,11 +73,11 @@ FORMS = {"plain": {"form": 0}, "persistent": {"form": 1},
 # the stiff ensemble also at a sort over 1024 items in 512-thread blocks
 STIFF_FORMS = dict(FORMS, sorted_b512_r2={"form": 2, "block": 512, "tpl": 2})
 DEFAULT_FORM = {"lorenz_fp32": "sorted", "lorenz_fp64": "plain", "robertson": "sorted",
-                "gbm": "plain"}
+                "gbm": "plain", "orego": "sorted", "hires": "sorted", "pollu": "plain",
+                "crn": "plain"}
 # save times: "landing" (steps end on every save time) or "dense" (Tsit5's
 # dense output between steps that land only on the last save time)
-DEFAULT_SAVE = {"lorenz_fp32": "dense", "lorenz_fp64": "landing", "robertson": "landing",
-                "gbm": "landing"}
+DEFAULT_SAVE = {"lorenz_fp32": "dense"}  # every other workload: "landing"
 SAVE_MODES = {"landing": 0, "dense": 1}
 
 
@@ -84,10 +88,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="lorenz_fp32",
                     choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm", "orego", "hires",
-                             "pollu"])
+                             "pollu", "crn"])
     ap.add_argument("--n", type=int, default=0, help="override the ensemble size")
-    ap.add_argument("--alg", default="", choices=["", "rodas4", "ros23"],
-                    help="stiff method of the Robertson workload (default rodas4)")
+    ap.add_argument("--alg", default="", choices=["", "rodas4", "ros23", "siea"],
+                    help="stiff method of the Robertson and appendix-B.1 workloads (default "
+                         "rodas4), or siea for the GBM workload")
     ap.add_argument("--form", default="",
                     choices=["", "plain", "persistent", "sorted", "sorted_b512_r2", "auto"])
     ap.add_argument("--save-mode", default="", choices=["", "landing", "dense"])
@@ -128,6 +133,10 @@ def make_workload(name, n, alg=""):
     from paper_2304_06835_amd import workloads as W
     if name in W.STIFF:
         return W.stiff(name, N=n, alg=alg or "rodas4")
+    if name == "crn":
+        return W.crn()
+    if name == "gbm" and alg:
+        return W.gbm(N=n, alg=alg) if n else W.gbm(alg=alg)
     f = {"lorenz_fp32": W.lorenz_fp32, "lorenz_fp64": W.lorenz_fp64,
          "robertson": W.robertson, "gbm": W.gbm}[name]
     kw = {"alg": alg} if (alg and name == "robertson") else {}
@@ -148,7 +157,12 @@ def describe(e):
         return ("Robertson 2^20-ensemble, rates x logU[0.5,2], tf~logU[1,1e5], FP32 state + "
                 f"FP64 W/LU, {'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 "
                 "atol=1e-8, final state")
-    return "GBM 4-component 2^22-ensemble, Euler-Maruyama dt=1/256, Philox4x32-10, FP32"
+    if e.name == "crn":
+        return ("sigma-factor CRN SDE (appendix), 10^6-trajectory Cartesian parameter sweep, "
+                "Euler-Maruyama dt=0.1 on [0,1000] (10^4 steps), 8 Wiener processes, FP32")
+    return ("GBM 4-component 2^22-ensemble, "
+            f"{'weak order-2 scheme' if e.alg == 'siea' else 'Euler-Maruyama'} dt=1/256, "
+            "Philox4x32-10, FP32")
 
 
 def dev(a):
@@ -189,7 +203,7 @@ class Runner:
         self.s = ens.Solver(0, precision=precision)
         if e.h0:
             self.s.set(h0=e.h0)
-        if e.alg == "em":
+        if e.alg in ("em", "siea"):
             self.s.set(dt=e.dt, seed=e.seed)
         if opts:
             self.s.set(**opts)
@@ -261,8 +275,11 @@ def cpu_baseline(e, gpu_out, seconds):
 
     def run(idx, tol=None):
         p, u, ts = sub(idx)
-        if e.alg == "em":
-            return oracle.em(p, u, e.dt, e.n_steps, e.seed, ids=idx, nthreads=nth)[None]
+        if e.alg in ("em", "siea"):
+            sid = {"gbm4": oracle.GBM4, "crn": oracle.CRN}[e.system]
+            oalg = oracle.EM if e.alg == "em" else oracle.SIEA
+            return oracle.sde(sid, oalg, p, u, e.dt, e.n_steps, e.seed, ids=idx,
+                              nthreads=nth)[None]
         alg = {"tsit5": oracle.TSIT5, "rodas4": oracle.RODAS4, "ros23": oracle.ROS23}[e.alg]
         if tol is not None and alg == oracle.ROS23:  # the truth comes from the 4th-order method
             alg = oracle.RODAS4
@@ -292,8 +309,9 @@ def cpu_baseline(e, gpu_out, seconds):
                      f"FP64 C oracle, OpenMP over trajectories, {dt:.1f} s"}
     idx = W.sample_indices(e.n, 4096)
     g = gpu_out[:, :, idx].astype(np.float64)
-    if e.alg == "em":
+    if e.alg in ("em", "siea"):
         ref = run(idx)
+        g = g[-1:]  # the final state
         err = float((np.abs(g - ref) / np.abs(ref)).max())
         kind = "pathwise relative error vs FP64 oracle on the same Philox stream"
     else:
@@ -393,7 +411,7 @@ def stiff_variant(steps):
     return res
 
 
-def config_variant(name, precision, steps):
+def config_variant(name, precision, steps, alg=""):
     """Another configuration of the path at its own size: time, throughput,
     algorithmic rate and the error against the FP64 oracle.  Lorenz FP64 is
     compared on all 8192 trajectories with the oracle at the same method and
@@ -404,7 +422,7 @@ def config_variant(name, precision, steps):
 
     import oracle
     from paper_2304_06835_amd import workloads as W
-    e = make_workload(name, 0)
+    e = make_workload(name, 0, alg)
     r = Runner(e, precision, **FORMS["plain"])
     attempts, _ = r.attempts()
     _, ms, _ = r.time(max(3, steps), 2)
@@ -412,14 +430,26 @@ def config_variant(name, precision, steps):
     fl = FLOPS[(e.alg, e.system)] * attempts / (ms * 1e-3) / 1e12
     res = {"workload": describe(e), "kernel_ms": ms, "traj_per_s": e.n / (ms * 1e-3),
            "achieved_tflops": fl, "frac_of_peak": fl / PEAK[precision]}
-    if e.alg == "em":
-        idx = W.sample_indices(e.n, 4096)
-        ref = oracle.em(np.ascontiguousarray(e.params[:, idx]), np.ascontiguousarray(e.u0[:, idx]),
-                        e.dt, e.n_steps, e.seed, ids=idx)
-        res["max_pathwise_rel_err"] = float((np.abs(out[0][:, idx] - ref) / np.abs(ref)).max())
-        mu = e.params[0].astype(np.float64)
-        z = out[0].astype(np.float64) / ((1.0 + mu * e.dt) ** e.n_steps)[None, :]
-        res["standardised_mean_of_X1"] = float(z.mean())
+    if e.alg in ("em", "siea"):
+        sid = {"gbm4": oracle.GBM4, "crn": oracle.CRN}[e.system]
+        oalg = oracle.EM if e.alg == "em" else oracle.SIEA
+        k = 4096 if e.system == "gbm4" else 2048
+        idx = W.sample_indices(e.n, k)
+        P, U = np.ascontiguousarray(e.params[:, idx]), np.ascontiguousarray(e.u0[:, idx])
+        t0 = time.perf_counter()
+        ref = oracle.sde(sid, oalg, P, U, e.dt, e.n_steps, e.seed, ids=idx)
+        cpu_s = time.perf_counter() - t0
+        got = out[-1][:, idx].astype(np.float64)
+        rel = np.abs(got - ref).max(axis=0) / np.abs(ref).max(axis=0)
+        res["pathwise_rel_err_max"] = float(rel.max())
+        res["pathwise_rel_err_median"] = float(np.median(rel))
+        res["cpu_oracle"] = {"traj_per_s": k / cpu_s, "cores": oracle.default_threads(),
+                             "sample": f"{k} of {e.n} trajectories"}
+        res["speedup_vs_cpu_oracle"] = (e.n / (ms * 1e-3)) / (k / cpu_s)
+        if e.system == "gbm4" and e.alg == "em":
+            mu = e.params[0].astype(np.float64)
+            z = out[0].astype(np.float64) / ((1.0 + mu * e.dt) ** e.n_steps)[None, :]
+            res["standardised_mean_of_X1"] = float(z.mean())
     else:
         ref = oracle.solve(oracle.LORENZ, oracle.TSIT5, e.params, e.u0, e.tspan, e.abstol,
                            e.reltol, e.theta)[0]
@@ -510,11 +540,11 @@ def main():
     e = make_workload(args.workload, args.n, args.alg)
     precision = 64 if args.workload == "lorenz_fp64" else 32
     form = args.form or DEFAULT_FORM[args.workload]
-    save = args.save_mode or DEFAULT_SAVE[args.workload]
+    save = args.save_mode or DEFAULT_SAVE.get(args.workload, "landing")
     if e.alg != "tsit5":
         save = "landing"
     tuned = None
-    if e.alg == "em":
+    if e.alg in ("em", "siea"):
         form = "plain"
     if form == "auto":
         from paper_2304_06835_amd import workloads as W
@@ -547,7 +577,8 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak if achieved else None,
             "traffic": recorded_traffic(e.name, form + ("/dense" if save == "dense" else ""), 1),
-            "kernel": {"tsit5": "tsit5", "rodas4": "ros", "ros23": "ros", "em": "em_gbm4"}[e.alg]
+            "kernel": {"tsit5": "tsit5", "rodas4": "ros", "ros23": "ros", "siea": "sde_fixed",
+                       "em": "em_gbm4" if e.system == "gbm4" else "sde_fixed"}[e.alg]
                       + {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
                          "sorted_b512_r2": "_sorted", "auto": ""}[form] + f"<{'double' if precision == 64 else 'float'}>",
             "kernel_ms_avg": ker_ms, "kernel_ms_min": ker_min,
@@ -566,7 +597,7 @@ def main():
     del r
 
     variants = {}
-    if not args.no_variants and e.alg != "em":
+    if not args.no_variants and e.alg not in ("em", "siea"):
         fv = form_variants(e, precision, args.steps, out_host, None, SAVE_MODES[save])
         plain_ms = fv["plain"]["kernel_ms"]
         for v in fv.values():
@@ -598,6 +629,8 @@ def main():
             variants["robertson_2p20_ros23"] = stiff_ros23_variant(rob, args.steps, rv)
             variants["lorenz_fp64_8192"] = config_variant("lorenz_fp64", 64, args.steps)
             variants["gbm_em_2p22"] = config_variant("gbm", 32, args.steps)
+            variants["gbm_siea_2p22"] = config_variant("gbm", 32, args.steps, alg="siea")
+            variants["crn_em_1e6"] = config_variant("crn", 32, 3)
             variants["stiff_appendix_b1_8192"] = stiff_variant(args.steps)
             if not args.no_surrogate:
                 variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms)
