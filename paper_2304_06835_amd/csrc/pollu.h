@@ -28,6 +28,26 @@
 namespace ens {
 
 constexpr int kGroup = 32;  // lanes per trajectory of a grouped system
+constexpr int kGroupMaxDim = 20;
+
+// Per-group LDS rows for the cooperative LU: the current pivot row and the
+// pivot lanes of the elimination steps (block of at most kMaxBlock threads).
+static __shared__ double lds_prow[kMaxBlock / kGroup][kGroupMaxDim];
+static __shared__ int lds_piv[kMaxBlock / kGroup][kGroupMaxDim];
+// Per-group LDS copy of the state, for gathering it in every lane, and the
+// trajectory's parameters (lane j holds parameter j and writes it here).
+static __shared__ double lds_state[kMaxBlock / kGroup][kGroup];
+static __shared__ double lds_param[kMaxBlock / kGroup][kGroup];
+
+// Orders LDS writes of one lane before reads of them by the other lanes of
+// the wave (LDS operations of a wave execute in issue order; this keeps the
+// compiler from moving them).
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline int group_slot() { return (int)(threadIdx.x / kGroup); }
 
 // Group reductions and broadcasts within the 32-lane half of a wave.
 template <class T>
@@ -48,19 +68,21 @@ __device__ inline uint32_t group_bits(unsigned long long ballot) {
   return (uint32_t)(ballot >> (threadIdx.x & (kWave - kGroup)));
 }
 
-// Inputs of a grouped trajectory: every lane loads all parameters (each
-// evaluates all rates) and its own component of u0.
-template <class R, int M, int D>
+// Inputs of a grouped trajectory: lane j loads parameter j (j < NP) into its
+// own register and the group's LDS parameter row, and its own component of u0.
+template <class R, int NP, int D>
 struct GroupInput {
-  R p[M], u[1];
+  R p[1], u[1];
   double t0, tf;
   int64_t i;
   __device__ inline void load(const LaunchArgs& a, int64_t k) {
     i = in_col(a, k);
-#pragma unroll
-    for (int r = 0; r < M; ++r) p[r] = load_col<R>(a, a.params, r, i);
     const int c = group_lane();
+    p[0] = c < NP ? load_col<R>(a, a.params, c, i) : (R)0;
     u[0] = c < D ? load_col<R>(a, a.u0, c, i) : (R)0;
+    wave_lds_sync();
+    lds_param[group_slot()][c] = (double)p[0];
+    wave_lds_sync();
     t0 = tspan_at(a, 0, i);
     tf = tspan_at(a, 1, i);
   }
@@ -70,10 +92,11 @@ struct GroupInput {
 template <class S>
 struct GroupW {
   static constexpr int D = S::kDim;
+  static_assert(D <= kGroupMaxDim, "group LDS rows hold kGroupMaxDim entries");
   double a[D];  // this lane's row: W, then its multipliers and U entries
   double inv;   // 1 / pivot of this lane's row
   int kr;       // elimination step at which this lane's row was the pivot (D: never)
-  int piv[D];   // group lane holding the pivot row of each step (same in all lanes)
+  // lds_piv[group][k]: group lane holding the pivot row of step k
 
   template <class R>
   __device__ inline void build(const R* p, const R* u, double alpha, double beta) {
@@ -86,7 +109,7 @@ struct GroupW {
   }
 
   __device__ inline void factor() {
-    const int r = group_lane();
+    const int r = group_lane(), g = group_slot();
     bool used = r >= D;  // padding lanes never hold a pivot
     kr = D;
     inv = 0.0;
@@ -95,11 +118,13 @@ struct GroupW {
       const double cand = used ? -1.0 : fabs(a[k]);
       const double m = group_max(cand);
       const int pk = __ffs(group_bits(__ballot(cand == m))) - 1;
-      piv[k] = pk;
-      double prow[D];
+      if (r == pk) {  // the pivot row goes to the group's LDS row
+        lds_piv[g][k] = pk;
 #pragma unroll
-      for (int c = k; c < D; ++c) prow[c] = __shfl(a[c], pk, kGroup);
-      const double ip = recip(prow[k]);
+        for (int c = k; c < D; ++c) lds_prow[g][c] = a[c];
+      }
+      wave_lds_sync();
+      const double ip = recip(lds_prow[g][k]);
       if (r == pk) {
         used = true;
         kr = k;
@@ -108,8 +133,9 @@ struct GroupW {
         const double l = a[k] * ip;
         a[k] = l;
 #pragma unroll
-        for (int c = k + 1; c < D; ++c) a[c] = fma(-l, prow[c], a[c]);
+        for (int c = k + 1; c < D; ++c) a[c] = fma(-l, lds_prow[g][c], a[c]);
       }
+      wave_lds_sync();
     }
   }
 
@@ -119,17 +145,17 @@ struct GroupW {
   // out (padding lanes: 0).
   template <bool>
   __device__ inline void solve(double* x) const {
-    const int r = group_lane();
+    const int r = group_lane(), g = group_slot();
     double b = x[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) {  // L z = P b
-      const double z = __shfl(b, piv[k], kGroup);
+      const double z = __shfl(b, lds_piv[g][k], kGroup);
       if (kr > k) b = fma(-a[k], z, b);
     }
     double res = 0.0;
 #pragma unroll
     for (int c = D - 1; c >= 0; --c) {  // U x = z, pivot c finalises x_c
-      const double v = __shfl(b * inv, piv[c], kGroup);
+      const double v = __shfl(b * inv, lds_piv[g][c], kGroup);
       if (kr < c) b = fma(-a[c], v, b);
       if (r == c) res = v;
     }
@@ -175,9 +201,15 @@ constexpr MassAction kPollu[25] = {
 
 struct Pollu {
   static constexpr bool kGrouped = true;
-  static constexpr int kDim = 20, N = 1, M = 25;
+  // N = 1 component and M = 1 parameter per lane; the 25 rate constants sit
+  // in the group's LDS parameter row
+  static constexpr int kDim = 20, kParams = 25, N = 1, M = 1;
   template <class R>
-  using Input = GroupInput<R, M, kDim>;
+  using Input = GroupInput<R, kParams, kDim>;
+  template <class R>
+  __device__ static inline R rate_constant(int j) {
+    return (R)lds_param[group_slot()][j];
+  }
   using Matrix = GroupW<Pollu>;
   static constexpr int kFlopsF = 140;  // 25 rates (13 two-factor) + 63 stoichiometric terms x 2
 
@@ -192,25 +224,43 @@ struct Pollu {
     return (T)(int)(((r.pos1 >> i) & 1u) + 2u * ((r.pos2 >> i) & 1u)) - (T)(int)((r.neg >> i) & 1u);
   }
 
+  // every lane gets the group's whole state (through the group's LDS row:
+  // one write per lane, broadcast reads at fixed offsets)
   template <class R>
   __device__ static inline void gather(const R* u, R* y) {
+    const int g = group_slot();
+    wave_lds_sync();  // earlier readers of the row have read it
+    lds_state[g][group_lane()] = (double)u[0];
+    wave_lds_sync();
 #pragma unroll
-    for (int c = 0; c < kDim; ++c) y[c] = __shfl(u[0], c, kGroup);
+    for (int c = 0; c < kDim; ++c) y[c] = (R)lds_state[g][c];
   }
 
+  // Every lane forms the whole right-hand side (the stoichiometric table is
+  // compile-time, so every term lands in a fixed register) and keeps its own
+  // component: no per-lane coefficients to hold.
   template <class R>
-  __device__ static inline void f(const R* k, const R* u, R* du) {
-    R y[kDim];
+  __device__ static inline void f(const R*, const R* u, R* du) {
+    R y[kDim], d[kDim];
     gather(u, y);
-    const int i = group_lane();
-    R acc = (R)0;
+#pragma unroll
+    for (int c = 0; c < kDim; ++c) d[c] = (R)0;
 #pragma unroll
     for (int j = 0; j < 25; ++j) {
-      R r = k[j] * y[kPollu[j].a];
+      R r = rate_constant<R>(j) * y[kPollu[j].a];
       if (kPollu[j].b >= 0) r = r * y[kPollu[j].b];
-      acc = fma(coef<R>(j, i), r, acc);
+#pragma unroll
+      for (int c = 0; c < kDim; ++c) {
+        const int s = (int)((kPollu[j].pos1 >> c) & 1u) + 2 * (int)((kPollu[j].pos2 >> c) & 1u) -
+                      (int)((kPollu[j].neg >> c) & 1u);
+        if (s != 0) d[c] = fma((R)s, r, d[c]);
+      }
     }
-    du[0] = acc;
+    const int i = group_lane();
+    R own = (R)0;
+#pragma unroll
+    for (int c = 0; c < kDim; ++c) own = i == c ? d[c] : own;
+    du[0] = own;
   }
 
   // this lane's row of J = S dr/dy (padding lanes: 0)
@@ -225,7 +275,7 @@ struct Pollu {
     for (int j = 0; j < 25; ++j) {
       const double s = coef<double>(j, i);
       const int ra = kPollu[j].a, rb = kPollu[j].b;
-      const double kj = (double)k[j];
+      const double kj = (double)rate_constant<R>(j);
       if (rb >= 0) {
         row[ra] = fma(s, kj * (double)yr[rb], row[ra]);
         row[rb] = fma(s, kj * (double)yr[ra], row[rb]);

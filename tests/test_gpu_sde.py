@@ -128,3 +128,19 @@ def test_sde_argument_errors(ens):
         s.solve("gbm4", to_dev(e.params.astype(np.float64)), to_dev(e.u0.astype(np.float64)),
                 to_dev(e.tspan), "siea", 0.0, 0.0, e.theta)
     s.close()
+
+
+def test_crn_degenerate_spans(ens):
+    e = crn_small(t_end=5.0, vals=2)
+    e.tspan = np.ascontiguousarray(e.tspan.copy())
+    e.tspan[1, 3] = e.tspan[0, 3] - 1.0      # inverted: status 3, NaN saves
+    e.tspan[1, 4] = np.inf                   # non-finite
+    import torch
+    s = ens.Solver(0, precision=32, dt=e.dt, seed=e.seed)
+    st = torch.empty(e.n, dtype=torch.uint8, device="cuda")
+    out = to_host(s.solve("crn", to_dev(e.params), to_dev(e.u0), to_dev(e.tspan), "em", 0.0, 0.0,
+                          e.theta, status=st))
+    st = to_host(st)
+    assert st[3] == 3 and st[4] == 3 and np.isnan(out[:, :, [3, 4]]).all()
+    assert (np.delete(st, [3, 4]) == 0).all() and np.isfinite(np.delete(out, [3, 4], axis=2)).all()
+    s.close()

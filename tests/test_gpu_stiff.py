@@ -175,3 +175,35 @@ def test_full_ensemble(ens, orc, name):
                                     np.quantile(worst, 0.99), (worst / bar).max()))
     check_fp32(name, worst, bar, err)
     s.close()
+
+
+@pytest.mark.parametrize("name", ["hires", "pollu"])
+def test_status_codes_and_degenerate_inputs(ens, orc, name):
+    """Per-trajectory failures stay per trajectory, also inside a 32-lane
+    group: a non-finite rate gives status 3 and NaN saves, tf == t0 returns
+    u0 at every save, an inverted span gives status 3, and maxiters stops
+    every trajectory with status 1 after exactly that many attempts."""
+    import torch
+    e = W.stiff(name, N=70, dtype=np.float64)
+    e.params[0, 5] = np.nan
+    e.tspan[1, 7] = e.tspan[0, 7]
+    e.tspan[1, 9] = -1.0
+    banner(f"{name} status codes")
+    out, st, stats = run(ens, e, 64)
+    assert st[5] == 3 and np.isnan(out[:, :, 5]).all()
+    assert st[7] == 0 and (out[:, :, 7] == e.u0[:, 7]).all() and stats[0, 7] == 0
+    assert st[9] == 3 and np.isnan(out[:, :, 9]).all()
+    assert (np.delete(st, [5, 9]) == 0).all()
+    ref, rst, *_ = oracle(orc, e, orc.RODAS4)
+    ok = np.setdiff1d(np.arange(e.n), [5, 9])
+    assert np.array_equal(rst[ok], st[ok])
+    out, st, stats = run(ens, W.stiff(name, N=70, dtype=np.float64), 64, maxiters=3)
+    assert (st == 1).all() and (stats.sum(0) == 3).all() and np.isnan(out).all()
+    s = ens.Solver(0, precision=64)
+    n, m = ens.system_dims(name)
+    zp = torch.empty((m, 0), dtype=torch.float64, device="cuda")
+    zu = torch.empty((n, 0), dtype=torch.float64, device="cuda")
+    o = s.solve(name, zp, zu, torch.tensor([0.0, 1.0], dtype=torch.float64, device="cuda"),
+                "rodas4", 1e-6, 1e-6, [1.0])
+    assert o.shape == (1, n, 0)
+    s.close()
