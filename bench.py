@@ -230,6 +230,19 @@ class Runner:
         return self.out.cpu().numpy()
 
 
+def kernel_name(e, form, precision):
+    """The solver kernel a launch of workload e in `form` runs."""
+    prec = "double" if precision == 64 else "float"
+    if e.alg in ("em", "siea"):
+        return "em_gbm4" if (e.alg == "em" and e.system == "gbm4") else f"sde_fixed<{prec}>"
+    if e.system == "pollu":
+        return f"ros_grouped<{prec}>"
+    base = "tsit5" if e.alg == "tsit5" else "ros"
+    suffix = {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
+              "sorted_b512_r2": "_sorted", "auto": ""}[form]
+    return f"{base}{suffix}<{prec}>"
+
+
 def kernel_source_hash(files=None):
     """Hash of the sources a recorded traffic measurement refers to: the
     named files of the kernel's translation unit, or every solver source."""
@@ -577,10 +590,7 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak if achieved else None,
             "traffic": recorded_traffic(e.name, form + ("/dense" if save == "dense" else ""), 1),
-            "kernel": {"tsit5": "tsit5", "rodas4": "ros", "ros23": "ros", "siea": "sde_fixed",
-                       "em": "em_gbm4" if e.system == "gbm4" else "sde_fixed"}[e.alg]
-                      + {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
-                         "sorted_b512_r2": "_sorted", "auto": ""}[form] + f"<{'double' if precision == 64 else 'float'}>",
+            "kernel": kernel_name(e, form, precision),
             "kernel_ms_avg": ker_ms, "kernel_ms_min": ker_min,
             "flops_per_launch": flops, "attempted_steps": attempts, "flops_per_attempt": fpa,
             "dense_output_saves": dense_saves, "flops_per_dense_save": DENSE_FLOPS_PER_SAVE}
