@@ -65,12 +65,14 @@ template <class R, class S>
 struct Tsit5Lane {
   static constexpr int N = S::N, M = S::M;
   using Input = LaneInput<R, M, N>;
+  using Time = typename TimeOf<R>::type;  // FP64 pair for FP64 lanes, float pair for FP32
   R p[M], u[N], k1[N];
-  CompTime t;
+  Time t;
   double t0, tf;
   double ts;     // next save time
   double tland;  // the time steps land on: the next save time, or with dense
                  // output (a.dense) the last one
+  typename Time::Mark tland_m;  // tland as the target of t.to()
   R h;
   R hmax;    // tf - t0: no step is longer
   R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
@@ -84,7 +86,7 @@ struct Tsit5Lane {
   // Store u at every save time reached; sp walks the [n_save][N][stride]
   // output one save at a time, so a save costs N stores and an add.
   __device__ inline void save_reached(const LaunchArgs& a) {
-    while (j < a.n_save && ts <= t.hi + t.lo) {
+    while (j < a.n_save && ts <= t.value()) {
 #pragma unroll
       for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
       sp += N * a.out_stride;
@@ -152,6 +154,7 @@ struct Tsit5Lane {
     ts = save_time(a, t0, tf, 0);
     save_reached(a);  // saves that coincide with t0 (tf == t0)
     tland = a.dense ? save_time(a, t0, tf, a.n_save - 1) : ts;
+    tland_m = Time::mark(tland);
     if (done) return;
     S::f(p, u, k1);
     h = (a.h0 > 0.0) ? (R)a.h0 : initial_step(a);
@@ -168,7 +171,7 @@ struct Tsit5Lane {
     using F = Num<R>;
     const R ih = F::rcp(he);
     while (j < a.n_save - 1) {
-      const R d = (R)t.to(ts);
+      const R d = (R)((ts - (double)t.hi) - (double)t.lo);  // FP64: once per save
       if (!(d <= he)) break;
       const R th = d * ih;
       R bt[7];
@@ -198,7 +201,7 @@ struct Tsit5Lane {
     // distance to the next save time: a longer step is cut to land on it,
     // and one ending within 10% short of it is stretched onto it (after a
     // rejected stretched step h <= 0.9 rem, so the stretch cannot repeat)
-    const R rem = (R)t.to(tland);
+    const R rem = (R)t.to(tland_m);
     const bool clamped = h * (R)kStretch >= rem;
     const R he = clamped ? rem : h;
 
@@ -242,7 +245,7 @@ struct Tsit5Lane {
       if (clamped)
         t.set(tland);
       else
-        t.add((double)he);
+        t.add(he);
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         u[c] = y[c];
@@ -258,7 +261,10 @@ struct Tsit5Lane {
       if (clamped) {  // only a cut step lands on a save time
         save_reached(a);
         if (done) return;
-        if (!a.dense) tland = ts;
+        if (!a.dense) {
+          tland = ts;
+          tland_m = Time::mark(ts);
+        }
       }
     } else {
       ++nrej;
