@@ -7,7 +7,7 @@ One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
     python bench.py [--steps K] [--warmup W] [--workload lorenz_fp32|lorenz_fp64|
                      robertson|gbm] [--alg rodas4|ros23]
-                    [--form plain|persistent|sorted|sorted_b512_r2|auto]
+                    [--form plain|persistent|sorted|sorted_b512_r2|sorted_staged|auto]
                     [--save-mode landing|dense]
                     [--no-cpu-baseline] [--no-variants] [--no-surrogate]
 
@@ -72,6 +72,9 @@ FORMS = {"plain": {"form": 0}, "persistent": {"form": 1},
          "sorted": {"form": 2, "block": 256}}
 # the stiff ensemble also at a sort over 1024 items in 512-thread blocks
 STIFF_FORMS = dict(FORMS, sorted_b512_r2={"form": 2, "block": 512, "tpl": 2})
+# Tsit5 also with the sorted form's saves staged in LDS (whole-row writes)
+TSIT5_FORMS = dict(FORMS, sorted_staged={"form": 2, "block": 256, "stage_saves": 1})
+LAUNCH_FORMS = dict(STIFF_FORMS, **TSIT5_FORMS)
 DEFAULT_FORM = {"lorenz_fp32": "sorted", "lorenz_fp64": "plain", "robertson": "sorted",
                 "gbm": "plain", "orego": "sorted", "hires": "sorted", "pollu": "plain",
                 "crn": "plain"}
@@ -94,7 +97,8 @@ def parse():
                     help="stiff method of the Robertson and appendix-B.1 workloads (default "
                          "rodas4), or siea for the GBM workload")
     ap.add_argument("--form", default="",
-                    choices=["", "plain", "persistent", "sorted", "sorted_b512_r2", "auto"])
+                    choices=["", "plain", "persistent", "sorted", "sorted_b512_r2", "sorted_staged",
+                             "auto"])
     ap.add_argument("--save-mode", default="", choices=["", "landing", "dense"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -239,7 +243,7 @@ def kernel_name(e, form, precision):
         return f"ros_grouped<{prec}>"
     base = "tsit5" if e.alg == "tsit5" else "ros"
     suffix = {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
-              "sorted_b512_r2": "_sorted", "auto": ""}[form]
+              "sorted_b512_r2": "_sorted", "sorted_staged": "_sorted", "auto": ""}[form]
     return f"{base}{suffix}<{prec}>"
 
 
@@ -571,7 +575,7 @@ def main():
                                     pe.abstol, pe.reltol, pe.theta)
         opts = dict(tuned)
     else:
-        opts = dict(STIFF_FORMS[form])
+        opts = dict(LAUNCH_FORMS[form])
     opts["save_mode"] = SAVE_MODES[save]
     r = Runner(e, precision, **opts)
     print(f"[bench] {e.name} N={e.n} precision={precision} form={form} save={save}",
@@ -599,7 +603,7 @@ def main():
     config = {"workload": describe(e), "name": e.name, "n_traj": e.n, "alg": e.alg,
               "abstol": e.abstol, "reltol": e.reltol, "n_save": len(e.theta),
               "form": form, "save_times": save,
-              "launch": {k2: int(r.s.get(k2)) for k2 in ("form", "block", "tpl", "save_mode")},
+              "launch": {k2: int(r.s.get(k2)) for k2 in ("form", "block", "tpl", "save_mode", "stage_saves")},
               "tuned": tuned,
               "steps_per_traj_mean": float(steps_per.mean()),
               "steps_per_traj_max": int(steps_per.max()),
@@ -608,7 +612,8 @@ def main():
 
     variants = {}
     if not args.no_variants and e.alg not in ("em", "siea"):
-        fv = form_variants(e, precision, args.steps, out_host, None, SAVE_MODES[save])
+        fv = form_variants(e, precision, args.steps, out_host, None, SAVE_MODES[save],
+                           forms=TSIT5_FORMS if e.alg == "tsit5" else None)
         plain_ms = fv["plain"]["kernel_ms"]
         for v in fv.values():
             v["speedup_vs_plain"] = plain_ms / v["kernel_ms"]
@@ -616,7 +621,7 @@ def main():
         if e.alg == "tsit5":
             other = "landing" if save == "dense" else "dense"
             ov = form_variants(e, precision, args.steps, _plain_out(e, SAVE_MODES[other]), None,
-                               SAVE_MODES[other])
+                               SAVE_MODES[other], forms=TSIT5_FORMS)
             for v in ov.values():
                 v["speedup_vs_plain_headline_save_mode"] = plain_ms / v["kernel_ms"]
             variants[f"forms_{other}_saves"] = ov

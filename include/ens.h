@@ -141,6 +141,16 @@ typedef struct ens_ctx ens_ctx;
                                 steps land on the last save time only and the
                                 earlier ones are read off the step's 4th-order
                                 dense output (section 5.2.1's interpolation) */
+#define ENS_OPT_STAGE_SAVES 14 /* 1: the sorted form with block 256 and one
+                                  round (ENS_ALG_TSIT5) keeps a block's saves in
+                                  LDS (n_save x dim x 256 values, used when they
+                                  fit in 64 KiB) and writes them out as whole
+                                  rows when the block is done, so HBM writes
+                                  equal the output size instead of several
+                                  partial write-backs of each 128-byte line;
+                                  the LDS it holds lowers the blocks resident
+                                  per CU.  0 (default): saves are stored
+                                  directly.  Results are bitwise identical.   */
 
 /* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
 #define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,

@@ -13,7 +13,7 @@ SYSTEMS = {"linear": 0, "lorenz": 1, "robertson": 2, "gbm4": 3, "orego": 4, "hir
 ALGS = {"tsit5": 1, "rodas4": 2, "em": 3, "ros23": 4, "siea": 5}
 OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
         "maxiters": 7, "tspan_broadcast": 8, "refill": 9, "grid": 10, "tpl": 11,
-        "mlp_tile": 12, "save_mode": 13}
+        "mlp_tile": 12, "save_mode": 13, "stage_saves": 14}
 PTRS = {"status": 1, "stats": 2}
 
 # Every symbol include/ens.h declares.

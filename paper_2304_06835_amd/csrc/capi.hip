@@ -135,6 +135,7 @@ ens::LaunchArgs make_args(ens_ctx* c, int64_t n, const void* params, const void*
   a.refill = c->refill;
   a.tpl = c->tpl;
   a.dense = c->save_mode == 1;
+  a.stage = c->stage_saves;
   for (int j = 0; j < n_save; ++j) a.theta[j] = theta[j];
   return a;
 }
@@ -315,6 +316,10 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "save mode must be 0 or 1");
       c->save_mode = (int)v;
       return ENS_OK;
+    case ENS_OPT_STAGE_SAVES:
+      if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "stage_saves must be 0 or 1");
+      c->stage_saves = (int)v;
+      return ENS_OK;
     case ENS_OPT_MLP_TILE:
       if (v != 0 && v != 2 && v != 3 && v != 4 && v != 12 && v != 13)
         return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3, 4, 12 or 13");
@@ -340,6 +345,7 @@ int ens_get_option(const ens_ctx* c, int key, double* v) {
     case ENS_OPT_TPL: *v = c->tpl; return ENS_OK;
     case ENS_OPT_MLP_TILE: *v = c->mlp_tile; return ENS_OK;
     case ENS_OPT_SAVE_MODE: *v = c->save_mode; return ENS_OK;
+    case ENS_OPT_STAGE_SAVES: *v = c->stage_saves; return ENS_OK;
   }
   return ENS_EINVAL;
 }

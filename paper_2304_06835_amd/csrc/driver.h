@@ -175,6 +175,13 @@ struct LaneInput {
 // first initialisation is thrown away; the second, on the lane the item was
 // sorted to, is the same computation, so results are bit-identical to the
 // other forms.
+//
+// Staged variant (one round): a wave's lanes hold items scattered over the
+// block's window and, with dense output, each writes a save in whichever
+// step covers it, so every 128-byte output line would be filled by several
+// waves at different times and leave L2 partially written again and again.
+// Instead the saves go to LDS rows [j][c][item] (n_save N B values) and the
+// block copies them out, one full row at a time, once all its lanes are done.
 
 // Ascending bitonic sort of v[0..NE) in LDS by the B threads of the block.
 template <int NE, int B>
@@ -206,10 +213,14 @@ __device__ inline float work_key(const Lane& L) {
   return (r >= 0.0f && r <= 3.0e38f) ? r : 3.0e38f;  // NaN or inf: last
 }
 
-template <class Lane, int B, int R>
+template <class Lane, int B, int R, bool Staged = false>
 __device__ inline void run_sorted(const LaunchArgs& a) {
   constexpr int NE = B * R, W = B / kWave;
+  static_assert(!Staged || R == 1, "the staged form holds one round's saves");
   __shared__ uint64_t keys[NE];
+  extern __shared__ __align__(16) unsigned char lds_stage_bytes[];
+  using Real = typename Lane::Real;
+  Real* const stage = reinterpret_cast<Real*>(lds_stage_bytes);
   stage_theta(a);
   const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
   const int64_t base = (int64_t)blockIdx.x * NE;
@@ -231,14 +242,27 @@ __device__ inline void run_sorted(const LaunchArgs& a) {
   block_sort<NE, B>(keys);
   for (int r = 0; r < R; ++r) {
     const int grp = r * W + ((r & 1) ? (W - 1 - wave) : wave);
-    const int64_t k = base + (int64_t)(uint32_t)keys[grp * kWave + lane];
+    const int item = (int)(uint32_t)keys[grp * kWave + lane];
+    const int64_t k = base + item;
     if (k >= n) continue;
     typename Lane::Input in;
     in.load(a, k);
     Lane L;
-    L.init(a, k, in);
+    if constexpr (Staged)
+      L.init_to(a, in, stage + item, B);
+    else
+      L.init(a, k, in);
     while (!L.done) L.attempt(a, k);
     L.finish(a, k);
+  }
+  if constexpr (Staged) {
+    __syncthreads();
+    const int64_t k = base + tid;
+    if (k < n) {
+      Real* const dst = static_cast<Real*>(a.out) + out_col(a, k, in_col(a, k));
+      const int rows = a.n_save * Lane::N;
+      for (int r = 0; r < rows; ++r) dst[r * a.out_stride] = stage[r * B + tid];
+    }
   }
 }
 

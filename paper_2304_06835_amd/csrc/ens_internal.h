@@ -39,6 +39,7 @@ struct LaunchArgs {
   int refill;                // persistent form: idle lanes that trigger a refill
   int tpl;                   // plain form: trajectories per lane
   int dense;                 // Tsit5: 1 = save times from the dense output
+  int stage;                 // sorted Tsit5: 1 = saves staged in LDS when they fit
   double theta[kMaxSave];
 };
 
@@ -86,6 +87,7 @@ struct ens_ctx {
   int grid = 0;
   int mlp_tile = 13;
   int save_mode = 0;
+  int stage_saves = 0;
   int tspan_bcast = 0;
   double dt = 0.0;
   double h0 = 0.0;

@@ -188,6 +188,7 @@ constexpr double kLog2QFloor = -13.287712379549449;  // log2(1e-4)
 
 template <class R, class S, class M>
 struct RosLane {
+  using Real = R;
   static constexpr int N = S::N, NP = S::M;
   using V = View<S>;
   using Input = typename V::template Input<R>;

@@ -63,6 +63,7 @@ constexpr double kEta = 0.9, kFacMin = 0.2, kFacMax = 10.0, kQFloor = 1e-4;
 
 template <class R, class S>
 struct Tsit5Lane {
+  using Real = R;
   static constexpr int N = S::N, M = S::M;
   using Input = LaneInput<R, M, N>;
   using Time = typename TimeOf<R>::type;  // FP64 pair for FP64 lanes, float pair for FP32
@@ -78,18 +79,19 @@ struct Tsit5Lane {
   R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
   R lqold;  // log2 of the last accepted error proportion
   R* sp;        // out[j][0][col]: where the next save goes
+  int64_t os;   // row stride of the save destination
   int j;        // next save index
   int nacc, nrej;
   int status;
   bool done;
 
-  // Store u at every save time reached; sp walks the [n_save][N][stride]
-  // output one save at a time, so a save costs N stores and an add.
+  // Store u at every save time reached; sp walks the [n_save][N][os]
+  // destination one save at a time, so a save costs N stores and an add.
   __device__ inline void save_reached(const LaunchArgs& a) {
     while (j < a.n_save && ts <= t.value()) {
 #pragma unroll
-      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
-      sp += N * a.out_stride;
+      for (int c = 0; c < N; ++c) sp[c * os] = u[c];
+      sp += N * os;
       ++j;
       if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
@@ -134,7 +136,14 @@ struct Tsit5Lane {
   }
 
   __device__ inline void init(const LaunchArgs& a, int64_t k, const Input& in) {
-    sp = static_cast<R*>(a.out) + out_col(a, k, in.i);
+    init_to(a, in, static_cast<R*>(a.out) + out_col(a, k, in.i), a.out_stride);
+  }
+
+  // Saves go to dst[(j N + c) stride] instead of the output column (the
+  // staged sorted form points dst at the block's LDS rows).
+  __device__ inline void init_to(const LaunchArgs& a, const Input& in, R* dst, int64_t stride) {
+    sp = dst;
+    os = stride;
 #pragma unroll
     for (int r = 0; r < M; ++r) p[r] = in.p[r];
 #pragma unroll
@@ -183,9 +192,9 @@ struct Tsit5Lane {
         R acc = bt[0] * k[0][c];
 #pragma unroll
         for (int i = 1; i < 7; ++i) acc = fma(bt[i], k[i][c], acc);
-        sp[c * a.out_stride] = fma(he, acc, u[c]);
+        sp[c * os] = fma(he, acc, u[c]);
       }
-      sp += N * a.out_stride;
+      sp += N * os;
       ++j;
       ts = save_time(a, t0, tf, j);
     }
@@ -278,9 +287,9 @@ struct Tsit5Lane {
   }
 
   __device__ inline void finish(const LaunchArgs& a, int64_t k) {
-    for (int jj = j; jj < a.n_save; ++jj, sp += N * a.out_stride)
+    for (int jj = j; jj < a.n_save; ++jj, sp += N * os)
 #pragma unroll
-      for (int c = 0; c < N; ++c) sp[c * a.out_stride] = Num<R>::nan();
+      for (int c = 0; c < N; ++c) sp[c * os] = Num<R>::nan();
     if (a.status) a.status[k] = (uint8_t)status;
     if (a.stats) {
       a.stats[k] = nacc;
@@ -299,19 +308,29 @@ __global__ void __launch_bounds__(kMaxBlock) tsit5_persistent(const LaunchArgs a
   run_persistent<Tsit5Lane<R, S>>(a);
 }
 
-template <class R, class S, int B, int RR>
+template <class R, class S, int B, int RR, bool Staged>
 __global__ void __launch_bounds__(B) tsit5_sorted(const LaunchArgs a) {
-  run_sorted<Tsit5Lane<R, S>, B, RR>(a);
+  run_sorted<Tsit5Lane<R, S>, B, RR, Staged>(a);
 }
 
-// Sorted form: block in {256, 512, 1024} x rounds (tpl) in {1, 2, 4}.
+// LDS the staged sorted form may take for one block's saves.
+constexpr size_t kStageBytes = 64 * 1024;
+
+// Sorted form: block in {256, 512, 1024} x rounds (tpl) in {1, 2, 4}; on
+// request (a.stage), block 256 with one round stages its saves in LDS when
+// they fit.
 template <class R, class S>
 void launch_sorted(const LaunchCfg& cfg, const LaunchArgs& a, hipStream_t s) {
   const int rr = a.tpl >= 4 ? 4 : (a.tpl >= 2 ? 2 : 1);
   const int64_t per = (int64_t)cfg.block * rr;
   const dim3 grid((unsigned)((a.n + per - 1) / per)), blk((unsigned)cfg.block);
+  const size_t stage = (size_t)a.n_save * S::N * 256 * sizeof(R);
+  if (a.stage && cfg.block == 256 && rr == 1 && stage <= kStageBytes) {
+    hipLaunchKernelGGL((tsit5_sorted<R, S, 256, 1, true>), grid, blk, stage, s, a);
+    return;
+  }
 #define ENS_SORTED(BB, RRR) \
-  if (cfg.block == BB && rr == RRR) { hipLaunchKernelGGL((tsit5_sorted<R, S, BB, RRR>), grid, blk, 0, s, a); return; }
+  if (cfg.block == BB && rr == RRR) { hipLaunchKernelGGL((tsit5_sorted<R, S, BB, RRR, false>), grid, blk, 0, s, a); return; }
   ENS_SORTED(256, 1) ENS_SORTED(256, 2) ENS_SORTED(256, 4)
   ENS_SORTED(512, 1) ENS_SORTED(512, 2) ENS_SORTED(512, 4)
   ENS_SORTED(1024, 1) ENS_SORTED(1024, 2) ENS_SORTED(1024, 4)

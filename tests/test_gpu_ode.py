@@ -104,6 +104,32 @@ def test_tsit5_forms_and_launch_shapes_bitwise_equal(ens, precision):
         assert np.array_equal(st, st0) and np.array_equal(s, s0), opts
 
 
+@pytest.mark.parametrize("precision,n_save", [(32, 1), (32, 21), (32, 22), (64, 10), (64, 11)])
+def test_sorted_staged_saves_bitwise_equal(ens, precision, n_save):
+    """With stage_saves, the sorted form with block 256 and one round keeps a
+    block's saves in LDS when n_save x 3 x 256 values fit in 64 KiB (FP32:
+    n_save <= 21, FP64: <= 10) and copies them out when the block is done.  On both sides
+    of that limit, in both save modes, with a ragged tail, a span with
+    tf == t0, an invalid span and a non-finite parameter, it gives the plain
+    form's bits, statuses and step counts."""
+    e = W.lorenz_fp32(N=1000, seed=31)
+    if precision == 64:
+        e.params, e.u0 = e.params.astype(np.float64), e.u0.astype(np.float64)
+    e.theta = (np.arange(n_save, dtype=np.float64) + 1.0) / n_save
+    e.tspan = np.ascontiguousarray(e.tspan.copy())
+    e.tspan[1, 300] = e.tspan[0, 300]          # tf == t0: every save is u0
+    e.tspan[1, 301] = e.tspan[0, 301] - 1.0    # inverted span: status 3, NaN saves
+    e.params[1, 302] = np.nan                  # non-finite error estimate
+    banner(f"sorted staged saves fp{precision} n_save={n_save}")
+    for mode in (0, 1):
+        base, st0, s0 = run(ens, e, precision, save_mode=mode)
+        out, st, s = run(ens, e, precision, save_mode=mode, form=2, block=256, stage_saves=1)
+        assert st0[300] == 0 and st0[301] == 3 and st0[302] == 3
+        assert np.isnan(base[:, :, 301]).all() and np.array_equal(base[-1, :, 300], e.u0[:, 300])
+        assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), mode
+        assert np.array_equal(st, st0) and np.array_equal(s, s0), mode
+
+
 def test_robertson_fp32_rodas4(ens, orc):
     e = W.robertson(N=2053)
     banner(f"robertson fp32 rodas4 N={e.n}")
@@ -204,6 +230,8 @@ def test_argument_errors_are_reported(ens):
         s.set(refill=0)
     with pytest.raises(ens.EnsError, match="block"):
         s.set(block=96)
+    with pytest.raises(ens.EnsError, match="stage_saves"):
+        s.set(stage_saves=2)
 
 
 def test_autotune_picks_a_valid_config_with_identical_results(ens):
