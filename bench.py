@@ -274,6 +274,31 @@ def recorded_traffic(name, form, launches_units):
     return r.get("hbm_bytes_per_launch")
 
 
+def output_checks(e, out):
+    """Checks on the whole GPU output that need no oracle: Robertson's
+    conserved sum y1 + y2 + y3 = 1 (every Rosenbrock step preserves it up to
+    rounding), and for the GBM Euler-Maruyama ensemble the exact discrete
+    moments of the scheme: Z = X_N / (1 + mu h)^N has mean 1 and variance
+    ((1 + mu h)^2 + sigma^2 h)^N / (1 + mu h)^(2N) - 1 per path, so the
+    standardised sum of Z - 1 over all paths and components is N(0, 1)."""
+    import numpy as np
+    if e.system == "robertson":
+        return {"invariant_max_abs_sum_minus_1":
+                float(np.abs(out[-1].astype(np.float64).sum(axis=0) - 1.0).max())}
+    if e.system == "gbm4" and e.alg == "em":
+        mu = e.params[0].astype(np.float64)
+        sg = e.params[1].astype(np.float64)
+        h, n = e.dt, e.n_steps
+        a = 1.0 + mu * h
+        var = ((a * a + sg * sg * h) / (a * a)) ** n - 1.0
+        z = out[-1].astype(np.float64) / (e.u0.astype(np.float64) * a ** n) - 1.0
+        zs = float(z.sum() / np.sqrt(z.shape[0] * var.sum()))
+        zv = z * z - var          # second moment of Z - 1, per path
+        return {"em_mean_z_score": zs,
+                "em_second_moment_rel_dev": float(zv.sum() / (z.shape[0] * var.sum()))}
+    return {}
+
+
 def cpu_baseline(e, gpu_out, seconds):
     """The oracle timed on the host cores on a bounded sample of the same
     workload, plus the max normwise error of the GPU result against the FP64
@@ -608,6 +633,12 @@ def main():
               "steps_per_traj_mean": float(steps_per.mean()),
               "steps_per_traj_max": int(steps_per.max()),
               "rejected_frac": float(st[1].sum() / max(1, st.sum()))}
+    if e.alg not in ("em", "siea"):
+        import numpy as np
+        config["steps_per_traj_cv"] = float(steps_per.std() / max(1e-30, steps_per.mean()))
+        config["steps_per_traj_quantiles"] = {
+            q: float(np.quantile(steps_per, float(q))) for q in ("0.5", "0.9", "0.99")}
+    config.update(output_checks(e, out_host))
     del r
 
     variants = {}
