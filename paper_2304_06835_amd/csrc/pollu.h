@@ -9,16 +9,19 @@
 // equations (u_9 and u_16 there read as y9 and y16): reaction j runs at
 // r_j = k_j y_a (y_b), and dy_i = sum_j s_ij r_j with s_ij in {-1, 0, 1, 2}
 // stored as three species bit masks per reaction.  Every lane gathers the
-// group's state with cross-lane reads (ds_bpermute), evaluates the 25 rates
+// group's state through an LDS row, evaluates the 25 rates
 // and forms its own component; its row of J follows the same table.
 //
-// The cooperative LU (section 5.1.3, eq. 16's per-system block, here per
-// group) keeps partial pivoting: at step k the group's largest remaining
-// |W_rk| (lowest lane on ties) becomes the pivot row, which is broadcast
-// from its lane; the other rows eliminate against it and keep their
-// multiplier in place.  Solves run the same order: forward through the
-// pivots, back through them in reverse, each value broadcast from the lane
-// that finalises it.
+// W is inverted cooperatively (section 5.1.3, eq. 16's per-system block,
+// here per group) by Gauss-Jordan elimination in place with partial
+// pivoting: at step k the group's largest |W_rk| among the rows not yet used
+// (lowest lane on ties) is the pivot row; its lane scales it and broadcasts
+// it through LDS, and every other row eliminates column k against it and
+// keeps the new column in place.  Lane r ends with the row of (P W)^-1 that
+// belongs to the step at which it was the pivot, so each of a step's solves
+// is one LDS exchange of the right-hand side in pivot order, a 20-term dot
+// product per lane and one exchange of the result -- instead of forward and
+// back substitutions whose 40 broadcasts each wait for the previous one.
 #pragma once
 #include <type_traits>
 
@@ -30,10 +33,12 @@ namespace ens {
 constexpr int kGroup = 32;  // lanes per trajectory of a grouped system
 constexpr int kGroupMaxDim = 20;
 
-// Per-group LDS rows for the cooperative LU: the current pivot row and the
-// pivot lanes of the elimination steps (block of at most kMaxBlock threads).
+// Per-group LDS rows of the cooperative inverse: the current pivot row, and
+// a solve's right-hand side (in pivot order) and result (block of at most
+// kMaxBlock threads).
 static __shared__ double lds_prow[kMaxBlock / kGroup][kGroupMaxDim];
-static __shared__ int lds_piv[kMaxBlock / kGroup][kGroupMaxDim];
+static __shared__ double lds_rhs[kMaxBlock / kGroup][kGroupMaxDim];
+static __shared__ double lds_sol[kMaxBlock / kGroup][kGroupMaxDim];
 // Per-group LDS copy of the state, for gathering it in every lane, and the
 // trajectory's parameters (lane j holds parameter j and writes it here).
 static __shared__ double lds_state[kMaxBlock / kGroup][kGroup];
@@ -88,15 +93,13 @@ struct GroupInput {
   }
 };
 
-// W = alpha I - beta J of a grouped system, factored cooperatively.
+// W = alpha I - beta J of a grouped system, inverted cooperatively.
 template <class S>
 struct GroupW {
   static constexpr int D = S::kDim;
   static_assert(D <= kGroupMaxDim, "group LDS rows hold kGroupMaxDim entries");
-  double a[D];  // this lane's row: W, then its multipliers and U entries
-  double inv;   // 1 / pivot of this lane's row
+  double a[D];  // this lane's row: W, then the row kr of (P W)^-1
   int kr;       // elimination step at which this lane's row was the pivot (D: never)
-  // lds_piv[group][k]: group lane holding the pivot row of step k
 
   template <class R>
   __device__ inline void build(const R* p, const R* u, double alpha, double beta) {
@@ -108,33 +111,39 @@ struct GroupW {
     factor();
   }
 
+  // In-place Gauss-Jordan: with p_k the pivot lane of step k and P the
+  // permutation taking row p_k to position k, lane p_k ends holding row k of
+  // (P W)^-1, whose entry c is (W^-1)[k][p_c].
   __device__ inline void factor() {
     const int r = group_lane(), g = group_slot();
     bool used = r >= D;  // padding lanes never hold a pivot
     kr = D;
-    inv = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-      const double cand = used ? -1.0 : fabs(a[k]);
+      // a NaN entry counts as the largest, so every step pivots on a row not
+      // yet used (kr is a permutation of 0..D-1) and the NaN reaches x
+      const double v = fabs(a[k]);
+      const double cand = used ? -1.0 : (v == v ? v : __builtin_inf());
       const double m = group_max(cand);
       const int pk = __ffs(group_bits(__ballot(cand == m))) - 1;
-      if (r == pk) {  // the pivot row goes to the group's LDS row
-        lds_piv[g][k] = pk;
+      const bool piv = r == pk;
+      if (piv) {  // the pivot row goes to the group's LDS row unscaled
 #pragma unroll
-        for (int c = k; c < D; ++c) lds_prow[g][c] = a[c];
-      }
-      wave_lds_sync();
-      const double ip = recip(lds_prow[g][k]);
-      if (r == pk) {
+        for (int c = 0; c < D; ++c) lds_prow[g][c] = a[c];
         used = true;
         kr = k;
-        inv = ip;
-      } else if (!used) {
-        const double l = a[k] * ip;
-        a[k] = l;
-#pragma unroll
-        for (int c = k + 1; c < D; ++c) a[c] = fma(-l, lds_prow[g][c], a[c]);
       }
+      wave_lds_sync();
+      // pivot row: scaled by ip, its column k becomes ip; every other row
+      // (above and below, padding rows stay 0): row -= (a_k ip) pivot row,
+      // its column k becomes -a_k ip.  Selects, not branches, so the row is
+      // not held twice across a divergent update.
+      const double ip = recip(lds_prow[g][k]);
+      const double l = piv ? 0.0 : a[k] * ip;
+      const double sc = piv ? ip : 1.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+        a[c] = c == k ? (piv ? ip : -l) : fma(-l, lds_prow[g][c], a[c] * sc);
       wave_lds_sync();
     }
   }
@@ -142,24 +151,21 @@ struct GroupW {
   __device__ inline bool pivoted() const { return true; }
 
   // x[0]: this lane's component of the right-hand side in, of the solution
-  // out (padding lanes: 0).
+  // out (padding lanes: 0).  x = W^-1 b: slot c of the exchange row gets
+  // b_{p_c} (lane r writes b_r at kr), lane r forms x_{kr} from its row, and
+  // lane j reads x_j back.
   template <bool>
   __device__ inline void solve(double* x) const {
     const int r = group_lane(), g = group_slot();
-    double b = x[0];
+    wave_lds_sync();  // earlier readers of the rows have read them
+    if (kr < D) lds_rhs[g][kr] = x[0];
+    wave_lds_sync();
+    double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < D; ++k) {  // L z = P b
-      const double z = __shfl(b, lds_piv[g][k], kGroup);
-      if (kr > k) b = fma(-a[k], z, b);
-    }
-    double res = 0.0;
-#pragma unroll
-    for (int c = D - 1; c >= 0; --c) {  // U x = z, pivot c finalises x_c
-      const double v = __shfl(b * inv, lds_piv[g][c], kGroup);
-      if (kr < c) b = fma(-a[c], v, b);
-      if (r == c) res = v;
-    }
-    x[0] = res;
+    for (int c = 0; c < D; ++c) s = fma(a[c], lds_rhs[g][c], s);
+    if (kr < D) lds_sol[g][kr] = s;
+    wave_lds_sync();
+    x[0] = r < D ? lds_sol[g][r] : 0.0;
   }
 };
 
@@ -302,8 +308,13 @@ __device__ inline void run_grouped(const LaunchArgs& a) {
   L.finish(a, k);
 }
 
+// At least two waves per SIMD (256 registers a lane): the step's latency
+// chains (group reductions, LDS exchanges) need a second wave to hide them;
+// left to itself the compiler takes 268 (FP32) and 308 (FP64) registers
+// and one wave.  The cap costs a 32-byte (FP32) and 200-byte (FP64)
+// scratch spill, and runs POLLU 1.2-1.4x faster.
 template <class R, class S, class M>
-__global__ void __launch_bounds__(kMaxBlock) ros_grouped(const LaunchArgs a) {
+__global__ void __launch_bounds__(kMaxBlock, 2) ros_grouped(const LaunchArgs a) {
   run_grouped<RosLane<R, S, M>>(a);
 }
 
