@@ -25,9 +25,14 @@ __device__ inline float unit_open(uint32_t x) {
 // (r cos 2 pi v, r sin 2 pi v), r = sqrt(-2 ln u).  The angle is in
 // revolutions, which is what the hardware sine and cosine take: one
 // instruction each instead of a range-reduced library sincos (measured on
-// 2^22 points of (0, 1): max absolute error 1.3e-7 against FP64).
+// 2^22 points of (0, 1): max absolute error 1.3e-7 against FP64).  The
+// radius also uses the bare hardware log2 and square root,
+// r = sqrt(-2 ln 2 log2 u): u lies in [2^-24, 1) and -2 ln u in (0, 33.3],
+// never zero, denormal, negative or infinite, so the library functions'
+// special-case handling (compares, selects and rescaling) has nothing to do.
 __device__ inline void box_muller(uint32_t a, uint32_t b, float& z0, float& z1) {
-  const float r = sqrtf(-2.0f * logf(unit_open(a)));
+  const float r =
+      __builtin_amdgcn_sqrtf(-1.38629436111989061f * __builtin_amdgcn_logf(unit_open(a)));
   const float v = unit_open(b);
   z0 = r * __builtin_amdgcn_cosf(v);
   z1 = r * __builtin_amdgcn_sinf(v);
@@ -116,18 +121,22 @@ struct Crn {
   __device__ inline float powc(float x) const {
     return __builtin_amdgcn_exp2f(n * __builtin_amdgcn_logf(x));
   }
+  // square root of a clamped (>= 0) rate: the bare hardware instruction; the
+  // library version's rescaling only matters below 2^-96, where the term it
+  // feeds is below 1e-14 of the unit-order drift
+  __device__ static inline float rt(float x) { return __builtin_amdgcn_sqrtf(x); }
   // X += a(X) h + b(X) dW, dW = sqrt(h) z
   __device__ inline void em_step(float* X, float h, float sqh, const float* z) const {
     const float s = fmaxf(X[0], 0.0f), a1 = fmaxf(X[1], 0.0f), a2 = fmaxf(X[2], 0.0f),
                 a3 = fmaxf(X[3], 0.0f);
     const float hs = powc(S * s), hd = powc(D * a3);
-    const float H = hs / (hs + hd + 1.0f);
+    const float H = hs * __builtin_amdgcn_rcpf(hs + hd + 1.0f);  // denominator >= 1
     const float prod = nu0 + H;
     const float es = eta * sqh;
-    const float d0 = fma(sqrtf(prod), z[0], -sqrtf(s) * z[1]);
-    const float d1 = fma(sqrtf(s * itau), z[2], -sqrtf(a1 * itau) * z[3]);
-    const float d2 = fma(sqrtf(a1 * itau), z[4], -sqrtf(a2 * itau) * z[5]);
-    const float d3 = fma(sqrtf(a2 * itau), z[6], -sqrtf(a3 * itau) * z[7]);
+    const float d0 = fma(rt(prod), z[0], -rt(s) * z[1]);
+    const float d1 = fma(rt(s * itau), z[2], -rt(a1 * itau) * z[3]);
+    const float d2 = fma(rt(a1 * itau), z[4], -rt(a2 * itau) * z[5]);
+    const float d3 = fma(rt(a2 * itau), z[6], -rt(a3 * itau) * z[7]);
     const float x0 = X[0], x1 = X[1], x2 = X[2], x3 = X[3];
     X[0] = fma(es, d0, fma(prod - x0, h, x0));
     X[1] = fma(es, d1, fma((x0 - x1) * itau, h, x1));
@@ -160,7 +169,8 @@ struct Gbm4Siea {
       const float bp = sigma * yp, bm = sigma * ym;
       const float drift = 0.5f * h * (mu * yb + a);
       const float diff = 0.25f * dW * (bp + bm + 2.0f * b);
-      const float fit = 0.25f * (bp - bm) * (dW * dW - h) / sqh;
+      // (dW^2 - h) / sqrt(h) = sqrt(h) (z^2 - 1) with dW = sqrt(h) z: no division
+      const float fit = 0.25f * (bp - bm) * (sqh * fma(z[c], z[c], -1.0f));
       X[c] = x + drift + diff + fit;
     }
   }
