@@ -61,6 +61,8 @@ struct CompTime {
   using Mark = double;
   __device__ static inline double mark(double v) { return v; }
   __device__ inline double value() const { return hi + lo; }
+  // the current time has reached save time v
+  __device__ inline bool reached(double v) const { return v <= hi + lo; }
 };
 
 // The same compensated time for FP32 lanes without FP64 instructions on the
@@ -91,6 +93,10 @@ struct PairTime {
   // distance to `m`, to FP32 accuracy (exact near the target: Sterbenz)
   __device__ inline float to(const Mark& m) const { return (m.hi - hi) + (m.lo - lo); }
   __device__ inline double value() const { return (double)hi + (double)lo; }
+  // The current time has reached save time v, compared in the pair form that
+  // a step landing on v sets (set(v) == mark(v)): hi + lo of a split v can
+  // fall below v itself, so a plain `v <= value()` would miss the landing.
+  __device__ inline bool reached(double v) const { return to(mark(v)) <= 0.0f; }
 };
 
 template <class R>

@@ -49,7 +49,7 @@ struct Rodas4 {
     typename WOf<S>::type W;
     W.build(p, u, recip(kGamma * (double)he), 1.0);
 
-    const R inv_h = (R)1 / he;
+    const R inv_h = Num<R>::rcp(he);  // FP32: the hardware reciprocal (1 ulp)
     with_pivoting(W, [&](auto piv) {
       constexpr bool P = decltype(piv)::value;
       R U[6][N], y[N], fy[N];

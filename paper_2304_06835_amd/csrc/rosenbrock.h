@@ -194,9 +194,14 @@ struct RosLane {
   using Input = typename V::template Input<R>;
   R p[NP], u[N];
   R f0[M::kFsal ? N : 1];  // f(u), carried from step to step by FSAL methods
-  CompTime t;
+  // FP64 pair in both precisions: these lanes are FP64-heavy already, and the
+  // float pair of the FP32 Tsit5 lanes measured no faster for Rodas4 and 12%
+  // slower for Rosenbrock23's 512-thread sorted form
+  using Time = CompTime;
+  Time t;
   double t0, tf;
-  double ts;  // next save time
+  double ts;                  // next save time
+  typename Time::Mark ts_m;   // ts as the target of t.to()
   R h;
   R hmax;    // tf - t0: no step is longer
   R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
@@ -208,7 +213,7 @@ struct RosLane {
   // Store u at every save time reached; sp walks the [n_save][n][stride]
   // output one save at a time, so a save costs N stores and an add.
   __device__ inline void save_reached(const LaunchArgs& a) {
-    while (j < a.n_save && ts <= t.hi + t.lo) {
+    while (j < a.n_save && t.reached(ts)) {
       if (V::writes()) {
 #pragma unroll
         for (int c = 0; c < N; ++c) sp[c * a.out_stride] = u[c];
@@ -217,6 +222,7 @@ struct RosLane {
       ++j;
       if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
+    ts_m = Time::mark(ts);
     if (j >= a.n_save) done = true;
   }
 
@@ -299,7 +305,7 @@ struct RosLane {
     // distance to the next save time: a longer step is cut to land on it,
     // and one ending within 10% short of it is stretched onto it (after a
     // rejected stretched step h <= 0.9 rem, so the stretch cannot repeat)
-    const R rem = (R)t.to(ts);
+    const R rem = (R)t.to(ts_m);
     const bool clamped = h * (R)kStretch >= rem;
     const R he = clamped ? rem : h;
 

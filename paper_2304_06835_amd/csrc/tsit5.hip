@@ -88,7 +88,7 @@ struct Tsit5Lane {
   // Store u at every save time reached; sp walks the [n_save][N][os]
   // destination one save at a time, so a save costs N stores and an add.
   __device__ inline void save_reached(const LaunchArgs& a) {
-    while (j < a.n_save && ts <= t.value()) {
+    while (j < a.n_save && t.reached(ts)) {
 #pragma unroll
       for (int c = 0; c < N; ++c) sp[c * os] = u[c];
       sp += N * os;

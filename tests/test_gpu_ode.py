@@ -125,9 +125,37 @@ def test_sorted_staged_saves_bitwise_equal(ens, precision, n_save):
         base, st0, s0 = run(ens, e, precision, save_mode=mode)
         out, st, s = run(ens, e, precision, save_mode=mode, form=2, block=256, stage_saves=1)
         assert st0[300] == 0 and st0[301] == 3 and st0[302] == 3
+        assert (np.delete(st0, [301, 302]) == 0).all(), mode
         assert np.isnan(base[:, :, 301]).all() and np.array_equal(base[-1, :, 300], e.u0[:, 300])
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), mode
         assert np.array_equal(st, st0) and np.array_equal(s, s0), mode
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_fp32_landing_on_non_dyadic_times(ens, orc, mode):
+    """FP32 lanes keep time as a pair of floats.  Spans and save times that
+    no float pair holds exactly (per-trajectory t0 in [-0.7, 0.7], tf - t0 in
+    [0.31, 0.97], save fractions j/7) must still be landed on and written:
+    every status 0, the oracle's accuracy and step counts, and the same bits
+    in the plain and sorted forms."""
+    e = W.lorenz_fp32(N=2051, seed=32)
+    rng = np.random.default_rng(33)
+    t0 = rng.uniform(-0.7, 0.7, e.n)
+    e.tspan = np.ascontiguousarray(np.stack([t0, t0 + rng.uniform(0.31, 0.97, e.n)]))
+    e.theta = (np.arange(7, dtype=np.float64) + 1.0) / 7.0
+    banner(f"lorenz fp32 non-dyadic times, save mode {mode}")
+    out, st, stats = run(ens, e, 32, save_mode=mode)
+    assert (st == 0).all(), np.unique(st, return_counts=True)
+    truth, _, na, nr = oracle_solve(orc, e, tol=1e-12)
+    err = normwise(out, truth)
+    same, _, na, nr = orc.solve(orc.LORENZ, orc.TSIT5, e.params, e.u0, e.tspan, e.abstol,
+                                e.reltol, e.theta, save_mode=mode)
+    print("fp32 non-dyadic vs truth: max %.3e; attempts gpu %.1f oracle %.1f"
+          % (err.max(), stats.sum(0).mean(), (na + nr).mean()))
+    assert err.max() <= FP32_BAR
+    assert abs(stats.sum(0).mean() / (na + nr).mean() - 1.0) < 0.03
+    srt, st2, s2 = run(ens, e, 32, save_mode=mode, form=2, block=256)
+    assert np.array_equal(srt.view(np.uint8), out.view(np.uint8)) and np.array_equal(s2, stats)
 
 
 def test_robertson_fp32_rodas4(ens, orc):
