@@ -200,8 +200,7 @@ struct RosLane {
   using Time = CompTime;
   Time t;
   double t0, tf;
-  double ts;                  // next save time
-  typename Time::Mark ts_m;   // ts as the target of t.to()
+  double ts;  // next save time
   R h;
   R hmax;    // tf - t0: no step is longer
   R hfloor;  // 16 eps64 |t|: steps at or below it stop the trajectory (status 2)
@@ -222,7 +221,6 @@ struct RosLane {
       ++j;
       if (j < a.n_save) ts = save_time(a, t0, tf, j);
     }
-    ts_m = Time::mark(ts);
     if (j >= a.n_save) done = true;
   }
 
@@ -305,7 +303,7 @@ struct RosLane {
     // distance to the next save time: a longer step is cut to land on it,
     // and one ending within 10% short of it is stretched onto it (after a
     // rejected stretched step h <= 0.9 rem, so the stretch cannot repeat)
-    const R rem = (R)t.to(ts_m);
+    const R rem = (R)t.to(ts);
     const bool clamped = h * (R)kStretch >= rem;
     const R he = clamped ? rem : h;
 
