@@ -39,7 +39,11 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_dims_and_null_handling(lib):
     n, m = ctypes.c_int(), ctypes.c_int()
-    expect = {0: (3, 9), 1: (3, 3), 2: (3, 3), 3: (4, 2)}
+    # (state size, parameters per trajectory): Lorenz (sigma, rho, beta),
+    # Robertson's three rates, the GBMs' (mu, sigma), OREGO's three, HIRES's
+    # twelve and POLLU's 25 rate constants, the CRN's (S, D, tau, nu0, n, eta)
+    expect = {0: (3, 9), 1: (3, 3), 2: (3, 3), 3: (4, 2), 4: (3, 3), 5: (8, 12), 6: (20, 25),
+              7: (4, 6)}
     for sid, (nn, mm) in expect.items():
         assert lib.ens_system_dims(sid, ctypes.byref(n), ctypes.byref(m)) == 0
         assert (n.value, m.value) == (nn, mm)
@@ -67,3 +71,28 @@ def test_product_package_never_imports_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", src, flags=re.M), f
                 assert "liboracle" not in src and "oracle.h" not in src, f
+
+
+def header_constants(prefix):
+    text = open(HEADER).read()
+    return {m.group(1).lower(): int(m.group(2))
+            for m in re.finditer(r"^#define " + prefix + r"(\w+)\s+\(?(-?\d+)\)?", text, flags=re.M)}
+
+
+def test_binding_constants_match_header():
+    """The Python binding's name tables are the header's #defines: every
+    system, algorithm, option, pointer slot and error code, same values."""
+    from paper_2304_06835_amd import _native
+    assert header_constants("ENS_SYS_") == _native.SYSTEMS
+    assert header_constants("ENS_ALG_") == _native.ALGS
+    assert header_constants("ENS_OPT_") == _native.OPTS
+    assert header_constants("ENS_PTR_") == _native.PTRS
+    errs = {k: v for k, v in header_constants("ENS_").items()
+            if k in ("ok", "einval", "enomem", "edevice", "eunsupported")}
+    assert errs == {"ok": _native.ENS_OK, "einval": _native.ENS_EINVAL,
+                    "enomem": _native.ENS_ENOMEM, "edevice": _native.ENS_EDEVICE,
+                    "eunsupported": _native.ENS_EUNSUPPORTED}
+    surr = header_constants("ENS_SURR_")
+    assert {k: surr[k] for k in _native.SURR_BUFFERS} == _native.SURR_BUFFERS
+    assert surr["nparam"] == _native.SURR_NPARAM
+
