@@ -55,9 +55,11 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("ros23", "robertson"): 181,
          ("em", "gbm4"): 32, ("siea", "gbm4"): 132, ("em", "crn"): 88}
 # Tsit5 dense output, per save time read off a step (save mode 1; every save
-# but the last, which a step lands on): theta 2, the seven weight polynomials
-# b_i(theta) by Horner 7 x 7, and u + h sum_i b_i k_i for n = 3: 3 x 15 -> 96.
-DENSE_FLOPS_PER_SAVE = 96
+# but the last, which a step lands on): theta 2; h b_0(theta) by Horner 8;
+# h theta^2 2; the six other weights have no linear term, b_i = theta^2 q_i,
+# q_i by Horner 6 x 4; u + (h b_0) k_0 + (h theta^2) sum_{i>0} q_i k_i for
+# n = 3: 3 x 15 -> 81.
+DENSE_FLOPS_PER_SAVE = 81
 MLP_FLOPS_PER_QUERY = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 48)  # 288,768
 
 # MI355X published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s, FP64

@@ -183,16 +183,24 @@ struct Tsit5Lane {
       const R d = (R)((ts - (double)t.hi) - (double)t.lo);  // FP64: once per save
       if (!(d <= he)) break;
       const R th = d * ih;
-      R bt[7];
+      // b_0 = th (1 + th (B01 + th (B02 + th B03))); every other weight has
+      // no linear term, b_i = th^2 q_i with q_i = B_i1 + th (B_i2 + th B_i3),
+      // so u + he sum b_i k_i = u + (he b_0) k_0 + (he th^2) sum_{i>0} q_i k_i
+      static_assert(TD[1][0] == 0.0 && TD[2][0] == 0.0 && TD[3][0] == 0.0 && TD[4][0] == 0.0 &&
+                        TD[5][0] == 0.0 && TD[6][0] == 0.0,
+                    "the factored form needs b_i(0)' = 0 for i > 0");
+      const R hb0 =
+          he * (fma(fma(fma((R)TD[0][3], th, (R)TD[0][2]), th, (R)TD[0][1]), th, (R)TD[0][0]) * th);
+      const R hth2 = he * (th * th);
+      R q[7];
 #pragma unroll
-      for (int i = 0; i < 7; ++i)
-        bt[i] = fma(fma(fma((R)TD[i][3], th, (R)TD[i][2]), th, (R)TD[i][1]), th, (R)TD[i][0]) * th;
+      for (int i = 1; i < 7; ++i) q[i] = fma(fma((R)TD[i][3], th, (R)TD[i][2]), th, (R)TD[i][1]);
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        R acc = bt[0] * k[0][c];
+        R acc = q[1] * k[1][c];
 #pragma unroll
-        for (int i = 1; i < 7; ++i) acc = fma(bt[i], k[i][c], acc);
-        sp[c * os] = fma(he, acc, u[c]);
+        for (int i = 2; i < 7; ++i) acc = fma(q[i], k[i][c], acc);
+        sp[c * os] = fma(hth2, acc, fma(hb0, k[0][c], u[c]));
       }
       sp += N * os;
       ++j;
