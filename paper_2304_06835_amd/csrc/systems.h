@@ -12,6 +12,7 @@
 // configuration performs bit-identical operations.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "driver.h"  // Num<R>
 
 namespace ens {
 
@@ -86,7 +87,9 @@ struct Orego {
   __device__ static inline void f(const R* p, const R* u, R* du) {
     const R one = (R)1;
     du[0] = p[0] * (u[1] + u[0] * ((one - p[1] * u[0]) - u[1]));
-    du[1] = (u[2] - (one + u[0]) * u[1]) / p[0];
+    // one reciprocal of the lane-constant k1 (shared by the step's inlined
+    // calls) instead of a division per call
+    du[1] = (u[2] - (one + u[0]) * u[1]) * Num<R>::rcp(p[0]);
     du[2] = p[2] * (u[0] - u[2]);
   }
   template <class R>
@@ -94,7 +97,8 @@ struct Orego {
     const double k1 = p[0], k2 = p[1], k3 = p[2];
     const double y1 = u[0], y2 = u[1];
     J[0] = k1 * ((1.0 - 2.0 * k2 * y1) - y2); J[1] = k1 * (1.0 - y1); J[2] = 0.0;
-    J[3] = -y2 / k1;                          J[4] = -(1.0 + y1) / k1; J[5] = 1.0 / k1;
+    const double ik1 = 1.0 / k1;
+    J[3] = -y2 * ik1;                         J[4] = -(1.0 + y1) * ik1; J[5] = ik1;
     J[6] = k3;                                J[7] = 0.0;              J[8] = -k3;
   }
   static constexpr int kFlopsF = 14;
