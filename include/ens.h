@@ -233,7 +233,9 @@ int ens_philox_fill(ens_ctx *ctx, uint64_t seed, int64_t n_traj, uint32_t step,
  * (plain form with trajectories per lane in {1, 2, 4}, or persistent form
  * with refill threshold in {4, 16, 32}), and the sorted form with block in
  * {256, 512, 1024} sorting one block's worth of trajectories or block in
- * {256, 512} sorting two (ENS_OPT_TPL 2) -- on the given probe ensemble (same
+ * {256, 512} sorting two (ENS_OPT_TPL 2); the plain form alone for the SDE
+ * algorithms, and block alone for ENS_SYS_POLLU (one trajectory per 32-lane
+ * group, plain form only) -- on the given probe ensemble (same
  * arguments as ens_solve; `out` is overwritten), and set ENS_OPT_FORM,
  * ENS_OPT_BLOCK, ENS_OPT_TPL and ENS_OPT_REFILL to the fastest.  Results are
  * bitwise identical across configurations, so tuning never changes answers.

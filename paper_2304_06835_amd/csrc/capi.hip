@@ -406,12 +406,19 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
   Cand cands[64];
   int nc = 0;
   const int blocks[3] = {64, 128, 256};
+  // the grouped system (POLLU) runs one trajectory per 32-lane group in the
+  // plain form only: its launches differ by block size alone
+  const bool grouped = sys == ENS_SYS_POLLU;
   for (int b : blocks) {
+    if (grouped) {
+      cands[nc++] = {0, b, 1, 64};
+      continue;
+    }
     for (int tpl : {1, 2, 4}) cands[nc++] = {0, b, tpl, 64};
     if (!is_sde(alg))
       for (int rf : {4, 16, 32}) cands[nc++] = {1, b, 1, rf};
   }
-  if (!is_sde(alg)) {
+  if (!is_sde(alg) && !grouped) {
     for (int b : {256, 512, 1024}) cands[nc++] = {2, b, 1, 64};
     for (int b : {256, 512}) cands[nc++] = {2, b, 2, 64};  // sort over 2 * block items
   }

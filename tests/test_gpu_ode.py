@@ -280,6 +280,36 @@ def test_autotune_picks_a_valid_config_with_identical_results(ens):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("name", ["orego", "hires", "pollu", "gbm"])
+def test_autotune_on_the_other_systems(ens, name):
+    """The autotuner on the appendix problems (POLLU's grouped kernel runs its
+    plain form whatever is asked) and on an SDE (plain form only): a valid
+    configuration, and the same bits as the untuned solve afterwards."""
+    if name == "gbm":
+        e = W.gbm(N=4096)
+        s = ens.Solver(0, precision=32, dt=e.dt, seed=e.seed)
+        args = (to_dev(e.params), to_dev(e.u0), to_dev(e.tspan), "em", 0.0, 0.0, e.theta)
+    else:
+        e = W.stiff(name, N=1024)
+        s = ens.Solver(0, precision=32)
+        if e.h0:
+            s.set(h0=e.h0)
+        args = (to_dev(e.params), to_dev(e.u0), to_dev(e.tspan), e.alg, e.abstol, e.reltol,
+                e.theta)
+    banner(f"autotune {name}")
+    ref = to_host(s.solve(e.system, *args))
+    ms, cfg = s.autotune(e.system, *args)
+    print(f"autotune {name}:", ms, cfg)
+    assert ms > 0
+    if name in ("gbm", "pollu"):
+        assert cfg["form"] == 0 and cfg["block"] in (64, 128, 256)
+    if name == "pollu":
+        assert cfg["tpl"] == 1
+    out = to_host(s.solve(e.system, *args))
+    assert np.array_equal(out.view(np.uint8), ref.view(np.uint8))
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["lorenz_fp32", "robertson"])
 def test_full_size_in_the_benchmarked_launch(ens, orc, name):
     """The benchmark's workloads at their full sizes (2^24 Lorenz with 16
