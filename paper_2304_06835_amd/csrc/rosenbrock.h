@@ -36,8 +36,8 @@ __device__ inline double recip(double x) {
 
 // In-register LU with partial pivoting of an N x N FP64 matrix.  Column k
 // is pivoted by comparing row k with each row r > k in turn and swapping
-// the two when row r has the larger entry, so row k ends up holding the
-// largest.  The swaps are selects (no per-lane branches) recorded in `swp`
+// the two (in columns k..N-1) when row r has the larger entry, so row k ends
+// up holding the largest.  The swaps are selects (no per-lane branches) recorded in `swp`
 // for solve() to replay on the right-hand side.  A swap no lane of the wave
 // makes is skipped as a whole (wave-uniform branch on a ballot), and when no
 // lane swapped at all (`any` false) the solves take
@@ -60,8 +60,12 @@ struct LU {
         swp[k][r] = s;
         if (__ballot(s) != 0ull) {
           any = true;
+          // columns < k hold the multipliers of earlier columns, which stay
+          // with the row they were computed on: solve() replays this
+          // column's swaps on the right-hand side just before eliminating
+          // with column k (LINPACK's storage), so they must not move
 #pragma unroll
-          for (int c = 0; c < N; ++c) {
+          for (int c = k; c < N; ++c) {
             const double x = a[k][c], y = a[r][c];
             a[k][c] = s ? y : x;
             a[r][c] = s ? x : y;
