@@ -15,7 +15,13 @@ pytestmark = pytest.mark.gpu
 # activation's bf16 rounding (one bf16 ulp = 2^-8) for roughly one element in
 # a few hundred, so outputs differ by ~1e-3 of their scale at worst:
 FWD_BAR = 5e-3     # max |y_gpu - y_oracle| / max |y_oracle|
-GRAD_BAR = 2e-2    # per-layer ||g_gpu - g_oracle|| / ||g_oracle||
+# Gradients, element by element: dW_l = bf16(G_l)^T A_{l-1} sums products
+# whose bf16 factors may each sit one rounding (2^-8 relative) apart on the
+# two sides where an FP32-vs-FP64 difference flips a rounding; such flips are
+# rare and of both signs, so no element moves by more than one bf16 ulp of
+# the layer's largest gradient:
+#   |g_gpu - g_oracle| <= 2^-8 max |g_oracle|   over each weight / bias block.
+GRAD_BAR = 2.0**-8
 ADAM_BAR = 1e-5    # FP32 update vs FP64 update from the same gradient
 
 
@@ -121,13 +127,17 @@ def test_fused_forward_matches_tiled_path_across_many_tiles(ens, tile):
     assert np.abs(g - Y).max() / np.abs(Y).max() <= FWD_BAR
 
 
-def test_gradient_and_adam_match_oracle(ens):
+@pytest.mark.parametrize("B", [777, 65])
+def test_gradient_and_adam_match_oracle(ens, B):
+    """One training step: loss, every gradient element (B = 777: twelve
+    64-sample tiles and a 9-sample tail; B = 65: one tile and a 1-sample
+    tail, so the edge handling of the products and of the split-K weight
+    gradients is pinned), and Adam's update from the GPU's own gradient."""
     th = random_theta(2, scale=0.5)
     e = W.lorenz_fp32(N=1500, seed=12)
     rng = np.random.default_rng(3)
     y = rng.normal(0, 1, (48, e.n)).astype(np.float32)
-    B = 777                                  # ragged batch
-    banner("mlp gradient B=777")
+    banner(f"mlp gradient B={B}")
     s, m = make_model(ens, th)
     P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
     import torch
@@ -144,13 +154,53 @@ def test_gradient_and_adam_match_oracle(ens):
     lay, _ = mlp.layout()
     for li, (wo, (o, i), bo, nb) in enumerate(lay):
         for lo, hi in ((wo, wo + o * i), (bo, bo + nb)):
+            scale = np.abs(go[lo:hi]).max()
+            el = np.abs(g[lo:hi] - go[lo:hi]).max() / scale
             rel = np.linalg.norm(g[lo:hi] - go[lo:hi]) / np.linalg.norm(go[lo:hi])
-            print(f"layer {li} [{lo}:{hi}] grad rel err {rel:.3e}")
-            assert rel <= GRAD_BAR
+            print(f"layer {li} [{lo}:{hi}] grad max element err {el:.3e} of the block max "
+                  f"(norm rel {rel:.3e})")
+            assert el <= GRAD_BAR
     # Adam's first step from the GPU's own gradient
     w_exp, _, _ = mlp.adam(th, np.zeros_like(th), np.zeros_like(th), g, 1, lr)
     assert np.abs(w1 - w_exp).max() <= ADAM_BAR * max(1.0, np.abs(th).max())
     assert m.step == 1
+
+
+def test_save_load_round_trip_and_resume(ens, tmp_path):
+    """ens_surrogate_save / load: a model written after two Adam steps and
+    read into a fresh model (another seed) has the same master weights,
+    bf16 weights, Adam moments, step and normalisation bit for bit, predicts
+    the same bits, and resumes training identically; a truncated file is
+    refused and leaves the model unchanged."""
+    import torch
+    e = W.lorenz_fp32(N=1024, seed=15)
+    y = np.random.default_rng(8).normal(0, 1, (48, e.n)).astype(np.float32)
+    P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
+    s, m = make_model(ens, random_theta(6, scale=0.5))
+    m.fit_norm(P, U, Y)
+    for k in range(2):
+        m.train_step(P, U, Y, first=256 * k, batch=256, lr=1e-3)
+    path = tmp_path / "model.bin"
+    m.save_file(path)
+    m2 = ens.Surrogate(s, seed=99)
+    m2.load_file(path)
+    for b in ("master", "weights_bf16", "adam_m", "adam_v", "norm"):
+        assert np.array_equal(to_host(m.buffer(b)).view(np.uint8),
+                              to_host(m2.buffer(b)).view(np.uint8)), b
+    assert m2.step == m.step == 2
+    assert np.array_equal(to_host(m.predict(P, U)).view(np.uint8),
+                          to_host(m2.predict(P, U)).view(np.uint8))
+    for mm in (m, m2):
+        mm.train_step(P, U, Y, first=512, batch=256, lr=1e-3)
+    assert np.array_equal(to_host(m.buffer("master")).view(np.uint8),
+                          to_host(m2.buffer("master")).view(np.uint8))
+    bad = tmp_path / "short.bin"
+    bad.write_bytes(path.read_bytes()[:1000])
+    before = to_host(m2.buffer("master"))
+    with pytest.raises(ens.EnsError, match="not a surrogate file"):
+        m2.load_file(bad)
+    assert np.array_equal(to_host(m2.buffer("master")), before) and m2.step == 3
+    torch.cuda.synchronize()
 
 
 def test_affine_minibatch_selection(ens):

@@ -280,6 +280,53 @@ def test_autotune_picks_a_valid_config_with_identical_results(ens):
     torch.cuda.synchronize()
 
 
+def test_autotune_cache_and_file_round_trip(ens, tmp_path):
+    """The autotuner's results are cached per (system, algorithm, precision,
+    save mode, log2 n): a second call on the same key sets the recorded
+    configuration without timing and reports the recorded time; the JSON
+    file carries the entries to a new context; another size bucket is tuned
+    anew and added; a malformed file is refused; clearing the cache tunes
+    again."""
+    import json
+    import time
+    e = W.lorenz_fp32(N=1 << 14)
+    path = tmp_path / "tune.json"
+    s = ens.Solver(0, precision=32, save_mode=1)
+    s.set_autotune_file(path)
+    args = (to_dev(e.params), to_dev(e.u0), to_dev(e.tspan), "tsit5", 1e-6, 1e-6, e.theta)
+    ms1, cfg1 = s.autotune("lorenz", *args)
+    assert not cfg1["cached"]
+    rec = json.loads(path.read_text())["entries"]
+    assert len(rec) == 1 and rec[0]["sys"] == 1 and rec[0]["save_mode"] == 1
+    assert rec[0]["log2n"] == 14 and rec[0]["form"] == cfg1["form"]
+    s.set(form=0, block=64, tpl=1)
+    t0 = time.perf_counter()
+    ms2, cfg2 = s.autotune("lorenz", *args)
+    hit_s = time.perf_counter() - t0
+    assert cfg2["cached"] and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert {k: cfg2[k] for k in ("form", "block", "tpl")} == \
+        {k: cfg1[k] for k in ("form", "block", "tpl")}
+    assert hit_s < 0.05, hit_s
+    s2 = ens.Solver(0, precision=32, save_mode=1)
+    s2.set_autotune_file(path)
+    ms3, cfg3 = s2.autotune("lorenz", *args)
+    assert cfg3["cached"] and cfg3["form"] == cfg1["form"] and cfg3["block"] == cfg1["block"]
+    small = W.lorenz_fp32(N=1 << 12)
+    _, cfg4 = s2.autotune("lorenz", to_dev(small.params), to_dev(small.u0), to_dev(small.tspan),
+                          "tsit5", 1e-6, 1e-6, small.theta)
+    assert not cfg4["cached"]
+    assert sorted(r["log2n"] for r in json.loads(path.read_text())["entries"]) == [12, 14]
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"version": 1, "entries": [{"sys": 1}]}')
+    with pytest.raises(ens.EnsError, match="malformed"):
+        s2.set_autotune_file(bad)
+    s.set_autotune_file(None)
+    _, cfg5 = s.autotune("lorenz", *args)
+    assert not cfg5["cached"]
+    s.close()
+    s2.close()
+
+
 @pytest.mark.parametrize("name", ["orego", "hires", "pollu", "gbm"])
 def test_autotune_on_the_other_systems(ens, name):
     """The autotuner on the appendix problems (POLLU's grouped kernel runs its
@@ -312,24 +359,28 @@ def test_autotune_on_the_other_systems(ens, name):
 
 @pytest.mark.parametrize("name", ["lorenz_fp32", "robertson"])
 def test_full_size_in_the_benchmarked_launch(ens, orc, name):
-    """The benchmark's workloads at their full sizes (2^24 Lorenz with 16
-    saves, 2^20 Robertson) in the launch configuration bench.py times (the
-    cost-sorted form, block 256): every trajectory finishes with status 0,
-    and 4096 sampled trajectories match the FP64 oracle at tol 1e-12 within
-    the FP32 bar; the persistent form gives the same bits on the sample."""
+    """The benchmark's workloads at their full sizes in exactly the launch
+    bench.py times: 2^24 Lorenz with 16 saves read off Tsit5's dense output
+    (save mode 1) in the cost-sorted form with block 256, and 2^20 Robertson
+    (Rodas4, landing saves) in the same form.  Every trajectory finishes with
+    status 0, 4096 sampled trajectories match the FP64 oracle at tol 1e-12
+    within the FP32 bar, and the plain and persistent forms in the same save
+    mode give the same bits on the sample."""
     import torch
     e = W.lorenz_fp32() if name == "lorenz_fp32" else W.robertson()
-    banner(f"{name} full size N={e.n}, sorted form")
-    s = ens.Solver(0, precision=32, form=2, block=256)
+    mode = 1 if name == "lorenz_fp32" else 0
+    banner(f"{name} full size N={e.n}, sorted form block 256, save mode {mode}")
+    s = ens.Solver(0, precision=32, form=2, block=256, save_mode=mode)
     if e.h0:
         s.set(h0=e.h0)
     status = torch.empty(e.n, dtype=torch.uint8, device="cuda")
     P, U, T = to_dev(e.params), to_dev(e.u0), to_dev(e.tspan)
+    idx = W.sample_indices(e.n, 4096)
+    idx_d = torch.from_numpy(idx.astype(np.int64)).cuda()
     out = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta, status=status)
     st = to_host(status)
     assert (st == 0).all()
-    idx = W.sample_indices(e.n, 4096)
-    got = np.ascontiguousarray(to_host(out)[:, :, idx])
+    got = np.ascontiguousarray(to_host(out.index_select(2, idx_d)))
     sub = W.Ensemble(e.name, e.system, e.alg, np.ascontiguousarray(e.params[:, idx]),
                      np.ascontiguousarray(e.u0[:, idx]), np.ascontiguousarray(e.tspan[:, idx]),
                      e.theta, e.abstol, e.reltol, e.h0)
@@ -337,11 +388,12 @@ def test_full_size_in_the_benchmarked_launch(ens, orc, name):
     err = normwise(got, truth)
     print("%s full size, sampled: max normwise error %.3e" % (name, err.max()))
     assert err.max() <= FP32_BAR
-    del out
-    s.set(form=1, block=256)
-    out1 = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta)
-    got1 = np.ascontiguousarray(to_host(out1)[:, :, idx])
-    assert np.array_equal(got1.view(np.uint8), got.view(np.uint8))
+    for form in (0, 1):
+        s.set(form=form, block=256)
+        o = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta, out=out)
+        g = np.ascontiguousarray(to_host(o.index_select(2, idx_d)))
+        assert np.array_equal(g.view(np.uint8), got.view(np.uint8)), form
+    s.close()
 
 
 def test_dense_output_fp64_matches_oracle(ens, orc):

@@ -126,6 +126,65 @@ def test_crn_noise_matrix(orc):
         assert np.array_equal(orc.sde_step(orc.CRN, orc.EM, p, xneg, 0.1, np.eye(8)[j]), b0)
 
 
+def crn_reactions():
+    """The sigma-factor CRN of the paper's appendix as Gillespie's chemical
+    Langevin equation (the construction the appendix cites): eight
+    production / decay reactions read off the drift, each changing one
+    species by +-1, with propensities a_r(x) >= 0 --
+      s:  0 -> s at nu0 + H(s, A3),   s -> 0 at s,
+      Ak: 0 -> Ak at A(k-1) / tau,    Ak -> 0 at Ak / tau   (A0 = s),
+    H = (S s)^n / ((S s)^n + (D A3)^n + 1).  The CLE is then
+      dX = sum_r nu_r a_r dt + eta sum_r nu_r sqrt(a_r) dW_r."""
+    def hill(x, p):
+        S, D, tau, nu0, n, eta = p
+        hs, hd = (S * x[0]) ** n, (D * x[3]) ** n
+        return hs / (hs + hd + 1.0)
+    R = [(0, +1, lambda x, p: p[3] + hill(x, p)), (0, -1, lambda x, p: x[0])]
+    for k in (1, 2, 3):
+        R.append((k, +1, lambda x, p, k=k: x[k - 1] / p[2]))
+        R.append((k, -1, lambda x, p, k=k: x[k] / p[2]))
+    return R
+
+
+def test_crn_is_the_chemical_langevin_equation(orc):
+    """Pin of the CRN's drift and diffusion independent of how the oracle
+    writes them: at random positive states and parameters, the oracle's
+    Euler-Maruyama step has drift sum_r a_r nu_r and a noise matrix b (read
+    off with unit increments) whose covariance b b^T is
+    eta^2 sum_r a_r nu_r nu_r^T, the CLE's; and each column of b is
+    eta sqrt(a_r) nu_r of one reaction r, every reaction once."""
+    rng = np.random.default_rng(17)
+    R = crn_reactions()
+    h = 0.05
+    for _ in range(50):
+        p = [rng.uniform(0.1, 100), rng.uniform(0.1, 100), rng.uniform(0.1, 100),
+             rng.uniform(0.01, 0.2), rng.uniform(2, 4), rng.uniform(0.001, 0.1)]
+        x = rng.uniform(0.01, 2.0, 4)
+        eta = p[5]
+        base = orc.sde_step(orc.CRN, orc.EM, p, x, h, np.zeros(8))
+        drift = (base - x) / h
+        nu = np.zeros((len(R), 4))
+        a = np.empty(len(R))
+        for r, (c, sgn, prop) in enumerate(R):
+            nu[r, c] = sgn
+            a[r] = prop(x, p)
+        assert np.all(a >= 0)
+        f = nu.T @ a
+        assert np.abs(drift - f).max() <= 1e-9 * max(1.0, np.abs(f).max()), (drift, f)
+        B = np.empty((4, 8))
+        for j in range(8):
+            B[:, j] = orc.sde_step(orc.CRN, orc.EM, p, x, h, np.eye(8)[j]) - base
+        cov = eta ** 2 * (nu.T * a) @ nu
+        assert np.abs(B @ B.T - cov).max() <= 1e-12 * np.abs(cov).max()
+        cols = [eta * np.sqrt(a[r]) * nu[r] for r in range(len(R))]
+        used = set()
+        for j in range(8):
+            hit = [r for r in range(len(R)) if r not in used
+                   and np.abs(B[:, j] - cols[r]).max() <= 1e-12 * np.abs(cols[r]).max()]
+            assert hit, (j, B[:, j])
+            used.add(hit[0])
+
+
 def test_em_gbm_unchanged_by_the_general_path(orc):
     rng = np.random.default_rng(3)
     P = np.stack([rng.uniform(-.5, .5, 64), rng.uniform(.05, .5, 64)])
