@@ -49,6 +49,11 @@ typedef struct ens_ctx ens_ctx;
 #define ENS_EDEVICE (-3)      /* a HIP call failed                             */
 #define ENS_EUNSUPPORTED (-4) /* valid but unsupported (system, alg, precision) */
 
+/* Largest ensemble of one call: 2^32 - 2^11 trajectories (2^27 - 64 for
+ * ENS_SYS_POLLU, which takes a 32-lane group per trajectory), so that every
+ * launch's work-items fit the 32-bit dispatch size.  Larger n: ENS_EINVAL. */
+#define ENS_MAX_TRAJ 4294965248LL
+
 /* ---- systems (compile-time right-hand sides and analytic Jacobians) ------
  *                         n  m   params rows
  * ENS_SYS_LINEAR          3  9   A row-major: du = A u
@@ -151,6 +156,9 @@ typedef struct ens_ctx ens_ctx;
                                   the LDS it holds lowers the blocks resident
                                   per CU.  0 (default): saves are stored
                                   directly.  Results are bitwise identical.   */
+#define ENS_OPT_AUTOTUNE_CACHED 15 /* read-only (ens_get_option): 1 when the
+                                      last ens_autotune was answered from the
+                                      autotune cache without timing, else 0 */
 
 /* ---- pointer options (ens_set_ptr); NULL disables ------------------------ */
 #define ENS_PTR_STATUS 1 /* uint8 [N]: 0 ok, 1 maxiters, 2 step below 16 eps|t|,
@@ -246,6 +254,21 @@ int ens_autotune(ens_ctx *ctx, int system_id, int64_t n_traj,
                  int alg, double abstol, double reltol,
                  const double *save_times, int n_save, void *out, void *stream,
                  double *best_ms);
+/*
+ * The autotuner's results are cached in the context, keyed by (system_id,
+ * alg, ENS_OPT_PRECISION, ENS_OPT_SAVE_MODE, floor(log2 n_traj)) -- the
+ * occupancy-driven launch tuning of section 5.1.2 done once per problem
+ * class instead of once per call.  A key already in the cache is answered
+ * without timing anything: the stored configuration is set, *best_ms gets
+ * its recorded time, ENS_OPT_AUTOTUNE_CACHED reads 1, and nothing is
+ * enqueued.  ens_set_autotune_file attaches a JSON file to the cache: the
+ * in-memory cache is replaced by the file's entries for this device
+ * (architecture name and CU count; a missing file is an empty cache), and
+ * every new result rewrites the file (entries of other devices are kept).
+ * path NULL clears the cache and detaches the file.  ENS_EINVAL for an
+ * unreadable or malformed file, or one that cannot be written.
+ */
+int ens_set_autotune_file(ens_ctx *ctx, const char *path);
 
 /* ==========================================================================
  * Learned surrogate: a multilayer perceptron (rho, x0, y0, z0) -> 256 -> 256
@@ -289,6 +312,16 @@ int ens_surrogate_destroy(ens_surrogate *s);
  * Writing ENS_SURR_MASTER also refreshes the bfloat16 weights.               */
 int ens_surrogate_copy(ens_ctx *ctx, ens_surrogate *s, int which, void *dev_ptr,
                        int to_model, void *stream);
+/* Write the model -- FP32 master weights, Adam moments and step, and the
+ * normalisation -- to a file, or read one back into a model (the bfloat16
+ * weights are re-derived), so training can resume and a trained surrogate
+ * can be served by another process.  Format: "ENSSURR1", uint32 version (1),
+ * uint32 parameter count, int64 Adam step, uint32 normalisation size (160),
+ * then the float32 arrays master, m, v, norm (little-endian).  Both
+ * synchronise the device.  ENS_EINVAL for an unreadable, unwritable or
+ * mismatched file (the model is then unchanged).                           */
+int ens_surrogate_save(ens_ctx *ctx, ens_surrogate *s, const char *path);
+int ens_surrogate_load(ens_ctx *ctx, ens_surrogate *s, const char *path);
 /* Adam step counter (bias correction); restored with the moments on resume. */
 int ens_surrogate_get_step(const ens_surrogate *s, int64_t *step);
 int ens_surrogate_set_step(ens_surrogate *s, int64_t step);

@@ -144,7 +144,13 @@ class Solver:
                                          reltol, th, ns, out.data_ptr(), s,
                                          ctypes.byref(best)))
         cfg = {k: int(self.get(k)) for k in ("form", "block", "tpl", "refill")}
+        cfg["cached"] = bool(self.get("autotune_cached"))
         return best.value, cfg
+
+    def set_autotune_file(self, path: Optional[str]):
+        """Persist autotuner results to a JSON file (None: clear the cache)."""
+        self._check(self._L.ens_set_autotune_file(
+            self._ctx, None if path is None else str(path).encode()))
 
 
 _default = {}
@@ -222,6 +228,14 @@ class Surrogate:
         assert t.is_cuda and t.is_contiguous()
         self._c(self._L.ens_surrogate_copy(self.solver._ctx, self._s, _native.SURR_BUFFERS[which],
                                            t.data_ptr(), 1, self._stream(stream)))
+
+    def save_file(self, path):
+        """Write weights, Adam state and normalisation to `path` (ens_surrogate_save)."""
+        self._c(self._L.ens_surrogate_save(self.solver._ctx, self._s, str(path).encode()))
+
+    def load_file(self, path):
+        """Read a model written by save_file (ens_surrogate_load)."""
+        self._c(self._L.ens_surrogate_load(self.solver._ctx, self._s, str(path).encode()))
 
     @property
     def step(self) -> int:

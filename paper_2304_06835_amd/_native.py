@@ -13,16 +13,18 @@ SYSTEMS = {"linear": 0, "lorenz": 1, "robertson": 2, "gbm4": 3, "orego": 4, "hir
 ALGS = {"tsit5": 1, "rodas4": 2, "em": 3, "ros23": 4, "siea": 5}
 OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
         "maxiters": 7, "tspan_broadcast": 8, "refill": 9, "grid": 10, "tpl": 11,
-        "mlp_tile": 12, "save_mode": 13, "stage_saves": 14}
+        "mlp_tile": 12, "save_mode": 13, "stage_saves": 14, "autotune_cached": 15}
 PTRS = {"status": 1, "stats": 2}
+MAX_TRAJ = (1 << 32) - (1 << 11)  # ENS_MAX_TRAJ
 
 # Every symbol include/ens.h declares.
 EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
            "ens_get_option", "ens_set_ptr", "ens_system_dims", "ens_solve",
-           "ens_autotune", "ens_philox_fill", "ens_surrogate_create", "ens_surrogate_destroy",
+           "ens_autotune", "ens_set_autotune_file", "ens_philox_fill", "ens_surrogate_create", "ens_surrogate_destroy",
            "ens_surrogate_copy", "ens_surrogate_get_step", "ens_surrogate_set_step",
            "ens_surrogate_fit_norm", "ens_surrogate_train_step", "ens_surrogate_train",
-           "ens_surrogate_predict", "ens_surrogate_solve")
+           "ens_surrogate_predict", "ens_surrogate_solve", "ens_surrogate_save",
+           "ens_surrogate_load")
 SURR_BUFFERS = {"master": 1, "weights_bf16": 2, "grad": 3, "adam_m": 4, "adam_v": 5, "norm": 6}
 SURR_NPARAM = 145200
 
@@ -59,11 +61,14 @@ def lib() -> ctypes.CDLL:
     L.ens_solve.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp]
     L.ens_autotune.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp,
                                dp]
+    L.ens_set_autotune_file.argtypes = [vp, ctypes.c_char_p]
     L.ens_philox_fill.argtypes = [vp, ctypes.c_uint64, i64, ctypes.c_uint32, vp, vp]
     u64 = ctypes.c_uint64
     L.ens_surrogate_create.argtypes = [vp, u64, ctypes.POINTER(vp)]
     L.ens_surrogate_destroy.argtypes = [vp]
     L.ens_surrogate_copy.argtypes = [vp, vp, c_int, vp, c_int, vp]
+    L.ens_surrogate_save.argtypes = [vp, vp, ctypes.c_char_p]
+    L.ens_surrogate_load.argtypes = [vp, vp, ctypes.c_char_p]
     L.ens_surrogate_get_step.argtypes = [vp, ctypes.POINTER(i64)]
     L.ens_surrogate_set_step.argtypes = [vp, i64]
     L.ens_surrogate_fit_norm.argtypes = [vp, vp, vp, vp, vp, i64, vp]

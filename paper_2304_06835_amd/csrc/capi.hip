@@ -83,8 +83,12 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
     return fail(c, ENS_EUNSUPPORTED, "dense output (save mode 1) is implemented for Tsit5 only");
   if (is_sde(alg) && c->precision != 32)
     return fail(c, ENS_EUNSUPPORTED, "the SDE kernels are built for precision 32 only");
-  if (n < 0 || n > (int64_t(1) << 40))
-    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
+  // a dispatch counts its work-items in 32 bits: one lane per trajectory,
+  // or a 32-lane group per trajectory for the grouped system
+  const int64_t lanes = sys == ENS_SYS_POLLU ? 32 : 1;
+  if (n < 0 || n > ENS_MAX_TRAJ / lanes)
+    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, %lld] for system %d", (long long)n,
+                (long long)(ENS_MAX_TRAJ / lanes), sys);
   if (n_save < 1 || n_save > ens::kMaxSave)
     return fail(c, ENS_EINVAL, "n_save %d out of range [1, %d]", n_save, ens::kMaxSave);
   if (!theta) return fail(c, ENS_EINVAL, "null save_times pointer");
@@ -191,6 +195,120 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
 
 namespace {
 
+// ---- autotune cache: entries keyed by (system, algorithm, precision, save
+// mode, floor(log2 n)) for one device signature, persisted as a small JSON
+// file {"version": 1, "entries": [{"device": "...", "sys": ..., ...}, ...]}.
+
+int log2_bucket(int64_t n) {
+  int b = 0;
+  while (b < 62 && (int64_t(1) << (b + 1)) <= n) ++b;
+  return b;
+}
+
+// Number after "\"key\":" inside obj, or false.
+bool json_num(const std::string& obj, const char* key, double* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  const char* s = obj.c_str() + p + 1;
+  char* end = nullptr;
+  *v = std::strtod(s, &end);
+  return end != s;
+}
+
+bool json_str(const std::string& obj, const char* key, std::string* v) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  const size_t q0 = obj.find('"', p + 1);
+  if (q0 == std::string::npos) return false;
+  const size_t q1 = obj.find('"', q0 + 1);
+  if (q1 == std::string::npos) return false;
+  *v = obj.substr(q0 + 1, q1 - q0 - 1);
+  return true;
+}
+
+// Entries of this device from a cache file; a missing file is an empty cache.
+int tune_load(ens_ctx* c, const std::string& path) {
+  c->tune.clear();
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return ENS_OK;
+  std::string text;
+  char buf[4096];
+  size_t r;
+  while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+  std::fclose(f);
+  const size_t e = text.find("\"entries\"");
+  if (e == std::string::npos)
+    return fail(c, ENS_EINVAL, "autotune cache %s: no \"entries\" array", path.c_str());
+  size_t p = text.find('[', e);
+  while (p != std::string::npos) {
+    const size_t a = text.find('{', p);
+    if (a == std::string::npos) break;
+    const size_t b = text.find('}', a);
+    if (b == std::string::npos) break;
+    const std::string obj = text.substr(a, b - a + 1);
+    std::string dev;
+    double v[10];
+    const char* keys[10] = {"sys", "alg", "prec", "save_mode", "log2n",
+                            "form", "block", "tpl", "refill", "ms"};
+    bool ok = json_str(obj, "device", &dev);
+    for (int k = 0; k < 10 && ok; ++k) ok = json_num(obj, keys[k], &v[k]);
+    if (!ok) return fail(c, ENS_EINVAL, "autotune cache %s: malformed entry", path.c_str());
+    if (dev == c->dev_sig)
+      c->tune.push_back({(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5],
+                         (int)v[6], (int)v[7], (int)v[8], v[9]});
+    p = b + 1;
+  }
+  return ENS_OK;
+}
+
+// Rewrite the file: entries of other devices are kept as they were.
+int tune_store(ens_ctx* c) {
+  if (c->tune_path.empty()) return ENS_OK;
+  std::string others;
+  if (FILE* f = std::fopen(c->tune_path.c_str(), "rb")) {
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+    std::fclose(f);
+    size_t p = text.find("\"entries\"");
+    while (p != std::string::npos) {
+      const size_t a = text.find('{', p);
+      if (a == std::string::npos) break;
+      const size_t b = text.find('}', a);
+      if (b == std::string::npos) break;
+      const std::string obj = text.substr(a, b - a + 1);
+      std::string dev;
+      if (json_str(obj, "device", &dev) && dev != c->dev_sig) others += "    " + obj + ",\n";
+      p = b + 1;
+    }
+  }
+  const std::string tmp = c->tune_path + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(c, ENS_EINVAL, "cannot write autotune cache %s", tmp.c_str());
+  std::fprintf(f, "{\"version\": 1, \"entries\": [\n%s", others.c_str());
+  for (size_t k = 0; k < c->tune.size(); ++k) {
+    const ens_tune_entry& t = c->tune[k];
+    std::fprintf(f,
+                 "    {\"device\": \"%s\", \"sys\": %d, \"alg\": %d, \"prec\": %d, "
+                 "\"save_mode\": %d, \"log2n\": %d, \"form\": %d, \"block\": %d, "
+                 "\"tpl\": %d, \"refill\": %d, \"ms\": %.6g}%s\n",
+                 c->dev_sig.c_str(), t.sys, t.alg, t.prec, t.save_mode, t.log2n, t.form, t.block,
+                 t.tpl, t.refill, t.ms, k + 1 < c->tune.size() ? "," : "");
+  }
+  std::fprintf(f, "]}\n");
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), c->tune_path.c_str()) != 0)
+    return fail(c, ENS_EINVAL, "cannot write autotune cache %s", c->tune_path.c_str());
+  return ENS_OK;
+}
+
 ens::LaunchCfg current_cfg(const ens_ctx* c) {
   ens::LaunchCfg cfg;
   cfg.form = c->form;
@@ -241,6 +359,7 @@ int ens_create(ens_ctx** out, int device) {
     return ENS_EDEVICE;
   }
   c->num_cu = prop.multiProcessorCount;
+  c->dev_sig = std::string(prop.gcnArchName) + "/" + std::to_string(c->num_cu);
   if (hipMalloc(&c->queue, 256) != hipSuccess) {
     delete c;
     return ENS_ENOMEM;
@@ -320,6 +439,8 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       if (v != 0 && v != 1) return fail(c, ENS_EINVAL, "stage_saves must be 0 or 1");
       c->stage_saves = (int)v;
       return ENS_OK;
+    case ENS_OPT_AUTOTUNE_CACHED:
+      return fail(c, ENS_EINVAL, "option %d is read-only", key);
     case ENS_OPT_MLP_TILE:
       if (v != 0 && v != 2 && v != 3 && v != 4 && v != 12 && v != 13)
         return fail(c, ENS_EINVAL, "mlp tile must be 0, 2, 3, 4, 12 or 13");
@@ -346,6 +467,7 @@ int ens_get_option(const ens_ctx* c, int key, double* v) {
     case ENS_OPT_MLP_TILE: *v = c->mlp_tile; return ENS_OK;
     case ENS_OPT_SAVE_MODE: *v = c->save_mode; return ENS_OK;
     case ENS_OPT_STAGE_SAVES: *v = c->stage_saves; return ENS_OK;
+    case ENS_OPT_AUTOTUNE_CACHED: *v = c->tune_cached; return ENS_OK;
   }
   return ENS_EINVAL;
 }
@@ -377,8 +499,9 @@ int ens_philox_fill(ens_ctx* c, uint64_t seed, int64_t n, uint32_t step, uint32_
                     void* stream) {
   if (!c) return ENS_EINVAL;
   c->err.clear();
-  if (n < 0 || n > (int64_t(1) << 40))
-    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, 2^40]", (long long)n);
+  if (n < 0 || n > ENS_MAX_TRAJ)
+    return fail(c, ENS_EINVAL, "n_traj %lld out of range [0, %lld]", (long long)n,
+                (long long)ENS_MAX_TRAJ);
   if (n == 0) return ENS_OK;
   if (!out) return fail(c, ENS_EINVAL, "null out pointer");
   DeviceGuard g(c->device);
@@ -396,6 +519,20 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
   int rc = check_problem(c, sys, n, params, u0, tspan, alg, atol, rtol, theta, n_save, out);
   if (rc != ENS_OK) return rc;
   if (n == 0) return fail(c, ENS_EINVAL, "autotune needs a non-empty probe ensemble");
+  c->tune_cached = 0;
+  const int log2n = log2_bucket(n);
+  for (const ens_tune_entry& t : c->tune) {
+    if (t.sys == sys && t.alg == alg && t.prec == c->precision && t.save_mode == c->save_mode &&
+        t.log2n == log2n) {
+      c->form = t.form;
+      c->block = t.block;
+      c->tpl = t.tpl;
+      if (t.form == 1) c->refill = t.refill;
+      if (best_ms) *best_ms = t.ms;
+      c->tune_cached = 1;
+      return ENS_OK;
+    }
+  }
   DeviceGuard g(c->device);
   if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -458,7 +595,18 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
   c->tpl = win.tpl;
   if (win.form == 1) c->refill = win.refill;
   if (best_ms) *best_ms = best;
-  return ENS_OK;
+  c->tune.push_back({sys, alg, c->precision, c->save_mode, log2n, win.form, win.block, win.tpl,
+                     win.refill, best});
+  return tune_store(c);
+}
+
+int ens_set_autotune_file(ens_ctx* c, const char* path) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  c->tune.clear();
+  c->tune_path = path ? path : "";
+  if (!path) return ENS_OK;
+  return tune_load(c, c->tune_path);
 }
 
 }  // extern "C"

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 namespace ens {
 
@@ -75,6 +76,13 @@ hipError_t reset_queue(unsigned long long* q, hipStream_t s);
 
 }  // namespace ens
 
+// One autotuner result: the launch that was fastest for a problem class.
+struct ens_tune_entry {
+  int sys, alg, prec, save_mode, log2n;  // the key
+  int form, block, tpl, refill;          // the winning launch
+  double ms;                             // its time on the probe ensemble
+};
+
 // The context behind the opaque ens_ctx handle of include/ens.h.
 struct ens_ctx {
   int device = 0;
@@ -96,6 +104,10 @@ struct ens_ctx {
   uint8_t* status = nullptr;
   int32_t* stats = nullptr;
   unsigned long long* queue = nullptr;  // device workspace: persistent work counter
+  std::vector<ens_tune_entry> tune;     // autotuner results of this device
+  std::string tune_path;                // file the results persist to ("" = none)
+  std::string dev_sig;                  // device architecture and CU count
+  int tune_cached = 0;                  // the last ens_autotune was a cache hit
   std::string err;
 };
 

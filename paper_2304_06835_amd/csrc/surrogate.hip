@@ -5,7 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <new>
+#include <string>
 
 #include "../../include/ens.h"
 #include "ens_internal.h"
@@ -394,6 +398,82 @@ int ens_surrogate_copy(ens_ctx* c, ens_surrogate* s, int which, void* p, int to_
   return e == hipSuccess ? ENS_OK : fail(c, ENS_EDEVICE, "%s", hipGetErrorString(e));
 }
 
+// File image: "ENSSURR1", uint32 version 1, uint32 parameter count, int64
+// Adam step, uint32 normalisation size, then FP32 master weights, Adam
+// first and second moments and the normalisation, little-endian.
+int ens_surrogate_save(ens_ctx* c, ens_surrogate* s, const char* path) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (!path) return fail(c, ENS_EINVAL, "null path");
+  DeviceGuard g(c->device);
+  const size_t P = (size_t)s->L.total;
+  float* h = static_cast<float*>(std::malloc(sizeof(float) * (3 * P + ens::kNormSize)));
+  if (!h) return fail(c, ENS_ENOMEM, "cannot allocate host staging for the model");
+  bool ok = hipDeviceSynchronize() == hipSuccess &&
+            hipMemcpy(h, s->w, sizeof(float) * P, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(h + P, s->m, sizeof(float) * P, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(h + 2 * P, s->v, sizeof(float) * P, hipMemcpyDeviceToHost) == hipSuccess &&
+            hipMemcpy(h + 3 * P, s->norm, sizeof(float) * ens::kNormSize,
+                      hipMemcpyDeviceToHost) == hipSuccess;
+  if (!ok) {
+    std::free(h);
+    return fail(c, ENS_EDEVICE, "cannot read the model from the device");
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) {
+    std::free(h);
+    return fail(c, ENS_EINVAL, "cannot open %s for writing", tmp.c_str());
+  }
+  const uint32_t ver = 1, np = (uint32_t)P, nn = (uint32_t)ens::kNormSize;
+  const int64_t step = s->step;
+  ok = std::fwrite("ENSSURR1", 1, 8, f) == 8 && std::fwrite(&ver, 4, 1, f) == 1 &&
+       std::fwrite(&np, 4, 1, f) == 1 && std::fwrite(&step, 8, 1, f) == 1 &&
+       std::fwrite(&nn, 4, 1, f) == 1 &&
+       std::fwrite(h, sizeof(float), 3 * P + nn, f) == 3 * P + nn;
+  ok = (std::fclose(f) == 0) && ok;
+  std::free(h);
+  if (!ok || std::rename(tmp.c_str(), path) != 0)
+    return fail(c, ENS_EINVAL, "cannot write %s", path);
+  return ENS_OK;
+}
+
+int ens_surrogate_load(ens_ctx* c, ens_surrogate* s, const char* path) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (!path) return fail(c, ENS_EINVAL, "null path");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, ENS_EINVAL, "cannot open %s", path);
+  const size_t P = (size_t)s->L.total;
+  char magic[8];
+  uint32_t ver = 0, np = 0, nn = 0;
+  int64_t step = 0;
+  bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "ENSSURR1", 8) == 0 &&
+            std::fread(&ver, 4, 1, f) == 1 && std::fread(&np, 4, 1, f) == 1 &&
+            std::fread(&step, 8, 1, f) == 1 && std::fread(&nn, 4, 1, f) == 1 && ver == 1 &&
+            np == (uint32_t)P && nn == (uint32_t)ens::kNormSize && step >= 0;
+  float* h = ok ? static_cast<float*>(std::malloc(sizeof(float) * (3 * P + nn))) : nullptr;
+  ok = ok && h && std::fread(h, sizeof(float), 3 * P + nn, f) == 3 * P + nn &&
+       std::fgetc(f) == EOF;
+  std::fclose(f);
+  if (!ok) {
+    std::free(h);
+    return fail(c, ENS_EINVAL, "%s is not a surrogate file of this architecture", path);
+  }
+  DeviceGuard g(c->device);
+  ok = hipDeviceSynchronize() == hipSuccess &&
+       hipMemcpy(s->w, h, sizeof(float) * P, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(s->m, h + P, sizeof(float) * P, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(s->v, h + 2 * P, sizeof(float) * P, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(s->norm, h + 3 * P, sizeof(float) * nn, hipMemcpyHostToDevice) == hipSuccess &&
+       ens::mlp_to_bf16(s->w, s->wb, s->L.total, nullptr) == hipSuccess &&
+       hipDeviceSynchronize() == hipSuccess;
+  std::free(h);
+  if (!ok) return fail(c, ENS_EDEVICE, "cannot write the model to the device");
+  s->step = step;
+  return ENS_OK;
+}
+
 int ens_surrogate_set_step(ens_surrogate* s, int64_t step) {
   if (!s || step < 0) return ENS_EINVAL;
   s->step = step;
@@ -410,7 +490,8 @@ int ens_surrogate_fit_norm(ens_ctx* c, ens_surrogate* s, const float* params, co
                            const float* y, int64_t n, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 2 || !params || !u0 || !y) return fail(c, ENS_EINVAL, "need n >= 2 and device arrays");
+  if (n < 2 || n > ENS_MAX_TRAJ || !params || !u0 || !y)
+    return fail(c, ENS_EINVAL, "need 2 <= n <= ENS_MAX_TRAJ and device arrays");
   DeviceGuard g(c->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   ens::RowSet in{}, outr{};
@@ -430,7 +511,8 @@ int ens_surrogate_train_step(ens_ctx* c, ens_surrogate* s, const float* params, 
                              uint64_t mult, uint64_t add, double lr, float* loss, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 1 || batch < 1 || !params || !u0 || !y || !(lr >= 0.0))
+  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > ENS_MAX_TRAJ || !params || !u0 || !y ||
+      !(lr >= 0.0))
     return fail(c, ENS_EINVAL, "bad training arguments");
   if (gcd(mult % (uint64_t)n, (uint64_t)n) != 1 && n > 1)
     return fail(c, ENS_EINVAL, "mult must be coprime with n (a permutation of the set)");
@@ -444,7 +526,7 @@ int ens_surrogate_train(ens_ctx* c, ens_surrogate* s, const float* params, const
                         double lr_min, uint64_t seed, float* epoch_loss, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 1 || batch < 1 || batch > n || epochs < 1 || !params || !u0 || !y ||
+  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > n || epochs < 1 || !params || !u0 || !y ||
       !(lr_max >= lr_min) || !(lr_min >= 0.0))
     return fail(c, ENS_EINVAL, "bad training arguments");
   DeviceGuard g(c->device);
@@ -473,7 +555,7 @@ int ens_surrogate_predict(ens_ctx* c, ens_surrogate* s, const float* params, con
                           int64_t n, float* out, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 0) return fail(c, ENS_EINVAL, "n < 0");
+  if (n < 0 || n > ENS_MAX_TRAJ) return fail(c, ENS_EINVAL, "n out of range [0, ENS_MAX_TRAJ]");
   if (n == 0) return ENS_OK;
   if (!params || !u0 || !out) return fail(c, ENS_EINVAL, "null device array");
   DeviceGuard g(c->device);
@@ -487,7 +569,7 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
                         uint8_t* used_solver, float* report, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 0) return fail(c, ENS_EINVAL, "n < 0");
+  if (n < 0 || n > ENS_MAX_TRAJ) return fail(c, ENS_EINVAL, "n out of range [0, ENS_MAX_TRAJ]");
   if (n_save * 3 != kDims[4]) return fail(c, ENS_EINVAL, "the surrogate predicts 16 save times");
   if (!(audit_frac >= 0.0 && audit_frac <= 1.0) || !(fallback_tol > 0.0))
     return fail(c, ENS_EINVAL, "audit_frac in [0, 1] and fallback_tol > 0 required");

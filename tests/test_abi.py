@@ -92,6 +92,7 @@ def test_binding_constants_match_header():
     assert errs == {"ok": _native.ENS_OK, "einval": _native.ENS_EINVAL,
                     "enomem": _native.ENS_ENOMEM, "edevice": _native.ENS_EDEVICE,
                     "eunsupported": _native.ENS_EUNSUPPORTED}
+    assert header_constants("ENS_MAX_")["traj"] == _native.MAX_TRAJ == 2**32 - 2**11
     surr = header_constants("ENS_SURR_")
     assert {k: surr[k] for k in _native.SURR_BUFFERS} == _native.SURR_BUFFERS
     assert surr["nparam"] == _native.SURR_NPARAM
