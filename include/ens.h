@@ -380,6 +380,32 @@ int ens_surrogate_solve(ens_ctx *ctx, ens_surrogate *s, const float *params,
                         uint64_t audit_seed, float *out, uint8_t *used_solver,
                         float *report, void *stream);
 
+/*
+ * ens_surrogate_solve without any device allocation, for callers that cannot
+ * allocate device memory during the call: code under stream capture, serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, results and
+ * report as ens_surrogate_solve (the same kernels), but its workspace --
+ * audit and fallback lists, the audited answers, per-query flags, counters
+ * and bin flags -- is one static device array per GPU of about 18 MiB,
+ * held from the first ens_create on that GPU until the process ends,
+ * instead of buffers the model allocates on demand.  Limits: n at most
+ * ENS_STATIC_MAX_QUERIES, an audit list of at most 40960 entries (audit_frac
+ * up to 2% at that n; more is ENS_EINVAL), and the fused inference kernel
+ * (ENS_OPT_MLP_TILE 0 gives ENS_EUNSUPPORTED).  Every static call on a GPU
+ * shares that array and the previous call's contents remain (the call
+ * clears its counters and flags itself), so calls that overlap on one GPU,
+ * from any context or stream, race: serialise them.  Asynchronous.
+ */
+#define ENS_STATIC_MAX_QUERIES 1048576LL
+int ens_surrogate_solve_static(ens_ctx *ctx, ens_surrogate *s,
+                               const float *params, const float *u0,
+                               const double *tspan, double abstol,
+                               double reltol, const double *save_times,
+                               int n_save, int64_t n, double audit_frac,
+                               double fallback_tol, uint64_t audit_seed,
+                               float *out, uint8_t *used_solver, float *report,
+                               void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -281,8 +281,11 @@ class Surrogate:
         return out
 
     def solve(self, params, u0, tspan, abstol, reltol, save_times, audit_frac=0.01,
-              fallback_tol=1e-3, audit_seed=8, out=None, used=None, report=None, stream=None):
-        """Audited surrogate solve; returns (out, used [N] uint8, report [4])."""
+              fallback_tol=1e-3, audit_seed=8, out=None, used=None, report=None, stream=None,
+              static=False):
+        """Audited surrogate solve; returns (out, used [N] uint8, report [4]).
+        static=True: ens_surrogate_solve_static (no device allocation, at most
+        2^20 queries)."""
         torch = _torch()
         N = u0.shape[1]
         dev = u0.device
@@ -298,7 +301,8 @@ class Surrogate:
             self.solver.set(tspan_broadcast=0)
         theta = [float(x) for x in save_times]
         th = (ctypes.c_double * len(theta))(*theta)
-        self._c(self._L.ens_surrogate_solve(
+        fn = self._L.ens_surrogate_solve_static if static else self._L.ens_surrogate_solve
+        self._c(fn(
             self.solver._ctx, self._s, params.data_ptr(), u0.data_ptr(), tspan.data_ptr(),
             abstol, reltol, th, len(theta), N, audit_frac, fallback_tol, audit_seed,
             out.data_ptr(), used.data_ptr(), report.data_ptr(), self._stream(stream)))

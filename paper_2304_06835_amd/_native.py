@@ -16,6 +16,7 @@ OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
         "mlp_tile": 12, "save_mode": 13, "stage_saves": 14, "autotune_cached": 15}
 PTRS = {"status": 1, "stats": 2}
 MAX_TRAJ = (1 << 32) - (1 << 11)  # ENS_MAX_TRAJ
+STATIC_MAX_QUERIES = 1 << 20      # ENS_STATIC_MAX_QUERIES
 
 # Every symbol include/ens.h declares.
 EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
@@ -24,7 +25,7 @@ EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
            "ens_surrogate_copy", "ens_surrogate_get_step", "ens_surrogate_set_step",
            "ens_surrogate_fit_norm", "ens_surrogate_train_step", "ens_surrogate_train",
            "ens_surrogate_predict", "ens_surrogate_solve", "ens_surrogate_save",
-           "ens_surrogate_load")
+           "ens_surrogate_load", "ens_surrogate_solve_static")
 SURR_BUFFERS = {"master": 1, "weights_bf16": 2, "grad": 3, "adam_m": 4, "adam_v": 5, "norm": 6}
 SURR_NPARAM = 145200
 
@@ -78,6 +79,7 @@ def lib() -> ctypes.CDLL:
     L.ens_surrogate_predict.argtypes = [vp, vp, vp, vp, i64, vp, vp]
     L.ens_surrogate_solve.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, dp, c_int, i64, dbl, dbl, u64,
                                       vp, vp, vp, vp]
+    L.ens_surrogate_solve_static.argtypes = L.ens_surrogate_solve.argtypes
     for name in EXPORTS:
         getattr(L, name).restype = getattr(L, name).restype or c_int
     L.ens_last_error.restype = ctypes.c_char_p

@@ -360,6 +360,10 @@ int ens_create(ens_ctx** out, int device) {
   }
   c->num_cu = prop.multiProcessorCount;
   c->dev_sig = std::string(prop.gcnArchName) + "/" + std::to_string(c->num_cu);
+  if (ens::init_static_scratch(device) != ENS_OK) {
+    delete c;
+    return ENS_EDEVICE;
+  }
   if (hipMalloc(&c->queue, 256) != hipSuccess) {
     delete c;
     return ENS_ENOMEM;

@@ -129,6 +129,10 @@ struct DeviceGuard {
   }
 };
 
+// Looks up this device's address of the static workspace of
+// ens_surrogate_solve_static (once per device; `device` must be current).
+int init_static_scratch(int device);
+
 // Launch one adaptive or fixed-step solve described by `a` with `cfg`
 // (resets the persistent queue first when cfg.form == 1).
 int launch_solve(ens_ctx* c, int sys, int alg, LaunchArgs a, const LaunchCfg& cfg, hipStream_t s);

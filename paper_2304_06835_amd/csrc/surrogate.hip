@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -319,6 +320,193 @@ uint64_t gcd(uint64_t a, uint64_t b) {
 
 }  // namespace
 
+namespace {
+
+// Workspace of one audited solve: audit list, fallback list, the solver's
+// answers for the audited queries, per-query flags, the two list counters and
+// the bin flags (+ max error bits).  The model's own lazily grown buffers, or
+// views into the static workspace below.
+struct AuditWs {
+  int64_t* alist;
+  int64_t* flist;
+  float* answers;
+  uint8_t* used;
+  unsigned long long* counts;  // [0] audited, [1] fallback
+  unsigned int* words;         // [0, kBins) bins, [kBins] max error bits
+  int64_t cap_audit;
+};
+
+// Audit-list capacity for n queries at audit_frac: 1.5x the expected count
+// plus 4096, far beyond any Bernoulli fluctuation.
+int64_t audit_capacity(double audit_frac, int64_t n) {
+  return (int64_t)std::ceil(audit_frac * (double)n * 1.5) + 4096;
+}
+
+int check_solve_args(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                     const double* tspan, double abstol, double reltol, const double* save_times,
+                     int n_save, int64_t n, double audit_frac, double fallback_tol,
+                     const float* out) {
+  int rc = check_model(c, s);
+  if (rc != ENS_OK) return rc;
+  if (n < 0 || n > ENS_MAX_TRAJ) return fail(c, ENS_EINVAL, "n out of range [0, ENS_MAX_TRAJ]");
+  if (n_save * 3 != kDims[4]) return fail(c, ENS_EINVAL, "the surrogate predicts 16 save times");
+  if (!(audit_frac >= 0.0 && audit_frac <= 1.0) || !(fallback_tol > 0.0))
+    return fail(c, ENS_EINVAL, "audit_frac in [0, 1] and fallback_tol > 0 required");
+  if (!save_times || !(abstol > 0.0) || !(reltol > 0.0))
+    return fail(c, ENS_EINVAL, "save_times and positive tolerances required");
+  for (int j = 0; j < n_save; ++j)
+    if (!(save_times[j] > (j ? save_times[j - 1] : 0.0)) || !(save_times[j] <= 1.0))
+      return fail(c, ENS_EINVAL, "save_times must be strictly increasing in (0, 1]");
+  if (n > 0 && (!params || !u0 || !tspan || !out))
+    return fail(c, ENS_EINVAL, "null device array");
+  return ENS_OK;
+}
+
+// ---- the static workspace of ens_surrogate_solve_static ---------------------
+// One copy per GPU, held until the process ends; every static call on a GPU
+// shares it.  Layout (bytes): fallback list int64 [Q], audit list int64 [A],
+// audited answers float [48][A], flags uint8 [Q], counters uint64 [2], bin
+// words uint32 [kBins + 1], with Q = ENS_STATIC_MAX_QUERIES, A = kStaticAudit.
+constexpr int64_t kStaticAudit = 40960;  // audit_frac up to 2% at the largest n
+constexpr int64_t kOffFlist = 0;
+constexpr int64_t kOffAlist = kOffFlist + 8 * ENS_STATIC_MAX_QUERIES;
+constexpr int64_t kOffAnswers = kOffAlist + 8 * kStaticAudit;
+constexpr int64_t kOffUsed = kOffAnswers + 4 * 48 * kStaticAudit;
+constexpr int64_t kOffCounts = (kOffUsed + ENS_STATIC_MAX_QUERIES + 255) / 256 * 256;
+constexpr int64_t kOffWords = kOffCounts + 16;
+constexpr int64_t kScratchBytes = kOffWords + 4 * (kBins + 1);
+static_assert(kOffCounts % 8 == 0 && kOffAnswers % 4 == 0, "aligned counters and answers");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+unsigned char* g_scratch_addr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+}  // namespace
+
+namespace ens {
+// Device address of this GPU's copy of the static workspace, looked up once
+// per device (ens_create calls it with the device current; the host-side name
+// of the array is not a device address).
+int init_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return ENS_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_addr[device]) return ENS_OK;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return ENS_EDEVICE;
+  g_scratch_addr[device] = static_cast<unsigned char*>(ptr);
+  return ENS_OK;
+}
+}  // namespace ens
+
+namespace {
+
+unsigned char* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
+// The audited solve on a given workspace (section 5.2's ensemble solve as the
+// auditor and fallback of the learned answers).
+int audited_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
+                  const double* tspan, double abstol, double reltol, const double* save_times,
+                  int n_save, int64_t n, double audit_frac, double fallback_tol,
+                  uint64_t audit_seed, float* out, float* report, const AuditWs& ws,
+                  hipStream_t st) {
+  hipError_t e = hipSuccess;
+#define ENS_TRY(x)                                                                   \
+  do {                                                                               \
+    if ((e = (x)) != hipSuccess)                                                     \
+      return fail(c, ENS_EDEVICE, "surrogate solve: %s", hipGetErrorString(e));     \
+  } while (0)
+  hipLaunchKernelGGL(zero_u8, dim3(grid_of(n)), dim3(256), 0, st, ws.used, n);
+  ENS_TRY(hipGetLastError());
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, ws.words, kBins + 1);
+  ENS_TRY(hipGetLastError());
+  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st,
+                     reinterpret_cast<unsigned int*>(ws.counts), 4);
+  ENS_TRY(hipGetLastError());
+
+  // 1. surrogate answers for every query
+  int rc = predict(c, s, params, u0, n, out, st);
+  if (rc != ENS_OK) return rc;
+
+  // 2. audit sample: Bernoulli(audit_frac) per query
+  const double thr_d = std::floor(audit_frac * 4294967296.0);
+  const uint32_t thr = thr_d >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)thr_d;
+  hipLaunchKernelGGL(select_audit, dim3(grid_of(n)), dim3(256), 0, st, n, thr, audit_seed,
+                     ws.alist, ws.cap_audit, ws.counts);
+  ENS_TRY(hipGetLastError());
+
+  // 3. solve the audited queries (sorted-form Tsit5, FP32, count read on the device)
+  ens::LaunchArgs a{};
+  a.n = ws.cap_audit;
+  a.in_stride = n;
+  a.out_stride = ws.cap_audit;
+  a.params = params;
+  a.u0 = u0;
+  a.tspan = tspan;
+  a.out = ws.answers;
+  a.idx = ws.alist;
+  a.n_dev = ws.counts;
+  a.scatter = 0;
+  a.queue = c->queue;
+  a.atol = abstol;
+  a.rtol = reltol;
+  a.h0 = 0.0;
+  a.maxiters = (int64_t)c->maxiters;
+  a.n_save = n_save;
+  a.tspan_bcast = c->tspan_bcast;
+  a.refill = c->refill;
+  a.tpl = 1;
+  for (int j = 0; j < n_save; ++j) a.theta[j] = save_times[j];
+  const int saved_prec = c->precision;
+  c->precision = 32;
+  // cost-sorted form (block 256): it reads the device-side count, the index
+  // list and the scattered output columns as the other forms do, and is the
+  // fastest on Lorenz (about 5.5 ms against 7.6 for the persistent form on a
+  // full 2^24 ensemble with landing saves)
+  ens::LaunchCfg cfg{2, 256, 0};
+  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
+  c->precision = saved_prec;
+  if (rc != ENS_OK) return rc;
+
+  // 4. compare, flag bins, return the solver's answer for audited queries
+  hipLaunchKernelGGL(audit_compare, dim3(grid_of(ws.cap_audit)), dim3(256), 0, st, ws.alist,
+                     ws.counts, ws.cap_audit, ws.answers, out, n, n_save, 3, params, s->norm,
+                     (float)fallback_tol, ws.words, ws.used, ws.words + kBins);
+  ENS_TRY(hipGetLastError());
+
+  // 5. fallback set: outside the box or in a flagged bin
+  hipLaunchKernelGGL(select_fallback, dim3(grid_of(n)), dim3(256), 0, st, n, params, u0, s->norm,
+                     ws.words, ws.used, ws.flist, ws.counts + 1);
+  ENS_TRY(hipGetLastError());
+
+  // 6. solve them straight into out
+  a.n = n;
+  a.out = out;
+  a.out_stride = n;
+  a.idx = ws.flist;
+  a.n_dev = ws.counts + 1;
+  a.scatter = 1;
+  c->precision = 32;
+  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
+  c->precision = saved_prec;
+  if (rc != ENS_OK) return rc;
+
+  if (report) {
+    hipLaunchKernelGGL(write_report, dim3(1), dim3(64), 0, st, ws.counts, ws.words,
+                       ws.words + kBins, report);
+    ENS_TRY(hipGetLastError());
+  }
+#undef ENS_TRY
+  return ENS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int ens_surrogate_create(ens_ctx* c, uint64_t seed, ens_surrogate** out) {
@@ -567,24 +755,12 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
                         const double* save_times, int n_save, int64_t n, double audit_frac,
                         double fallback_tol, uint64_t audit_seed, float* out,
                         uint8_t* used_solver, float* report, void* stream) {
-  int rc = check_model(c, s);
-  if (rc != ENS_OK) return rc;
-  if (n < 0 || n > ENS_MAX_TRAJ) return fail(c, ENS_EINVAL, "n out of range [0, ENS_MAX_TRAJ]");
-  if (n_save * 3 != kDims[4]) return fail(c, ENS_EINVAL, "the surrogate predicts 16 save times");
-  if (!(audit_frac >= 0.0 && audit_frac <= 1.0) || !(fallback_tol > 0.0))
-    return fail(c, ENS_EINVAL, "audit_frac in [0, 1] and fallback_tol > 0 required");
-  if (!save_times || !(abstol > 0.0) || !(reltol > 0.0))
-    return fail(c, ENS_EINVAL, "save_times and positive tolerances required");
-  for (int j = 0; j < n_save; ++j)
-    if (!(save_times[j] > (j ? save_times[j - 1] : 0.0)) || !(save_times[j] <= 1.0))
-      return fail(c, ENS_EINVAL, "save_times must be strictly increasing in (0, 1]");
-  if (n == 0) return ENS_OK;
-  if (!params || !u0 || !tspan || !out) return fail(c, ENS_EINVAL, "null device array");
+  int rc = check_solve_args(c, s, params, u0, tspan, abstol, reltol, save_times, n_save, n,
+                            audit_frac, fallback_tol, out);
+  if (rc != ENS_OK || n == 0) return rc;
   DeviceGuard g(c->device);
-  hipStream_t st = static_cast<hipStream_t>(stream);
-
-  // workspace for n queries
-  const int64_t cap_a = (int64_t)std::ceil(audit_frac * (double)n * 1.5) + 4096;
+  // workspace for n queries, grown on demand and kept by the model
+  const int64_t cap_a = audit_capacity(audit_frac, n);
   if (n > s->cap_n || cap_a > s->cap_audit) {
     void* old[] = {s->alist, s->flist, s->scratch, s->used};
     for (void* p : old)
@@ -593,102 +769,53 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
     s->scratch = nullptr;
     s->used = nullptr;
     s->cap_n = s->cap_audit = 0;
-    const int64_t nn = n > s->cap_n ? n : s->cap_n;
-    if (alloc(&s->alist, cap_a) != hipSuccess || alloc(&s->flist, nn) != hipSuccess ||
-        alloc(&s->scratch, cap_a * kDims[4]) != hipSuccess || alloc(&s->used, nn) != hipSuccess)
+    if (alloc(&s->alist, cap_a) != hipSuccess || alloc(&s->flist, n) != hipSuccess ||
+        alloc(&s->scratch, cap_a * kDims[4]) != hipSuccess || alloc(&s->used, n) != hipSuccess)
       return fail(c, ENS_ENOMEM, "cannot allocate the audit workspace");
-    s->cap_n = nn;
+    s->cap_n = n;
     s->cap_audit = cap_a;
   }
-  uint8_t* used = used_solver ? used_solver : s->used;
-  hipError_t e = hipSuccess;
-#define ENS_TRY(x)                                                                   \
-  do {                                                                               \
-    if ((e = (x)) != hipSuccess)                                                     \
-      return fail(c, ENS_EDEVICE, "surrogate solve: %s", hipGetErrorString(e));     \
-  } while (0)
-  hipLaunchKernelGGL(zero_u8, dim3(grid_of(n)), dim3(256), 0, st, used, n);
-  ENS_TRY(hipGetLastError());
-  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, s->words, kBins + 1);
-  ENS_TRY(hipGetLastError());
-  hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st,
-                     reinterpret_cast<unsigned int*>(s->counts), 4);
-  ENS_TRY(hipGetLastError());
+  AuditWs ws{s->alist, s->flist, s->scratch, used_solver ? used_solver : s->used, s->counts,
+             s->words, s->cap_audit};
+  return audited_solve(c, s, params, u0, tspan, abstol, reltol, save_times, n_save, n,
+                       audit_frac, fallback_tol, audit_seed, out, report, ws,
+                       static_cast<hipStream_t>(stream));
+}
 
-  // 1. surrogate answers for every query
-  rc = predict(c, s, params, u0, n, out, st);
-  if (rc != ENS_OK) return rc;
-
-  // 2. audit sample: Bernoulli(audit_frac) per query
-  const double thr_d = std::floor(audit_frac * 4294967296.0);
-  const uint32_t thr = thr_d >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)thr_d;
-  hipLaunchKernelGGL(select_audit, dim3(grid_of(n)), dim3(256), 0, st, n, thr, audit_seed,
-                     s->alist, s->cap_audit, s->counts);
-  ENS_TRY(hipGetLastError());
-
-  // 3. solve the audited queries (sorted-form Tsit5, FP32, count read on the device)
-  ens::LaunchArgs a{};
-  a.n = s->cap_audit;
-  a.in_stride = n;
-  a.out_stride = s->cap_audit;
-  a.params = params;
-  a.u0 = u0;
-  a.tspan = tspan;
-  a.out = s->scratch;
-  a.idx = s->alist;
-  a.n_dev = s->counts;
-  a.scatter = 0;
-  a.queue = c->queue;
-  a.atol = abstol;
-  a.rtol = reltol;
-  a.h0 = 0.0;
-  a.maxiters = (int64_t)c->maxiters;
-  a.n_save = n_save;
-  a.tspan_bcast = c->tspan_bcast;
-  a.refill = c->refill;
-  a.tpl = 1;
-  for (int j = 0; j < n_save; ++j) a.theta[j] = save_times[j];
-  const int saved_prec = c->precision;
-  c->precision = 32;
-  // cost-sorted form (block 256): it reads the device-side count, the index
-  // list and the scattered output columns as the other forms do, and is the
-  // fastest on Lorenz (about 5.5 ms against 7.6 for the persistent form on a
-  // full 2^24 ensemble with landing saves)
-  ens::LaunchCfg cfg{2, 256, 0};
-  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
-  c->precision = saved_prec;
-  if (rc != ENS_OK) return rc;
-
-  // 4. compare, flag bins, return the solver's answer for audited queries
-  hipLaunchKernelGGL(audit_compare, dim3(grid_of(s->cap_audit)), dim3(256), 0, st, s->alist,
-                     s->counts, s->cap_audit, s->scratch, out, n, n_save, 3, params, s->norm,
-                     (float)fallback_tol, s->words, used, s->words + kBins);
-  ENS_TRY(hipGetLastError());
-
-  // 5. fallback set: outside the box or in a flagged bin
-  hipLaunchKernelGGL(select_fallback, dim3(grid_of(n)), dim3(256), 0, st, n, params, u0, s->norm,
-                     s->words, used, s->flist, s->counts + 1);
-  ENS_TRY(hipGetLastError());
-
-  // 6. solve them straight into out
-  a.n = n;
-  a.out = out;
-  a.out_stride = n;
-  a.idx = s->flist;
-  a.n_dev = s->counts + 1;
-  a.scatter = 1;
-  c->precision = 32;
-  rc = ens::launch_solve(c, ENS_SYS_LORENZ, ENS_ALG_TSIT5, a, cfg, st);
-  c->precision = saved_prec;
-  if (rc != ENS_OK) return rc;
-
-  if (report) {
-    hipLaunchKernelGGL(write_report, dim3(1), dim3(64), 0, st, s->counts, s->words,
-                       s->words + kBins, report);
-    ENS_TRY(hipGetLastError());
-  }
-#undef ENS_TRY
-  return ENS_OK;
+int ens_surrogate_solve_static(ens_ctx* c, ens_surrogate* s, const float* params,
+                               const float* u0, const double* tspan, double abstol,
+                               double reltol, const double* save_times, int n_save, int64_t n,
+                               double audit_frac, double fallback_tol, uint64_t audit_seed,
+                               float* out, uint8_t* used_solver, float* report, void* stream) {
+  int rc = check_solve_args(c, s, params, u0, tspan, abstol, reltol, save_times, n_save, n,
+                            audit_frac, fallback_tol, out);
+  if (rc != ENS_OK || n == 0) return rc;
+  if (n > ENS_STATIC_MAX_QUERIES)
+    return fail(c, ENS_EINVAL, "ens_surrogate_solve_static takes at most %lld queries, not %lld",
+                (long long)ENS_STATIC_MAX_QUERIES, (long long)n);
+  const int64_t cap_a = audit_capacity(audit_frac, n);
+  if (cap_a > kStaticAudit)
+    return fail(c, ENS_EINVAL,
+                "audit_frac %g over %lld queries needs an audit list of %lld entries; the static "
+                "workspace holds %lld",
+                audit_frac, (long long)n, (long long)cap_a, (long long)kStaticAudit);
+  if (c->mlp_tile == 0)
+    return fail(c, ENS_EUNSUPPORTED,
+                "the static audited solve runs the fused inference kernel only (ENS_OPT_MLP_TILE "
+                "0 needs a workspace)");
+  DeviceGuard g(c->device);
+  unsigned char* base = static_scratch(c->device);
+  if (!base)
+    return fail(c, ENS_EDEVICE, "no address of the static workspace on device %d", c->device);
+  AuditWs ws{reinterpret_cast<int64_t*>(base + kOffAlist),
+             reinterpret_cast<int64_t*>(base + kOffFlist),
+             reinterpret_cast<float*>(base + kOffAnswers),
+             used_solver ? used_solver : base + kOffUsed,
+             reinterpret_cast<unsigned long long*>(base + kOffCounts),
+             reinterpret_cast<unsigned int*>(base + kOffWords), kStaticAudit};
+  return audited_solve(c, s, params, u0, tspan, abstol, reltol, save_times, n_save, n,
+                       audit_frac, fallback_tol, audit_seed, out, report, ws,
+                       static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
