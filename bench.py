@@ -7,7 +7,8 @@ One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
     python bench.py [--steps K] [--warmup W] [--workload lorenz_fp32|lorenz_fp64|
                      robertson|gbm] [--alg rodas4|ros23]
-                    [--form plain|persistent|sorted|sorted_b512_r2|sorted_staged|auto]
+                    [--form plain|persistent|persistent_sorted_chunks|sorted|sorted_b512_r2|
+                     sorted_staged|auto]
                     [--save-mode landing|dense]
                     [--no-cpu-baseline] [--no-variants] [--no-surrogate]
 
@@ -71,6 +72,7 @@ PEAK = {32: 157.3, 64: 78.6}
 PEAK_BF16_MFMA = 2500.0
 
 FORMS = {"plain": {"form": 0}, "persistent": {"form": 1},
+         "persistent_sorted_chunks": {"form": 3, "block": 256},
          "sorted": {"form": 2, "block": 256}}
 # the stiff ensemble also at a sort over 1024 items in 512-thread blocks
 STIFF_FORMS = dict(FORMS, sorted_b512_r2={"form": 2, "block": 512, "tpl": 2})
@@ -99,8 +101,8 @@ def parse():
                     help="stiff method of the Robertson and appendix-B.1 workloads (default "
                          "rodas4), or siea for the GBM workload")
     ap.add_argument("--form", default="",
-                    choices=["", "plain", "persistent", "sorted", "sorted_b512_r2", "sorted_staged",
-                             "auto"])
+                    choices=["", "plain", "persistent", "persistent_sorted_chunks", "sorted",
+                             "sorted_b512_r2", "sorted_staged", "auto"])
     ap.add_argument("--save-mode", default="", choices=["", "landing", "dense"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -244,7 +246,8 @@ def kernel_name(e, form, precision):
     if e.system == "pollu":
         return f"ros_grouped<{prec}>"
     base = "tsit5" if e.alg == "tsit5" else "ros"
-    suffix = {"plain": "_plain", "persistent": "_persistent", "sorted": "_sorted",
+    suffix = {"plain": "_plain", "persistent": "_persistent",
+              "persistent_sorted_chunks": "_chunked", "sorted": "_sorted",
               "sorted_b512_r2": "_sorted", "sorted_staged": "_sorted", "auto": ""}[form]
     return f"{base}{suffix}<{prec}>"
 

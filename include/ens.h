@@ -111,11 +111,17 @@ typedef struct ens_ctx ens_ctx;
                                64: FP64 throughout.  Also the dtype of params,
                                u0 and out.                                      */
 #define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;
-                               1: persistent kernel fed by an atomic work queue;
+                               1: persistent kernel fed by an atomic work queue,
+                               idle lanes refilled one trajectory at a time;
                                2: one lane per trajectory, the trajectories of
                                each block sorted by expected work (span / first
-                               step) so that a wave's lanes finish together    */
-#define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256 (forms 0, 1);
+                               step) so that a wave's lanes finish together;
+                               3: persistent kernel whose blocks each claim a
+                               chunk of `block` trajectories from the atomic
+                               queue, sort it by expected work as form 2 does
+                               and integrate it (one sorted group of 64 per
+                               wave), then claim the next                    */
+#define ENS_OPT_BLOCK 3     /* threads per block: 64, 128 or 256 (forms 0, 1, 3);
                                256, 512 or 1024 (form 2, the sorting group);
                                0 (default): 256, or 1024 for form 2            */
 #define ENS_OPT_DT 4        /* fixed step of ENS_ALG_EM / SIEA (> 0)             */
@@ -129,8 +135,8 @@ typedef struct ens_ctx ens_ctx;
                                      0 (default): tspan is [2][N]              */
 #define ENS_OPT_REFILL 9    /* persistent form: idle lanes per wave that trigger
                                a refill from the queue, 1..64 (default 16)      */
-#define ENS_OPT_GRID 10     /* persistent form: blocks launched; 0 (default):
-                               enough to fill every CU                          */
+#define ENS_OPT_GRID 10     /* persistent forms (1, 3): blocks launched; 0
+                               (default): enough to fill every CU               */
 #define ENS_OPT_TPL 11      /* forms 0 and 2: trajectories each lane integrates
                                one after another, 1..8 (default 1).  Form 0:
                                lane g of G takes g, g + G, g + 2G, ...; form 2:
@@ -239,9 +245,10 @@ int ens_philox_fill(ens_ctx *ctx, uint64_t seed, int64_t n_traj, uint32_t step,
 /*
  * Autotuner: time every launch configuration -- block in {64, 128, 256} x
  * (plain form with trajectories per lane in {1, 2, 4}, or persistent form
- * with refill threshold in {4, 16, 32}), and the sorted form with block in
+ * with refill threshold in {4, 16, 32}), the sorted form with block in
  * {256, 512, 1024} sorting one block's worth of trajectories or block in
- * {256, 512} sorting two (ENS_OPT_TPL 2); the plain form alone for the SDE
+ * {256, 512} sorting two (ENS_OPT_TPL 2), and the persistent sorted-chunk
+ * form with block 128 or 256; the plain form alone for the SDE
  * algorithms, and block alone for ENS_SYS_POLLU (one trajectory per 32-lane
  * group, plain form only) -- on the given probe ensemble (same
  * arguments as ens_solve; `out` is overwritten), and set ENS_OPT_FORM,

@@ -13,9 +13,9 @@
 #include "ens_internal.h"
 
 namespace ens {
-int tsit5_blocks_per_cu(int sys, int prec, int block);
-int rodas4_blocks_per_cu(int sys, int prec, int block);
-int ros23_blocks_per_cu(int sys, int prec, int block);
+int tsit5_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
+int rodas4_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
+int ros23_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 
 __global__ void zero_counter(unsigned long long* q) {
   if (threadIdx.x == 0) *q = 0ull;
@@ -26,10 +26,10 @@ hipError_t reset_queue(unsigned long long* q, hipStream_t s) {
   return hipGetLastError();
 }
 
-int persistent_grid(int alg, int sys, int prec, int block, int num_cu) {
-  const int per_cu = alg == ENS_ALG_RODAS4  ? rodas4_blocks_per_cu(sys, prec, block)
-                     : alg == ENS_ALG_ROS23 ? ros23_blocks_per_cu(sys, prec, block)
-                                            : tsit5_blocks_per_cu(sys, prec, block);
+int persistent_grid(int alg, int sys, int prec, int block, int num_cu, int form, int tpl) {
+  const int per_cu = alg == ENS_ALG_RODAS4  ? rodas4_blocks_per_cu(sys, prec, block, form, tpl)
+                     : alg == ENS_ALG_ROS23 ? ros23_blocks_per_cu(sys, prec, block, form, tpl)
+                                            : tsit5_blocks_per_cu(sys, prec, block, form, tpl);
   return per_cu * num_cu;
 }
 }  // namespace ens
@@ -175,10 +175,12 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
     e = alg == ENS_ALG_EM ? ens::launch_em(sys, c->precision, cfg, a, s)
                           : ens::launch_siea(sys, c->precision, cfg, a, s);
   } else {
-    if (cfg.form == 1) {
-      if (cfg.grid <= 0) cfg.grid = ens::persistent_grid(alg, sys, c->precision, cfg.block, c->num_cu);
+    if (cfg.form == 1 || cfg.form == 3) {
+      if (cfg.grid <= 0)
+        cfg.grid = ens::persistent_grid(alg, sys, c->precision, cfg.block, c->num_cu, cfg.form,
+                                        a.tpl);
       a.first_queued = (int64_t)cfg.grid * cfg.block;
-      a.tpl = 1;
+      if (cfg.form == 1) a.tpl = 1;
       e = ens::reset_queue(c->queue, s);
       if (e != hipSuccess)
         return fail(c, ENS_EDEVICE, "queue reset launch failed: %s", hipGetErrorString(e));
@@ -394,7 +396,8 @@ int ens_set_option(ens_ctx* c, int key, double v) {
       c->precision = (int)v;
       return ENS_OK;
     case ENS_OPT_FORM:
-      if (v != 0 && v != 1 && v != 2) return fail(c, ENS_EINVAL, "form must be 0, 1 or 2");
+      if (v != 0 && v != 1 && v != 2 && v != 3)
+        return fail(c, ENS_EINVAL, "form must be 0, 1, 2 or 3");
       c->form = (int)v;
       return ENS_OK;
     case ENS_OPT_BLOCK:
@@ -562,6 +565,7 @@ int ens_autotune(ens_ctx* c, int sys, int64_t n, const void* params, const void*
   if (!is_sde(alg) && !grouped) {
     for (int b : {256, 512, 1024}) cands[nc++] = {2, b, 1, 64};
     for (int b : {256, 512}) cands[nc++] = {2, b, 2, 64};  // sort over 2 * block items
+    for (int b : {128, 256}) cands[nc++] = {3, b, 1, 64};  // persistent sorted chunks
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

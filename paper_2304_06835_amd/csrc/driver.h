@@ -191,9 +191,8 @@ struct LaneInput {
 
 // Ascending bitonic sort of v[0..NE) in LDS by the B threads of the block.
 template <int NE, int B>
-__device__ inline void block_sort(uint64_t* v) {
+__device__ inline void block_sort(uint64_t* v, int tid) {
   static_assert((NE & (NE - 1)) == 0 && NE >= 2, "sort size must be a power of two");
-  const int tid = (int)threadIdx.x;
   for (int k = 2; k <= NE; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int p = tid; p < NE / 2; p += B) {
@@ -245,7 +244,7 @@ __device__ inline void run_sorted(const LaunchArgs& a) {
     keys[e] = ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)e;
   }
   __syncthreads();
-  block_sort<NE, B>(keys);
+  block_sort<NE, B>(keys, tid);
   for (int r = 0; r < R; ++r) {
     const int grp = r * W + ((r & 1) ? (W - 1 - wave) : wave);
     const int item = (int)(uint32_t)keys[grp * kWave + lane];
@@ -269,6 +268,53 @@ __device__ inline void run_sorted(const LaunchArgs& a) {
       const int rows = a.n_save * Lane::N;
       for (int r = 0; r < rows; ++r) dst[r * a.out_stride] = stage[r * B + tid];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Form 3 (persistent queue of cost-sorted chunks): a resident grid of blocks
+// of B threads, each claiming chunks of B consecutive trajectories from the
+// atomic work counter (one atomic per chunk), until the queue is empty.  A
+// chunk is handled as the sorted form handles its block: every thread
+// initialises one item to learn its expected work, the block sorts the chunk
+// by it in LDS, and wave w integrates the w-th group of 64 sorted items, so
+// a wave's lanes finish together.  The block then claims the next chunk:
+// blocks that drew cheap chunks take more of them.  Each item runs the same
+// lane code as in the other forms, so results are bit-identical.
+template <class Lane, int B>
+__device__ inline void run_chunked(const LaunchArgs& a) {
+  __shared__ uint64_t keys[B];
+  __shared__ unsigned int chunk;
+  stage_theta(a);
+  const int tid = (int)threadIdx.x;
+  const int64_t n = work_items(a);
+  while (true) {
+    if (tid == 0) chunk = (unsigned int)atomicAdd(a.queue, 1ull);
+    __syncthreads();
+    const int64_t base =
+        (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)chunk) * (int64_t)B;
+    if (base >= n) break;  // the same for the whole block
+    float key = __builtin_inff();  // items past the end sort last
+    if (base + tid < n) {
+      typename Lane::Input in;
+      in.load(a, base + tid);
+      Lane L;
+      L.init(a, base + tid, in);
+      key = work_key(L);
+    }
+    keys[tid] = ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)tid;
+    __syncthreads();
+    block_sort<B, B>(keys, tid);
+    const int64_t k = base + (int)(uint32_t)keys[tid];
+    if (k < n) {
+      typename Lane::Input in;
+      in.load(a, k);
+      Lane L;
+      L.init(a, k, in);
+      while (!L.done) L.attempt(a, k);
+      L.finish(a, k);
+    }
+    __syncthreads();  // keys and chunk are reused by the next chunk
   }
 }
 
@@ -336,9 +382,14 @@ __device__ inline void run_persistent(const LaunchArgs& a) {
         int64_t c0 = 0, c1 = 0;  // newly claimed chunk
         if (left < nidle && !queue_empty) {
           const int leader = __ffsll((long long)idle) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(a.queue, (unsigned long long)kChunk);
-          base = __shfl(base, leader);
+          unsigned long long got = 0;
+          if (lane == leader) got = atomicAdd(a.queue, (unsigned long long)kChunk);
+          // read back from the leader lane as a scalar, so that the pocket
+          // bounds derived from it stay in scalar registers
+          const unsigned long long base =
+              ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)(got >> 32), leader)
+               << 32) |
+              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)got, leader);
           c0 = a.first_queued + (int64_t)base;
           c1 = c0 + kChunk < n ? c0 + kChunk : n;
           if (c0 >= n) {

@@ -45,9 +45,9 @@ struct LaunchArgs {
 };
 
 struct LaunchCfg {
-  int form;   // 0 plain, 1 persistent, 2 cost-sorted
+  int form;   // 0 plain, 1 persistent, 2 cost-sorted, 3 persistent cost-sorted chunks
   int block;  // threads per block
-  int grid;   // persistent: blocks (0: occupancy-derived)
+  int grid;   // forms 1 and 3: blocks (0: occupancy-derived)
 };
 
 // Each returns hipSuccess or the launch error.  `sys` is ENS_SYS_*, `prec` 32|64.
@@ -68,7 +68,7 @@ hipError_t launch_philox_fill(uint64_t seed, int64_t n, uint32_t step, uint32_t*
 
 // Blocks per CU the persistent kernel of (alg, sys, prec) can keep resident
 // at `block` threads, and the grid that fills the device.
-int persistent_grid(int alg, int sys, int prec, int block, int num_cu);
+int persistent_grid(int alg, int sys, int prec, int block, int num_cu, int form, int tpl);
 
 // Zero the persistent work counter (a one-thread kernel, so the solve can be
 // captured into a graph without memset nodes).

@@ -99,13 +99,13 @@ hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, 
   return hipErrorInvalidValue;
 }
 
-int rodas4_blocks_per_cu(int sys, int prec, int block) {
+int rodas4_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   switch (sys) {
-    case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Rodas4>(prec, block);
-    case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Rodas4>(prec, block);
-    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Rodas4>(prec, block);
-    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Rodas4>(prec, block);
-    default: return ros_occ_prec<Linear, Rodas4>(prec, block);
+    case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Rodas4>(prec, block, form, tpl);
+    case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Rodas4>(prec, block, form, tpl);
+    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Rodas4>(prec, block, form, tpl);
+    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Rodas4>(prec, block, form, tpl);
+    default: return ros_occ_prec<Linear, Rodas4>(prec, block, form, tpl);
   }
 }
 

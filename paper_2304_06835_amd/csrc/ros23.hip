@@ -83,13 +83,13 @@ hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, h
   return hipErrorInvalidValue;
 }
 
-int ros23_blocks_per_cu(int sys, int prec, int block) {
+int ros23_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   switch (sys) {
-    case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Ros23>(prec, block);
-    case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Ros23>(prec, block);
-    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Ros23>(prec, block);
-    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Ros23>(prec, block);
-    default: return ros_occ_prec<Linear, Ros23>(prec, block);
+    case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Ros23>(prec, block, form, tpl);
+    case ENS_SYS_LORENZ: return ros_occ_prec<Lorenz, Ros23>(prec, block, form, tpl);
+    case ENS_SYS_OREGO: return ros_occ_prec<Orego, Ros23>(prec, block, form, tpl);
+    case ENS_SYS_HIRES: return ros_occ_prec<Hires, Ros23>(prec, block, form, tpl);
+    default: return ros_occ_prec<Linear, Ros23>(prec, block, form, tpl);
   }
 }
 

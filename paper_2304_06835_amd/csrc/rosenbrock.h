@@ -262,8 +262,18 @@ struct RosLane {
     }
     d2 = ::sqrt(V::sum(d2) / V::kDim) / h0;
     const double dm = fmax(d1, d2);
-    const double h1 =
-        (dm <= 1e-15) ? fmax(1e-6, h0 * 1e-3) : ::exp2(::log2(0.01 / dm) / (M::kP + 1.0));
+    double h1;
+    if (dm <= 1e-15) {
+      h1 = fmax(1e-6, h0 * 1e-3);
+    } else if constexpr (std::is_same_v<R, float>) {
+      // an FP32 lane keeps an FP32 step: the hardware log2 / exp2 suffice, and
+      // unlike the FP64 library routines they bring no table of polynomial
+      // constants that a loop around the lane would keep in registers
+      h1 = (double)Num<float>::exp2(Num<float>::log2((float)(0.01 / dm)) *
+                                    (float)(1.0 / (M::kP + 1.0)));
+    } else {
+      h1 = ::exp2(::log2(0.01 / dm) / (M::kP + 1.0));
+    }
     return (R)fmin(fmin(100.0 * h0, h1), hmax);
   }
 
@@ -388,6 +398,11 @@ __global__ void __launch_bounds__(kMaxBlock) ros_persistent(const LaunchArgs a) 
   run_persistent<RosLane<R, S, M>>(a);
 }
 
+template <class R, class S, class M, int B>
+__global__ void __launch_bounds__(B) ros_chunked(const LaunchArgs a) {
+  run_chunked<RosLane<R, S, M>, B>(a);
+}
+
 template <class R, class S, class M, int B, int RR>
 __global__ void __launch_bounds__(B) ros_sorted(const LaunchArgs a) {
   run_sorted<RosLane<R, S, M>, B, RR>(a);
@@ -419,6 +434,13 @@ hipError_t ros_launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   } else if (cfg.form == 1) {
     hipLaunchKernelGGL((ros_persistent<R, S, M>), dim3((unsigned)cfg.grid), dim3(cfg.block), 0,
                        s, a);
+  } else if (cfg.form == 3) {
+    if (cfg.block == 64)
+      hipLaunchKernelGGL((ros_chunked<R, S, M, 64>), dim3((unsigned)cfg.grid), dim3(64), 0, s, a);
+    else if (cfg.block == 128)
+      hipLaunchKernelGGL((ros_chunked<R, S, M, 128>), dim3((unsigned)cfg.grid), dim3(128), 0, s, a);
+    else
+      hipLaunchKernelGGL((ros_chunked<R, S, M, 256>), dim3((unsigned)cfg.grid), dim3(256), 0, s, a);
   } else {
     ros_launch_sorted<R, S, M>(cfg, a, s);
   }
@@ -426,11 +448,16 @@ hipError_t ros_launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
 }
 
 template <class R, class S, class M>
-int ros_occupancy_typed(int block) {
+int ros_occupancy_typed(int block, int form, int tpl) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ros_persistent<R, S, M>, block, 0) !=
-      hipSuccess)
-    return 1;
+  hipError_t e;
+  if (form == 3)
+    e = block == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ros_chunked<R, S, M, 64>, 64, 0)
+        : block == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ros_chunked<R, S, M, 128>, 128, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ros_chunked<R, S, M, 256>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ros_persistent<R, S, M>, block, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -441,9 +468,9 @@ hipError_t ros_launch_prec(int prec, const LaunchCfg& cfg, LaunchArgs a, hipStre
 }
 
 template <class S, class M>
-int ros_occ_prec(int prec, int block) {
-  return prec == 64 ? ros_occupancy_typed<double, S, M>(block)
-                    : ros_occupancy_typed<float, S, M>(block);
+int ros_occ_prec(int prec, int block, int form, int tpl) {
+  return prec == 64 ? ros_occupancy_typed<double, S, M>(block, form, tpl)
+                    : ros_occupancy_typed<float, S, M>(block, form, tpl);
 }
 
 }  // namespace ens

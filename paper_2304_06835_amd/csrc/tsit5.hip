@@ -316,6 +316,17 @@ __global__ void __launch_bounds__(kMaxBlock) tsit5_persistent(const LaunchArgs a
   run_persistent<Tsit5Lane<R, S>>(a);
 }
 
+// FP32 lanes of the chunked form held to five waves per SIMD (96 registers;
+// left alone the compiler takes 101, four waves): measured faster than
+// holding them to six or seven, where the stage chains lose their overlap
+template <class R>
+constexpr int kChunkWaves = sizeof(R) == 4 ? 5 : 1;
+
+template <class R, class S, int B>
+__global__ void __launch_bounds__(B, kChunkWaves<R>) tsit5_chunked(const LaunchArgs a) {
+  run_chunked<Tsit5Lane<R, S>, B>(a);
+}
+
 template <class R, class S, int B, int RR, bool Staged>
 __global__ void __launch_bounds__(B) tsit5_sorted(const LaunchArgs a) {
   run_sorted<Tsit5Lane<R, S>, B, RR, Staged>(a);
@@ -354,6 +365,13 @@ hipError_t launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   } else if (cfg.form == 1) {
     hipLaunchKernelGGL((tsit5_persistent<R, S>), dim3((unsigned)cfg.grid), dim3(cfg.block),
                        0, s, a);
+  } else if (cfg.form == 3) {
+    if (cfg.block == 64)
+      hipLaunchKernelGGL((tsit5_chunked<R, S, 64>), dim3((unsigned)cfg.grid), dim3(64), 0, s, a);
+    else if (cfg.block == 128)
+      hipLaunchKernelGGL((tsit5_chunked<R, S, 128>), dim3((unsigned)cfg.grid), dim3(128), 0, s, a);
+    else
+      hipLaunchKernelGGL((tsit5_chunked<R, S, 256>), dim3((unsigned)cfg.grid), dim3(256), 0, s, a);
   } else {
     launch_sorted<R, S>(cfg, a, s);
   }
@@ -361,11 +379,16 @@ hipError_t launch_typed(const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
 }
 
 template <class R, class S>
-int occupancy_typed(int block) {
+int occupancy_typed(int block, int form, int tpl) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_persistent<R, S>, block, 0) !=
-      hipSuccess)
-    return 1;
+  hipError_t e;
+  if (form == 3)
+    e = block == 64    ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_chunked<R, S, 64>, 64, 0)
+        : block == 128 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_chunked<R, S, 128>, 128, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_chunked<R, S, 256>, 256, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_persistent<R, S>, block, 0);
+  if (e != hipSuccess) return 1;
   return nb > 0 ? nb : 1;
 }
 
@@ -381,12 +404,12 @@ hipError_t launch_tsit5(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, h
   return hipErrorInvalidValue;
 }
 
-int tsit5_blocks_per_cu(int sys, int prec, int block) {
+int tsit5_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   if (sys == ENS_SYS_LORENZ)
-    return prec == 64 ? occupancy_typed<double, Lorenz>(block)
-                      : occupancy_typed<float, Lorenz>(block);
-  return prec == 64 ? occupancy_typed<double, Linear>(block)
-                    : occupancy_typed<float, Linear>(block);
+    return prec == 64 ? occupancy_typed<double, Lorenz>(block, form, tpl)
+                      : occupancy_typed<float, Lorenz>(block, form, tpl);
+  return prec == 64 ? occupancy_typed<double, Linear>(block, form, tpl)
+                    : occupancy_typed<float, Linear>(block, form, tpl);
 }
 
 }  // namespace ens

@@ -98,7 +98,8 @@ def test_tsit5_forms_and_launch_shapes_bitwise_equal(ens, precision):
                  {"form": 1}, {"form": 1, "block": 64, "refill": 1},
                  {"form": 1, "block": 128, "refill": 32}, {"form": 1, "grid": 3},
                  {"form": 2}, {"form": 2, "block": 256}, {"form": 2, "block": 512, "tpl": 2},
-                 {"form": 2, "block": 256, "tpl": 4}):
+                 {"form": 2, "block": 256, "tpl": 4}, {"form": 3}, {"form": 3, "block": 64},
+                 {"form": 3, "block": 128, "grid": 5}):
         out, st, s = run(ens, e, precision, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(st, st0) and np.array_equal(s, s0), opts
@@ -193,7 +194,8 @@ def test_rodas4_forms_bitwise_equal(ens, precision):
     banner(f"rodas4 forms fp{precision}")
     base, st0, s0 = run(ens, e, precision)
     for opts in ({"block": 64, "tpl": 3}, {"form": 1}, {"form": 1, "refill": 4, "block": 128},
-                 {"form": 2}, {"form": 2, "block": 256, "tpl": 2}):
+                 {"form": 2}, {"form": 2, "block": 256, "tpl": 2}, {"form": 3},
+                 {"form": 3, "block": 64, "grid": 7}):
         out, st, s = run(ens, e, precision, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(s, s0), opts
@@ -270,9 +272,11 @@ def test_autotune_picks_a_valid_config_with_identical_results(ens):
     ref = to_host(s.solve("lorenz", *args))
     ms, cfg = s.autotune("lorenz", *args)
     print("autotune:", ms, cfg)
-    assert ms > 0 and cfg["form"] in (0, 1, 2)
+    assert ms > 0 and cfg["form"] in (0, 1, 2, 3)
     if cfg["form"] == 2:   # sorted: one or two blocks' worth of trajectories per sort
         assert (cfg["block"], cfg["tpl"]) in {(256, 1), (512, 1), (1024, 1), (256, 2), (512, 2)}
+    elif cfg["form"] == 3:
+        assert cfg["block"] in (128, 256)
     else:
         assert cfg["block"] in (64, 128, 256)
     out = to_host(s.solve("lorenz", *args))
@@ -364,8 +368,8 @@ def test_full_size_in_the_benchmarked_launch(ens, orc, name):
     (save mode 1) in the cost-sorted form with block 256, and 2^20 Robertson
     (Rodas4, landing saves) in the same form.  Every trajectory finishes with
     status 0, 4096 sampled trajectories match the FP64 oracle at tol 1e-12
-    within the FP32 bar, and the plain and persistent forms in the same save
-    mode give the same bits on the sample."""
+    within the FP32 bar, and the plain and both persistent forms in the same
+    save mode give the same bits on the sample."""
     import torch
     e = W.lorenz_fp32() if name == "lorenz_fp32" else W.robertson()
     mode = 1 if name == "lorenz_fp32" else 0
@@ -388,7 +392,7 @@ def test_full_size_in_the_benchmarked_launch(ens, orc, name):
     err = normwise(got, truth)
     print("%s full size, sampled: max normwise error %.3e" % (name, err.max()))
     assert err.max() <= FP32_BAR
-    for form in (0, 1):
+    for form in (0, 1, 3):
         s.set(form=form, block=256)
         o = s.solve(e.system, P, U, T, e.alg, e.abstol, e.reltol, e.theta, out=out)
         g = np.ascontiguousarray(to_host(o.index_select(2, idx_d)))
@@ -414,7 +418,7 @@ def test_dense_output_fp64_matches_oracle(ens, orc):
     assert np.mean((stats[0] == na) & (stats[1] == nr)) > 0.95
 
 
-@pytest.mark.parametrize("form", [0, 1, 2])
+@pytest.mark.parametrize("form", [0, 1, 2, 3])
 def test_dense_output_fp32_accuracy_and_forms(ens, orc, form):
     """FP32 dense output against the FP64 truth (landing oracle at 1e-12):
     within the FP32 bar, fewer attempts than the landing mode, and the three

@@ -84,7 +84,8 @@ def test_ros23_forms_bitwise_equal(ens, precision):
     banner(f"ros23 forms fp{precision}")
     base, st0, s0 = run(ens, e, precision)
     for opts in ({"block": 64, "tpl": 3}, {"form": 1}, {"form": 1, "refill": 4, "block": 128},
-                 {"form": 2}, {"form": 2, "block": 256, "tpl": 2}):
+                 {"form": 2}, {"form": 2, "block": 256, "tpl": 2}, {"form": 3},
+                 {"form": 3, "block": 128}):
         out, st, s = run(ens, e, precision, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(s, s0), opts

@@ -180,7 +180,7 @@ def test_lane_forms_bitwise_equal(ens, name):
     banner(f"{name} forms")
     base, st0, s0 = run(ens, e, 32)
     for opts in ({"block": 64, "tpl": 3}, {"form": 1}, {"form": 2, "block": 256},
-                 {"form": 2, "block": 512, "tpl": 2}):
+                 {"form": 2, "block": 512, "tpl": 2}, {"form": 3}):
         out, st, s = run(ens, e, 32, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(s, s0), opts
@@ -193,7 +193,8 @@ def test_pollu_block_shapes_bitwise_equal_and_forms_ignored(ens):
     e = W.stiff("pollu", N=333)
     banner("pollu block shapes")
     base, st0, s0 = run(ens, e, 32)
-    for opts in ({"block": 64}, {"block": 128}, {"form": 1}, {"form": 2, "block": 1024}):
+    for opts in ({"block": 64}, {"block": 128}, {"form": 1}, {"form": 2, "block": 1024},
+                 {"form": 3}):
         out, st, s = run(ens, e, 32, **opts)
         assert np.array_equal(out.view(np.uint8), base.view(np.uint8)), opts
         assert np.array_equal(s, s0), opts
