@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 LINEAR, LORENZ, ROBERTSON, GBM4, OREGO, HIRES, POLLU, CRN = 0, 1, 2, 3, 4, 5, 6, 7
-TSIT5, RODAS4, ROS23, EM, SIEA = 1, 2, 3, 4, 5
+TSIT5, RODAS4, ROS23, EM, SIEA, RODAS5P = 1, 2, 3, 4, 5, 6
 DIMS = {LINEAR: (3, 9), LORENZ: (3, 3), ROBERTSON: (3, 3), GBM4: (4, 2), OREGO: (3, 3),
         HIRES: (8, 12), POLLU: (20, 25), CRN: (4, 6)}
 NOISES = {GBM4: 4, CRN: 8}
@@ -79,6 +79,8 @@ def lib():
         L.orc_tsit5_tableau.restype = None
         L.orc_rodas4_tableau.argtypes = [dp, dp, dp, dp, dp]
         L.orc_rodas4_tableau.restype = None
+        L.orc_rodas5p_tableau.argtypes = [dp, dp, dp, dp, dp]
+        L.orc_rodas5p_tableau.restype = None
         _lib = L
     return _lib
 
@@ -250,6 +252,13 @@ def rodas4_tableau():
     a, C, m, mh = np.empty(36), np.empty(36), np.empty(6), np.empty(6)
     lib().orc_rodas4_tableau(ctypes.byref(g), _p(a), _p(C), _p(m), _p(mh))
     return g.value, a.reshape(6, 6), C.reshape(6, 6), m, mh
+
+
+def rodas5p_tableau():
+    g = ctypes.c_double()
+    a, C, m, mh = np.empty(64), np.empty(64), np.empty(8), np.empty(8)
+    lib().orc_rodas5p_tableau(ctypes.byref(g), _p(a), _p(C), _p(m), _p(mh))
+    return g.value, a.reshape(8, 8), C.reshape(8, 8), m, mh
 
 
 def normwise_rel_err(x, ref):

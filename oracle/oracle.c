@@ -304,6 +304,62 @@ static const double RO_MHAT[6] = {1.221224509226641, 6.019134481288629,
                                   12.53708332932087, -0.6878860361058950, 1.0,
                                   0.0};
 
+/* Rodas5P of Steinebach (2023), the paper's GPURodas5P (section 5.2.1) and
+ * the reference method of its stiff comparison (section 6.4): an 8-stage
+ * stiffly accurate Rosenbrock method of order 5 with an embedded method of
+ * order 4, in the same transformed variables as RODAS4.  The stage points of
+ * stages 7 and 8 are the previous stage point plus the previous U, the
+ * solution is the 8th stage point plus U_8 and the embedded solution is the
+ * 8th stage point (so U_8 is the error estimate).  Coefficients from that
+ * publication.                                                              */
+static const double R5_GAMMA = 0.21193756319429014;
+static const double R5_A[8][8] = {
+    {0, 0, 0, 0, 0, 0, 0, 0},
+    {3.0, 0, 0, 0, 0, 0, 0, 0},
+    {2.849394379747939, 0.45842242204463923, 0, 0, 0, 0, 0, 0},
+    {-6.954028509809101, 2.489845061869568, -10.358996098473584, 0, 0, 0, 0, 0},
+    {2.8029986275628964, 0.5072464736228206, -0.3988312541770524,
+     -0.04721187230404641, 0, 0, 0, 0},
+    {-7.502846399306121, 2.561846144803919, -11.627539656261098,
+     -0.18268767659942256, 0.030198172008377946, 0, 0, 0},
+    {-7.502846399306121, 2.561846144803919, -11.627539656261098,
+     -0.18268767659942256, 0.030198172008377946, 1.0, 0, 0},
+    {-7.502846399306121, 2.561846144803919, -11.627539656261098,
+     -0.18268767659942256, 0.030198172008377946, 1.0, 1.0, 0}};
+static const double R5_C[8][8] = {
+    {0, 0, 0, 0, 0, 0, 0, 0},
+    {-14.155112264123755, 0, 0, 0, 0, 0, 0, 0},
+    {-17.97296035885952, -2.859693295451294, 0, 0, 0, 0, 0, 0},
+    {147.12150275711716, -1.41221402718213, 71.68940251302358, 0, 0, 0, 0, 0},
+    {165.43517024871676, -0.4592823456491126, 42.90938336958603,
+     -5.961986721573306, 0, 0, 0, 0},
+    {24.854864614690072, -3.0009227002832186, 47.4931110020768,
+     5.5814197821558125, -0.6610691825249471, 0, 0, 0},
+    {30.91273214028599, -3.1208243349937974, 77.79954646070892,
+     34.28646028294783, -19.097331116725623, -28.087943162872662, 0, 0},
+    {37.80277123390563, -3.2571969029072276, 112.26918849496327,
+     66.9347231244047, -40.06618937091002, -54.66780262877968,
+     -9.48861652309627, 0}};
+static const double R5_M[8] = {-7.502846399306121, 2.561846144803919,
+                               -11.627539656261098, -0.18268767659942256,
+                               0.030198172008377946, 1.0, 1.0, 1.0};
+static const double R5_MHAT[8] = {-7.502846399306121, 2.561846144803919,
+                                  -11.627539656261098, -0.18268767659942256,
+                                  0.030198172008377946, 1.0, 1.0, 0.0};
+
+void orc_rodas5p_tableau(double *gamma, double a[64], double C[64],
+                         double m[8], double mhat[8]) {
+  *gamma = R5_GAMMA;
+  for (int i = 0; i < 8; i++) {
+    m[i] = R5_M[i];
+    mhat[i] = R5_MHAT[i];
+    for (int j = 0; j < 8; j++) {
+      a[8 * i + j] = R5_A[i][j];
+      C[8 * i + j] = R5_C[i][j];
+    }
+  }
+}
+
 void orc_tsit5_tableau(double c[7], double a[49], double b[7],
                        double btilde[7]) {
   for (int i = 0; i < 7; i++) {
@@ -417,39 +473,54 @@ static void lu_solve(int n, const double *LU, const int *piv, double *x) {
 }
 
 /* Rosenbrock step (eqs. 5-8) in the transformed form stated above the
- * tableau: one Jacobian, one LU of W = I/(gamma h) - J, six solves.        */
-static void rodas4_step(int sys, const double *p, int n, const double *u,
-                        double h, double *unew, double *err) {
-  double J[NMAX * NMAX], W[NMAX * NMAX], U[6][NMAX], y[NMAX], fy[NMAX];
+ * tableaus: one Jacobian, one LU of W = I/(gamma h) - J, one solve per
+ * stage; ns stages with coefficient rows of stride ns.                      */
+static void rodas_step(int ns, double gamma, const double *A, const double *C,
+                       const double *M, const double *MHAT, int sys,
+                       const double *p, int n, const double *u, double h,
+                       double *unew, double *err) {
+  double J[NMAX * NMAX], W[NMAX * NMAX], U[8][NMAX], y[NMAX], fy[NMAX];
   int piv[NMAX];
   orc_jac(sys, p, u, J);
   for (int i = 0; i < n; i++)
     for (int j = 0; j < n; j++)
-      W[i * n + j] = (i == j ? 1.0 / (RO_GAMMA * h) : 0.0) - J[i * n + j];
+      W[i * n + j] = (i == j ? 1.0 / (gamma * h) : 0.0) - J[i * n + j];
   lu_factor(n, W, piv);
-  for (int i = 0; i < 6; i++) {
+  for (int i = 0; i < ns; i++) {
     for (int c = 0; c < n; c++) {
       double s = 0.0;
-      for (int j = 0; j < i; j++) s += RO_A[i][j] * U[j][c];
+      for (int j = 0; j < i; j++) s += A[ns * i + j] * U[j][c];
       y[c] = u[c] + s;
     }
     orc_rhs(sys, p, y, fy);
     for (int c = 0; c < n; c++) {
       double s = 0.0;
-      for (int j = 0; j < i; j++) s += RO_C[i][j] / h * U[j][c];
+      for (int j = 0; j < i; j++) s += C[ns * i + j] / h * U[j][c];
       U[i][c] = fy[c] + s;
     }
     lu_solve(n, W, piv, U[i]);
   }
   for (int c = 0; c < n; c++) {
     double s = 0.0, e = 0.0;
-    for (int j = 0; j < 6; j++) {
-      s += RO_M[j] * U[j][c];
-      e += (RO_M[j] - RO_MHAT[j]) * U[j][c];
+    for (int j = 0; j < ns; j++) {
+      s += M[j] * U[j][c];
+      e += (M[j] - MHAT[j]) * U[j][c];
     }
     unew[c] = u[c] + s;
     err[c] = e;
   }
+}
+
+static void rodas4_step(int sys, const double *p, int n, const double *u,
+                        double h, double *unew, double *err) {
+  rodas_step(6, RO_GAMMA, &RO_A[0][0], &RO_C[0][0], RO_M, RO_MHAT, sys, p, n, u,
+             h, unew, err);
+}
+
+static void rodas5p_step(int sys, const double *p, int n, const double *u,
+                         double h, double *unew, double *err) {
+  rodas_step(8, R5_GAMMA, &R5_A[0][0], &R5_C[0][0], R5_M, R5_MHAT, sys, p, n,
+             u, h, unew, err);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -555,8 +626,12 @@ static void solve_one(int sys, int alg, int n, const double *p,
                       int64_t maxiters, int save_mode) {
   /* PI exponent k = embedded order + 1; p = order of the propagated
    * solution (starting-step heuristic) */
-  const double kexp = (alg == ORC_TSIT5) ? 5.0 : (alg == ORC_RODAS4 ? 4.0 : 3.0);
-  const int porder = (alg == ORC_TSIT5) ? 5 : (alg == ORC_RODAS4 ? 4 : 2);
+  const double kexp = (alg == ORC_TSIT5 || alg == ORC_RODAS5P)
+                          ? 5.0
+                          : (alg == ORC_RODAS4 ? 4.0 : 3.0);
+  const int porder = (alg == ORC_TSIT5 || alg == ORC_RODAS5P)
+                         ? 5
+                         : (alg == ORC_RODAS4 ? 4 : 2);
   const int dense = save_mode == 1 && alg == ORC_TSIT5;
   double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX], kall[7][NMAX];
   double hmax = tf - t0;
@@ -599,6 +674,8 @@ static void solve_one(int sys, int alg, int n, const double *p,
       tsit5_step(sys, p, n, u, k1, he, unew, err, k7, kall);
     else if (alg == ORC_RODAS4)
       rodas4_step(sys, p, n, u, he, unew, err);
+    else if (alg == ORC_RODAS5P)
+      rodas5p_step(sys, p, n, u, he, unew, err);
     else
       ros23_step(sys, p, n, u, he, unew, err);
     double q = error_q(n, err, u, unew, atol, rtol);
@@ -651,7 +728,8 @@ int orc_solve_mode(int sys, int alg, int64_t N, const double *params,
                    int64_t maxiters, int nthreads, int save_mode) {
   int n, m;
   if (orc_dims(sys, &n, &m) != 0 || sys == ORC_GBM4) return -1;
-  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23) return -1;
+  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23 && alg != ORC_RODAS5P)
+    return -1;
   if (N < 0 || n_save < 1 || !params || !u0 || !tspan || !theta || !out)
     return -1;
   if (save_mode != 0 && save_mode != 1) return -1;
@@ -713,7 +791,8 @@ int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,
               int n_steps, double *u_out, double *uhat_out) {
   int n, m;
   if (orc_dims(sys, &n, &m) != 0) return -1;
-  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23) return -1;
+  if (alg != ORC_TSIT5 && alg != ORC_RODAS4 && alg != ORC_ROS23 && alg != ORC_RODAS5P)
+    return -1;
   double u[NMAX], k1[NMAX], unew[NMAX], err[NMAX], k7[NMAX];
   for (int c = 0; c < n; c++) u[c] = u0[c];
   orc_rhs(sys, p, u, k1);
@@ -722,6 +801,8 @@ int orc_fixed(int sys, int alg, const double *p, const double *u0, double h,
       tsit5_step(sys, p, n, u, k1, h, unew, err, k7, NULL);
     else if (alg == ORC_RODAS4)
       rodas4_step(sys, p, n, u, h, unew, err);
+    else if (alg == ORC_RODAS5P)
+      rodas5p_step(sys, p, n, u, h, unew, err);
     else
       ros23_step(sys, p, n, u, h, unew, err);
     if (s == n_steps - 1)

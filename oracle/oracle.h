@@ -35,7 +35,8 @@ enum {
   ORC_CRN = 7        /* appendix, sigma-factor CRN SDE (chemical Langevin), n = 4,
                         p = (S, D, tau, nu0, n, eta), 8 Wiener processes         */
 };
-enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3, ORC_EM = 4, ORC_SIEA = 5 };
+enum { ORC_TSIT5 = 1, ORC_RODAS4 = 2, ORC_ROS23 = 3, ORC_EM = 4, ORC_SIEA = 5,
+       ORC_RODAS5P = 6 };
 enum { ORC_OK = 0, ORC_MAXITERS = 1, ORC_DTMIN = 2, ORC_NONFINITE = 3 };
 
 int orc_dims(int sys, int *n, int *m);
@@ -119,6 +120,9 @@ void orc_tsit5_tableau(double c[7], double a[49], double b[7],
                        double btilde[7]);
 void orc_rodas4_tableau(double *gamma, double a[36], double C[36],
                         double m[6], double mhat[6]);
+/* Rodas5P (8 stages, a and C row-major [8][8], weights m, mhat [8]). */
+void orc_rodas5p_tableau(double *gamma, double a[64], double C[64],
+                         double m[8], double mhat[8]);
 
 #ifdef __cplusplus
 }

@@ -105,6 +105,49 @@ def rosenbrock_residuals(alpha, beta, b, gamma, p):
     return np.array([r for (q, r) in conds if q <= p])
 
 
+def rosenbrock_weight(t, alpha, B):
+    """Elementary weight vector of tree t for a Rosenbrock method: a vertex
+    with exactly one child couples through B = alpha + Gamma (the Jacobian
+    term enters only linearly), a vertex with several children through
+    alpha, one factor per child (Hairer & Wanner II, section IV.7)."""
+    s = alpha.shape[0]
+    if len(t) == 0:
+        return np.ones(s)
+    if len(t) == 1:
+        return B @ rosenbrock_weight(t[0], alpha, B)
+    v = np.ones(s)
+    for ch in t:
+        v = v * (alpha @ rosenbrock_weight(ch, alpha, B))
+    return v
+
+
+def rosenbrock_tree_residuals(alpha, Gamma, b, p):
+    """b^T Phi(t) - 1/gamma(t) for every rooted tree with |t| <= p, Phi the
+    Rosenbrock elementary weight with B = alpha + Gamma (Gamma lower
+    triangular with its diagonal): any order, unlike the explicit list of
+    rosenbrock_residuals, which it reproduces through order 4."""
+    B = alpha + Gamma
+    res = []
+    for q in range(1, p + 1):
+        for t in trees(q):
+            res.append(float(b @ rosenbrock_weight(t, alpha, B) - 1.0 / density(t)))
+    return np.array(res)
+
+
+def rosenbrock_transformed_full(gamma, a, C, m):
+    """(alpha, Gamma with diagonal, b) from transformed coefficients."""
+    s = a.shape[0]
+    G = np.linalg.inv(np.eye(s) / gamma - C)
+    return a @ G, G, m @ G
+
+
+def rosenbrock_stability(alpha, Gamma, b, z):
+    """R(z) = 1 + z b^T (I - z (alpha + Gamma))^-1 1 on y' = lambda y."""
+    B = alpha + Gamma
+    s = B.shape[0]
+    return 1.0 + z * (b @ np.linalg.solve(np.eye(s) - z * B, np.ones(s)))
+
+
 def continuous_extension(A, b, c, p=4):
     """Coefficients B [s][p] of a dense output u(t + theta h) = u + h sum_i
     b_i(theta) k_i with b_i(theta) = sum_m B[i][m-1] theta^m, chosen as:
