@@ -6,7 +6,7 @@ Tsit5 at reltol = abstol = 1e-6, 16 evenly spaced saves on t in [0, 1].
 One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
     python bench.py [--steps K] [--warmup W] [--workload lorenz_fp32|lorenz_fp64|
-                     robertson|gbm] [--alg rodas4|ros23]
+                     robertson|gbm] [--alg rodas4|rodas5p|ros23]
                     [--form plain|persistent|persistent_sorted_chunks|sorted|sorted_b512_r2|
                      sorted_staged|auto]
                     [--save-mode landing|dense]
@@ -40,10 +40,11 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 # Algorithmic flops per attempted step (FMA = 2), counted from the method:
 #  Tsit5, Lorenz (n = 3): stage combinations 144, 6 RHS x 8 = 48, error
 #    estimate 42, error norm 19, step-size control 7  -> 260.
-#  Rodas4, Robertson (n = 3): Jacobian 6, W 12, LU 26, 6 stages x (combination
-#    + RHS + solve-rhs + triangular solves) = 6 x 69 = 414 minus the
-#    empty first-stage combinations 18 -> 396, u_new 3, error norm 19,
-#    control 7  -> 466.
+#  Stiffly accurate Rosenbrock (RODAS4: 6 stages, Rodas5P: 8), Robertson
+#    (n = 3): Jacobian 6, W 12, LU 26; stage s = 0..S-1: stage point 6s, RHS 8,
+#    C-combination 6s + 6, triangular solves 15  -> 12s + 29 per stage, so
+#    12 S(S-1)/2 + 29 S over the stages (354 for S = 6, 568 for S = 8); u_new
+#    3, error norm 19, control 7  -> 427 (RODAS4), 641 (Rodas5P).
 #  Rosenbrock23, Robertson (n = 3): Jacobian 6, W 12, LU 26, three solves
 #    3 x 15, two RHS 2 x 8, stage right-hand sides and points 3 + 3 + 18 + 7
 #    + 6, error estimate 13, error norm 19, control 7  -> 181.
@@ -53,7 +54,8 @@ METRIC = "trajectories/sec at stated tolerance (FP32 vs FP64, plain vs persisten
 #    points, the three combinations) + Box-Muller 16 -> 132.
 #  EM, CRN: per step drift 14 + Hill term 10 (two powers as exp2/log2 counted
 #    as 1 each) + 8 noise terms 24 + updates 8, + Box-Muller 4 x 8 -> 88.
-FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 466, ("ros23", "robertson"): 181,
+FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 427, ("rodas5p", "robertson"): 641,
+         ("ros23", "robertson"): 181,
          ("em", "gbm4"): 32, ("siea", "gbm4"): 132, ("em", "crn"): 88}
 # Tsit5 dense output, per save time read off a step (save mode 1; every save
 # but the last, which a step lands on): theta 2; h b_0(theta) by Horner 8;
@@ -97,7 +99,7 @@ def parse():
                     choices=["lorenz_fp32", "lorenz_fp64", "robertson", "gbm", "orego", "hires",
                              "pollu", "crn"])
     ap.add_argument("--n", type=int, default=0, help="override the ensemble size")
-    ap.add_argument("--alg", default="", choices=["", "rodas4", "ros23", "siea"],
+    ap.add_argument("--alg", default="", choices=["", "rodas4", "rodas5p", "ros23", "siea"],
                     help="stiff method of the Robertson and appendix-B.1 workloads (default "
                          "rodas4), or siea for the GBM workload")
     ap.add_argument("--form", default="",
@@ -157,14 +159,13 @@ def describe(e):
                 "compensated time, Tsit5 rtol=atol=1e-6, 16 saves on [0,1]")
     if e.name == "lorenz_fp64":
         return "Lorenz 8192-ensemble, rho~U[0,21], FP64, Tsit5 rtol=atol=1e-8, final state"
+    method = {"ros23": "Rosenbrock23", "rodas5p": "Rodas5P"}.get(e.alg, "Rodas4")
     if e.name in ("orego", "hires", "pollu"):
         return (f"{e.name.upper()} 8192-ensemble (appendix B.1), rate constants x logU[0.5,2], "
-                f"{'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 atol=1e-8, "
-                "4 saves")
+                f"{method} rtol=1e-6 atol=1e-8, 4 saves")
     if e.name == "robertson":
         return ("Robertson 2^20-ensemble, rates x logU[0.5,2], tf~logU[1,1e5], FP32 state + "
-                f"FP64 W/LU, {'Rosenbrock23' if e.alg == 'ros23' else 'Rodas4'} rtol=1e-6 "
-                "atol=1e-8, final state")
+                f"FP64 W/LU, {method} rtol=1e-6 atol=1e-8, final state")
     if e.name == "crn":
         return ("sigma-factor CRN SDE (appendix), 10^6-trajectory Cartesian parameter sweep, "
                 "Euler-Maruyama dt=0.1 on [0,1000] (10^4 steps), 8 Wiener processes, FP32")
@@ -327,7 +328,8 @@ def cpu_baseline(e, gpu_out, seconds):
             oalg = oracle.EM if e.alg == "em" else oracle.SIEA
             return oracle.sde(sid, oalg, p, u, e.dt, e.n_steps, e.seed, ids=idx,
                               nthreads=nth)[None]
-        alg = {"tsit5": oracle.TSIT5, "rodas4": oracle.RODAS4, "ros23": oracle.ROS23}[e.alg]
+        alg = {"tsit5": oracle.TSIT5, "rodas4": oracle.RODAS4, "ros23": oracle.ROS23,
+               "rodas5p": oracle.RODAS5P}[e.alg]
         if tol is not None and alg == oracle.ROS23:  # the truth comes from the 4th-order method
             alg = oracle.RODAS4
         at = e.abstol if tol is None else tol
@@ -382,17 +384,17 @@ def form_variants(e, precision, steps, base_out, plain_ms, save_mode=0, forms=No
     return out
 
 
-def stiff_ros23_variant(rob, steps, rodas4_forms):
-    """The Robertson ensemble with Rosenbrock23 instead of Rodas4: every form
-    (bitwise check against its own plain form), attempts, the algorithmic
-    rate of the fastest form, its speedup over the fastest Rodas4 form, and
-    the error of a 4096 subsample against the FP64 truth (Rodas4 oracle at
-    tol 1e-12)."""
+def stiff_method_variant(alg, steps, rodas4_forms):
+    """The Robertson ensemble with another stiff method (Rosenbrock23 or
+    Rodas5P) instead of Rodas4: every form (bitwise check against its own
+    plain form), attempts, the algorithmic rate of the fastest form, its
+    speedup over the fastest Rodas4 form, and the error of a 4096 subsample
+    against the FP64 truth (Rodas4 oracle at tol 1e-12)."""
     import numpy as np
 
     import oracle
     from paper_2304_06835_amd import workloads as W
-    e = W.robertson(alg="ros23")
+    e = W.robertson(alg=alg)
     base = _plain_out(e)
     fv = form_variants(e, 32, steps, base, None, forms=STIFF_FORMS)
     pm = fv["plain"]["kernel_ms"]
@@ -403,7 +405,7 @@ def stiff_ros23_variant(rob, steps, rodas4_forms):
     attempts, stats = r.attempts()
     del r
     ms = fv[best]["kernel_ms"]
-    fl = FLOPS[("ros23", "robertson")] * attempts / (ms * 1e-3) / 1e12
+    fl = FLOPS[(alg, "robertson")] * attempts / (ms * 1e-3) / 1e12
     idx = W.sample_indices(e.n, 4096)
     truth = oracle.solve(oracle.ROBERTSON, oracle.RODAS4, np.ascontiguousarray(e.params[:, idx]),
                          np.ascontiguousarray(e.u0[:, idx]), np.ascontiguousarray(e.tspan[:, idx]),
@@ -430,10 +432,11 @@ def stiff_variant(steps):
     from paper_2304_06835_amd import workloads as W
     res = {}
     for name in ("orego", "hires", "pollu"):
-        for alg in ("rodas4", "ros23"):
+        for alg in ("rodas4", "rodas5p", "ros23"):
             e = W.stiff(name, alg=alg)
             sid = {"orego": oracle.OREGO, "hires": oracle.HIRES, "pollu": oracle.POLLU}[name]
-            oalg = oracle.RODAS4 if alg == "rodas4" else oracle.ROS23
+            oalg = {"rodas4": oracle.RODAS4, "rodas5p": oracle.RODAS5P,
+                    "ros23": oracle.ROS23}[alg]
             t0 = time.perf_counter()
             oracle.solve(sid, oalg, e.params, e.u0, e.tspan, e.abstol, e.reltol, e.theta)
             cpu_s = time.perf_counter() - t0
@@ -677,7 +680,16 @@ def main():
             for v in rv.values():
                 v["speedup_vs_plain"] = rp / v["kernel_ms"]
             variants["robertson_2p20_forms"] = rv
-            variants["robertson_2p20_ros23"] = stiff_ros23_variant(rob, args.steps, rv)
+            variants["robertson_2p20_ros23"] = stiff_method_variant("ros23", args.steps, rv)
+            r5 = stiff_method_variant("rodas5p", args.steps, rv)
+            variants["robertson_2p20_rodas5p"] = r5
+            # the paper's stiff table gives times relative to Rodas5P (section 6.4)
+            t5 = r5["forms"][r5["fastest_form"]]["kernel_ms"]
+            r23 = variants["robertson_2p20_ros23"]
+            variants["robertson_2p20_time_relative_to_rodas5p"] = {
+                "rodas5p": 1.0,
+                "rodas4": min(v["kernel_ms"] for v in rv.values()) / t5,
+                "ros23": r23["forms"][r23["fastest_form"]]["kernel_ms"] / t5}
             variants["lorenz_fp64_8192"] = config_variant("lorenz_fp64", 64, args.steps)
             variants["gbm_em_2p22"] = config_variant("gbm", 32, args.steps)
             variants["gbm_siea_2p22"] = config_variant("gbm", 32, args.steps, alg="siea")

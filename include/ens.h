@@ -99,6 +99,10 @@ typedef struct ens_ctx ens_ctx;
                             (Kloeden-Platen explicit order-2.0 weak scheme, the
                             reading of GPUSIEA), Philox4x32-10 normals as for EM
                                                             sec. 3.3, 5.2.2     */
+#define ENS_ALG_RODAS5P 6 /* adaptive Rodas5P (Steinebach 2023): 8-stage stiffly
+                            accurate Rosenbrock method of order 5 with an
+                            embedded order-4 estimate, W = I - gamma h J,
+                            FP64 LU and solves      sec. 3.2.1, 5.2.1, 6.4 */
 #define ENS_ALG_ROS23 4  /* adaptive Rosenbrock23: the L-stable 2(3) modified
                             Rosenbrock pair of Shampine & Reichelt, W = I - d h J
                             with d = 1/(2 + sqrt 2), FP64 LU, solves and stage
@@ -107,7 +111,8 @@ typedef struct ens_ctx ens_ctx;
 /* ---- scalar options (ens_set_option) ------------------------------------ */
 #define ENS_OPT_PRECISION 1 /* 32 (default): FP32 state, compensated time
                                (a TwoSum float pair for TSIT5, an FP64 pair
-                               with FP64 W/LU/solves for RODAS4 and ROS23);
+                               with FP64 W/LU/solves for RODAS4, RODAS5P and
+                               ROS23);
                                64: FP64 throughout.  Also the dtype of params,
                                u0 and out.                                      */
 #define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;
@@ -211,7 +216,7 @@ int ens_system_dims(int system_id, int *n, int *m);
  *   alg        ENS_ALG_*; (system, alg) must be one of
  *              {LINEAR, LORENZ} x TSIT5,
  *              {LINEAR, LORENZ, ROBERTSON, OREGO, HIRES, POLLU} x {RODAS4,
- *              ROS23}, {GBM4, CRN} x EM, GBM4 x SIEA
+ *              RODAS5P, ROS23}, {GBM4, CRN} x EM, GBM4 x SIEA
  *   abstol, reltol  > 0 for adaptive algorithms (ignored by EM and SIEA)
  *   save_times HOST, [n_save] fractions theta_j, 0 < theta_0 < ... <= 1; save
  *              j of trajectory i is at t0_i + theta_j (tf_i - t0_i).  Adaptive

@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(PKG, "libens.so")
 ENS_OK, ENS_EINVAL, ENS_ENOMEM, ENS_EDEVICE, ENS_EUNSUPPORTED = 0, -1, -2, -3, -4
 SYSTEMS = {"linear": 0, "lorenz": 1, "robertson": 2, "gbm4": 3, "orego": 4, "hires": 5,
            "pollu": 6, "crn": 7}
-ALGS = {"tsit5": 1, "rodas4": 2, "em": 3, "ros23": 4, "siea": 5}
+ALGS = {"tsit5": 1, "rodas4": 2, "em": 3, "ros23": 4, "siea": 5, "rodas5p": 6}
 OPTS = {"precision": 1, "form": 2, "block": 3, "dt": 4, "seed": 5, "h0": 6,
         "maxiters": 7, "tspan_broadcast": 8, "refill": 9, "grid": 10, "tpl": 11,
         "mlp_tile": 12, "save_mode": 13, "stage_saves": 14, "autotune_cached": 15}

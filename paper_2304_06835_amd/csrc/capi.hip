@@ -16,6 +16,7 @@ namespace ens {
 int tsit5_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 int rodas4_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 int ros23_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
+int rodas5p_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 
 __global__ void zero_counter(unsigned long long* q) {
   if (threadIdx.x == 0) *q = 0ull;
@@ -27,9 +28,10 @@ hipError_t reset_queue(unsigned long long* q, hipStream_t s) {
 }
 
 int persistent_grid(int alg, int sys, int prec, int block, int num_cu, int form, int tpl) {
-  const int per_cu = alg == ENS_ALG_RODAS4  ? rodas4_blocks_per_cu(sys, prec, block, form, tpl)
-                     : alg == ENS_ALG_ROS23 ? ros23_blocks_per_cu(sys, prec, block, form, tpl)
-                                            : tsit5_blocks_per_cu(sys, prec, block, form, tpl);
+  const int per_cu = alg == ENS_ALG_RODAS4    ? rodas4_blocks_per_cu(sys, prec, block, form, tpl)
+                     : alg == ENS_ALG_ROS23   ? ros23_blocks_per_cu(sys, prec, block, form, tpl)
+                     : alg == ENS_ALG_RODAS5P ? rodas5p_blocks_per_cu(sys, prec, block, form, tpl)
+                                              : tsit5_blocks_per_cu(sys, prec, block, form, tpl);
   return per_cu * num_cu;
 }
 }  // namespace ens
@@ -57,6 +59,7 @@ bool supported(int sys, int alg) {
     case ENS_ALG_TSIT5: return sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR;
     case ENS_ALG_RODAS4:
     case ENS_ALG_ROS23:
+    case ENS_ALG_RODAS5P:
       return sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR ||
              sys == ENS_SYS_OREGO || sys == ENS_SYS_HIRES || sys == ENS_SYS_POLLU;
     case ENS_ALG_EM: return sys == ENS_SYS_GBM4 || sys == ENS_SYS_CRN;
@@ -75,7 +78,7 @@ int check_problem(ens_ctx* c, int sys, int64_t n, const void* params, const void
   if (ens_system_dims(sys, &nn, &mm) != ENS_OK)
     return fail(c, ENS_EINVAL, "unknown system_id %d", sys);
   if (alg != ENS_ALG_TSIT5 && alg != ENS_ALG_RODAS4 && alg != ENS_ALG_EM &&
-      alg != ENS_ALG_ROS23 && alg != ENS_ALG_SIEA)
+      alg != ENS_ALG_ROS23 && alg != ENS_ALG_SIEA && alg != ENS_ALG_RODAS5P)
     return fail(c, ENS_EINVAL, "unknown alg %d", alg);
   if (!supported(sys, alg))
     return fail(c, ENS_EUNSUPPORTED, "system %d has no kernel for alg %d", sys, alg);
@@ -187,9 +190,10 @@ int ens::launch_solve(ens_ctx* c, int sys, int alg, ens::LaunchArgs a,
     } else {
       a.refill = 64;
     }
-    e = alg == ENS_ALG_TSIT5    ? ens::launch_tsit5(sys, c->precision, cfg, a, s)
-        : alg == ENS_ALG_RODAS4 ? ens::launch_rodas4(sys, c->precision, cfg, a, s)
-                                : ens::launch_ros23(sys, c->precision, cfg, a, s);
+    e = alg == ENS_ALG_TSIT5     ? ens::launch_tsit5(sys, c->precision, cfg, a, s)
+        : alg == ENS_ALG_RODAS4  ? ens::launch_rodas4(sys, c->precision, cfg, a, s)
+        : alg == ENS_ALG_RODAS5P ? ens::launch_rodas5p(sys, c->precision, cfg, a, s)
+                                 : ens::launch_ros23(sys, c->precision, cfg, a, s);
   }
   if (e != hipSuccess) return fail(c, ENS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return ENS_OK;

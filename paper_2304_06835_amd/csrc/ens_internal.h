@@ -57,6 +57,8 @@ hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                          hipStream_t s);
 hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                         hipStream_t s);
+hipError_t launch_rodas5p(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
+                          hipStream_t s);
 hipError_t launch_em(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                      hipStream_t s);
 

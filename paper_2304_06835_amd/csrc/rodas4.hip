@@ -13,13 +13,14 @@
 // the six triangular solves run in FP64 -- the per-system block-diagonal LU
 // of section 5.1.3 (eq. 16), held in registers.
 #include "pollu.h"
+#include "rodas.h"
 #include "rosenbrock.h"
 #include "systems.h"
 
 namespace ens {
 namespace {
 
-constexpr double kGamma = 0.25;
+constexpr double kGamma4 = 0.25;
 constexpr double RA[6][6] = {
     {0, 0, 0, 0, 0, 0},
     {1.544, 0, 0, 0, 0, 0},
@@ -36,54 +37,16 @@ constexpr double RC[6][6] = {
     {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136,
      -6.058818238834054, 0}};
 
-struct Rodas4 {
+// RODAS4 as a stiffly accurate Rosenbrock tableau (the step is in rodas.h).
+struct Rodas4Tab {
+  static constexpr int kStages = 6;
+  static constexpr double kGamma = kGamma4;
   static constexpr double kK = 4.0;  // PI exponent: embedded order 3 + 1
   static constexpr double kP = 4.0;
-  static constexpr bool kFsal = false;
-
-  template <class R, class S>
-  __device__ static inline void step(const R* p, const R* u, const R*, R he, R* unew, R* err,
-                                     R*) {
-    constexpr int N = S::N;
-    // W = I/(gamma h) - J, factored in FP64
-    typename WOf<S>::type W;
-    W.build(p, u, recip(kGamma * (double)he), 1.0);
-
-    const R inv_h = Num<R>::rcp(he);  // FP32: the hardware reciprocal (1 ulp)
-    with_pivoting(W, [&](auto piv) {
-      constexpr bool P = decltype(piv)::value;
-      R U[6][N], y[N], fy[N];
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          R acc = u[c];
-#pragma unroll
-          for (int q = 0; q < s; ++q) acc = fma((R)RA[s][q], U[q][c], acc);
-          y[c] = acc;
-        }
-        S::f(p, y, fy);
-        double x[N];
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          R cs = 0;
-#pragma unroll
-          for (int q = 0; q < s; ++q) cs = fma((R)RC[s][q], U[q][c], cs);
-          x[c] = (double)fma(cs, inv_h, fy[c]);
-        }
-        W.template solve<P>(x);
-#pragma unroll
-        for (int c = 0; c < N; ++c) U[s][c] = (R)x[c];
-      }
-      // u_new = 6th stage point + U_6; error estimate U_6
-#pragma unroll
-      for (int c = 0; c < N; ++c) {
-        unew[c] = y[c] + U[5][c];
-        err[c] = U[5][c];
-      }
-    });
-  }
+  __device__ static constexpr double a(int i, int j) { return RA[i][j]; }
+  __device__ static constexpr double c(int i, int j) { return RC[i][j]; }
 };
+using Rodas4 = StifflyAccurateRosenbrock<Rodas4Tab>;
 
 }  // namespace
 

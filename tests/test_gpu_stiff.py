@@ -34,7 +34,7 @@ from tests.test_gpu_ode import run
 pytestmark = pytest.mark.gpu
 
 SYS = {"orego": 4, "hires": 5, "pollu": 6}
-ALG = {"rodas4": 2, "ros23": 3}
+ALG = {"rodas4": 2, "ros23": 3, "rodas5p": 6}
 
 
 @pytest.fixture(scope="module")
@@ -76,7 +76,7 @@ def check_fp32(name, worst, bar, err):
 
 
 @pytest.mark.parametrize("name", ["orego", "hires", "pollu"])
-@pytest.mark.parametrize("alg", ["rodas4", "ros23"])
+@pytest.mark.parametrize("alg", ["rodas4", "rodas5p", "ros23"])
 def test_fp64_matches_oracle(ens, orc, name, alg):
     e = W.stiff(name, N=515, dtype=np.float64, alg=alg)   # ragged: 2 blocks + 3
     banner(f"{name} fp64 {alg} N={e.n}")
@@ -96,7 +96,7 @@ def test_fp64_matches_oracle(ens, orc, name, alg):
     assert same >= 0.95
 
 
-@pytest.mark.parametrize("alg", ["rodas4", "ros23"])
+@pytest.mark.parametrize("alg", ["rodas4", "rodas5p", "ros23"])
 def test_pivoting_lu_matches_oracle(ens, orc, alg):
     """W = I/(gamma h) - A for a lower-triangular A whose sub-diagonal entries
     exceed the diagonal of W: every factorisation swaps rows in column 0 and
@@ -133,17 +133,28 @@ def test_pivoting_lu_matches_oracle(ens, orc, alg):
     print("pivot %s: vs oracle max %.3e median %.3e, identical attempts %.3f, mean attempts %.1f;"
           " vs e^{At}u0 max %.3e" % (alg, err.max(), np.median(err), same,
                                       stats.sum(0).mean(), eex.max()))
-    # W here has condition ~5e3: a 1e-15 relative change of A moves the
-    # oracle's answer by up to 5e-12, so rounding-order differences sit well
-    # below 1e-10 (the pre-fix factorisation was off by O(1) in these solves)
-    assert err.max() <= 1e-10
-    assert np.median(err) <= 1e-12
-    assert same >= 0.98
+    # Rounding-order parity, measured on the problem itself: W is
+    # ill-conditioned here (condition ~|a10 a21| / (gamma h)^-2), so a 1e-15
+    # relative change of A moves the oracle's own answer by up to ~5e-12
+    # (Rodas4, Rosenbrock23) or ~6e-10 (Rodas5P, whose long steps make W
+    # worse conditioned) and changes its step counts in part of the
+    # ensemble.  The GPU must sit within 10x that response and take the same
+    # steps as often as the perturbed oracle does (the pre-fix factorisation
+    # was off by O(1) in these solves).
+    P = A * (1 + 1e-15 * np.random.default_rng(5).standard_normal(A.shape))
+    pr, _, pna, pnr = orc.solve(orc.LINEAR, ALG[alg], P, u0, tspan, tol, tol, theta)
+    resp = normwise(pr, ref)
+    psame = np.mean((pna == na) & (pnr == nr))
+    print("  oracle response to a 1e-15 perturbation of A: max %.3e median %.3e, same "
+          "attempts %.3f" % (resp.max(), np.median(resp), psame))
+    assert err.max() <= max(1e-10, 10 * resp.max())
+    assert np.median(err) <= max(1e-12, 10 * np.median(resp))
+    assert same >= min(0.98, psame - 0.1)
     assert eex.max() <= 2 * normwise(ref, ex).max() + 1e-12
 
 
 @pytest.mark.parametrize("name", ["orego", "hires", "pollu"])
-@pytest.mark.parametrize("alg", ["rodas4", "ros23"])
+@pytest.mark.parametrize("alg", ["rodas4", "rodas5p", "ros23"])
 def test_fp32_accuracy_and_invariants(ens, orc, name, alg):
     e = W.stiff(name, N=300, alg=alg)
     banner(f"{name} fp32 {alg} N={e.n}")
