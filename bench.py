@@ -461,6 +461,59 @@ def stiff_variant(steps):
     return res
 
 
+def mixed_variant(steps):
+    """Mixed systems in one launch (ens_solve_mixed) against the same groups
+    solved by separate launches one after another on the stream (each in
+    the sorted form with block 256), Rodas4 FP32: the appendix-B.1 OREGO
+    ensemble and a Robertson ensemble at the paper's 8192 trajectories each
+    (small ensembles whose single launches cannot fill the GPU), and at
+    2^20 Robertson + 2^16 OREGO.  The answers are bitwise the same."""
+    import numpy as np
+    import torch
+
+    import paper_2304_06835_amd as ens
+    from paper_2304_06835_amd import workloads as W
+    res = {}
+    for label, n_rob, n_or in (("robertson_8192+orego_8192", 8192, 8192),
+                               ("robertson_2p20+orego_2p16", 1 << 20, 1 << 16)):
+        gs = [W.robertson(N=n_rob), W.stiff("orego", N=n_or)]
+        dev_g = [{"system": e.system, "params": dev(e.params), "u0": dev(e.u0),
+                  "tspan": dev(e.tspan)} for e in gs]
+        theta = [1.0]
+        outs = [torch.empty((1, 3, e.n), dtype=torch.float32, device="cuda") for e in gs]
+        for g, o in zip(dev_g, outs):
+            g["out"] = o
+        # one block per chunk (default) and the persistent queue (form 3)
+        mixed = ens.Solver(0, precision=32, h0=1e-4)
+        _, b_ms, _ = event_time(lambda: mixed.solve_mixed(dev_g, "rodas4", 1e-8, 1e-6, theta),
+                                max(3, steps), 2)
+        block_h = [o.cpu().numpy() for o in outs]
+        mixed.set(form=3)
+        _, m_ms, _ = event_time(lambda: mixed.solve_mixed(dev_g, "rodas4", 1e-8, 1e-6, theta),
+                                max(3, steps), 2)
+        mixed_h = [o.cpu().numpy() for o in outs]
+        sep = ens.Solver(0, precision=32, h0=1e-4, form=2, block=256)
+
+        def separate():
+            for g, o in zip(dev_g, outs):
+                sep.solve(g["system"], g["params"], g["u0"], g["tspan"], "rodas4", 1e-8, 1e-6,
+                          theta, out=o)
+        _, s_ms, _ = event_time(separate, max(3, steps), 2)
+        same = all(np.array_equal(a.view(np.uint8), o.cpu().numpy().view(np.uint8)) and
+                   np.array_equal(b.view(np.uint8), a.view(np.uint8))
+                   for a, b, o in zip(mixed_h, block_h, outs))
+        n = sum(e.n for e in gs)
+        res[label] = {"mixed_persistent_ms": m_ms, "mixed_block_per_chunk_ms": b_ms,
+                      "separate_launches_ms": s_ms,
+                      "speedup_vs_separate_persistent": s_ms / m_ms,
+                      "speedup_vs_separate_block_per_chunk": s_ms / b_ms,
+                      "traj_per_s_mixed_best": n / (min(m_ms, b_ms) * 1e-3),
+                      "bitwise_equal_to_separate": same}
+        mixed.close()
+        sep.close()
+    return res
+
+
 def config_variant(name, precision, steps, alg=""):
     """Another configuration of the path at its own size: time, throughput,
     algorithmic rate and the error against the FP64 oracle.  Lorenz FP64 is
@@ -695,6 +748,7 @@ def main():
             variants["gbm_siea_2p22"] = config_variant("gbm", 32, args.steps, alg="siea")
             variants["crn_em_1e6"] = config_variant("crn", 32, 3)
             variants["stiff_appendix_b1_8192"] = stiff_variant(args.steps)
+            variants["mixed_systems_one_launch"] = mixed_variant(args.steps)
             if not args.no_surrogate:
                 variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms)
 

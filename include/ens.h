@@ -236,6 +236,53 @@ int ens_solve(ens_ctx *ctx, int system_id, int64_t n_traj, const void *params,
               void *stream);
 
 /*
+ * Mixed systems in one launch.  The paper's kernels give every thread a
+ * whole trajectory (section 5.2) and note that adaptive steps make the work
+ * per thread uneven (section 6.4); ens_solve_mixed extends the ensemble to
+ * several groups, each an ensemble of its own system with its own arrays
+ * (laid out as for ens_solve), solved by one kernel launch over a work queue
+ * of chunks of 256 trajectories of any group: no chunk mixes systems, and
+ * the groups' uneven work is balanced over the whole GPU in one launch
+ * instead of one launch running after another.  The queue holds the groups
+ * with fewer chunks first.  With ENS_OPT_FORM 3 a persistent grid drains it
+ * through an atomic counter; with any other form every chunk is one block of
+ * a grid the hardware dispatches (measured faster).  Each chunk is sorted by
+ * expected work as in ENS_OPT_FORM 2, and every trajectory gets exactly the
+ * bits ens_solve gives it.
+ *
+ *   groups[g]   system_id; n_traj; params [m][n_traj], u0 [n][n_traj], out
+ *               [n_save][n][n_traj] (device, dtype of ENS_OPT_PRECISION);
+ *               tspan device float64 [2][n_traj], or [2] when
+ *               tspan_broadcast is 1; status uint8 [n_traj] and stats int32
+ *               [2][n_traj] device arrays or NULL (as ENS_PTR_STATUS/STATS)
+ *   n_groups    1..8; groups with n_traj 0 are allowed
+ *   alg         ENS_ALG_TSIT5 (systems LORENZ, LINEAR) or ENS_ALG_RODAS4,
+ *               ENS_ALG_RODAS5P, ENS_ALG_ROS23 (systems ROBERTSON, OREGO,
+ *               LORENZ, LINEAR); other systems or algorithms ENS_EUNSUPPORTED
+ *   abstol, reltol, save_times, n_save   shared by all groups, as ens_solve
+ *
+ * Context options used: ENS_OPT_PRECISION, H0, MAXITERS, SAVE_MODE, FORM
+ * (3: persistent queue, else one block per chunk) and GRID (blocks of the
+ * persistent grid; 0 fills every CU); BLOCK, TPL and the context's
+ * STATUS/STATS pointers are not.  Returns after enqueueing.
+ */
+typedef struct ens_group {
+  int system_id;
+  int tspan_broadcast;
+  int64_t n_traj;
+  const void *params;
+  const void *u0;
+  const double *tspan;
+  void *out;
+  uint8_t *status;
+  int32_t *stats;
+} ens_group;
+
+int ens_solve_mixed(ens_ctx *ctx, int n_groups, const ens_group *groups, int alg,
+                    double abstol, double reltol, const double *save_times,
+                    int n_save, void *stream);
+
+/*
  * The raw Philox4x32-10 words the ENS_ALG_EM kernel draws at step `step`:
  * out[k][i] (k = 0..3, uint32, device, [4][n_traj]) = word k of
  * Philox4x32-10(counter = (step, i mod 2^32, i >> 32, 0), key = seed) (the

@@ -132,6 +132,54 @@ class Solver:
                                       out.data_ptr(), s))
         return out
 
+    def solve_mixed(self, groups, alg: str = "rodas4", abstol: float = 1e-6,
+                    reltol: float = 1e-6, save_times: Iterable[float] = (1.0,), stream=None):
+        """ens_solve_mixed: one persistent launch over several groups, each a
+        dict with system, params, u0, tspan and optionally out, status, stats
+        (torch device tensors, laid out as for solve()).  Returns the list of
+        output tensors, one per group."""
+        torch = _torch()
+        theta = [float(x) for x in save_times]
+        th = (ctypes.c_double * len(theta))(*theta)
+        dtype = torch.float64 if int(self.get("precision")) == 64 else torch.float32
+        arr = (_native.Group * len(groups))()
+        outs = []
+        for g, G in enumerate(groups):
+            system, params, u0, tspan = G["system"], G["params"], G["u0"], G["tspan"]
+            n, m = system_dims(system)
+            N = u0.shape[1]
+            if u0.shape != (n, N) or params.shape != (m, N):
+                raise ValueError(f"group {g}: params must be [{m}][N] and u0 [{n}][N]")
+            for name, t in (("params", params), ("u0", u0), ("tspan", tspan)):
+                if not t.is_cuda or not t.is_contiguous():
+                    raise ValueError(f"group {g}: {name} must be a contiguous device tensor")
+            if params.dtype != dtype or u0.dtype != dtype or tspan.dtype != torch.float64:
+                raise ValueError(f"group {g}: params/u0 must be {dtype}, tspan float64")
+            if tspan.shape not in ((2,), (2, N)):
+                raise ValueError(f"group {g}: tspan must be [2] or [2][N]")
+            out = G.get("out")
+            if out is None:
+                out = torch.empty((len(theta), n, N), dtype=dtype, device=u0.device)
+            elif out.shape != (len(theta), n, N) or out.dtype != dtype or not out.is_contiguous():
+                raise ValueError(f"group {g}: out has the wrong shape, dtype or layout")
+            st, sts = G.get("status"), G.get("stats")
+            if st is not None and (st.dtype != torch.uint8 or st.numel() != N):
+                raise ValueError(f"group {g}: status must be uint8 [N]")
+            if sts is not None and (sts.dtype != torch.int32 or sts.shape != (2, N)):
+                raise ValueError(f"group {g}: stats must be int32 [2][N]")
+            arr[g] = _native.Group(SYSTEMS[system], 1 if tspan.shape == (2,) else 0, N,
+                                   params.data_ptr(), u0.data_ptr(), tspan.data_ptr(),
+                                   out.data_ptr(), st.data_ptr() if st is not None else None,
+                                   sts.data_ptr() if sts is not None else None)
+            outs.append(out)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        elif not isinstance(stream, int):
+            stream = stream.cuda_stream
+        self._check(self._L.ens_solve_mixed(self._ctx, len(groups), arr, ALGS[alg], abstol,
+                                            reltol, th, len(theta), stream))
+        return outs
+
     def autotune(self, system: str, params, u0, tspan, alg: str = "tsit5",
                  abstol: float = 1e-6, reltol: float = 1e-6,
                  save_times: Iterable[float] = (1.0,), out=None, stream=None):

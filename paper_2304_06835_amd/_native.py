@@ -21,7 +21,7 @@ STATIC_MAX_QUERIES = 1 << 20      # ENS_STATIC_MAX_QUERIES
 # Every symbol include/ens.h declares.
 EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
            "ens_get_option", "ens_set_ptr", "ens_system_dims", "ens_solve",
-           "ens_autotune", "ens_set_autotune_file", "ens_philox_fill", "ens_surrogate_create", "ens_surrogate_destroy",
+           "ens_autotune", "ens_set_autotune_file", "ens_solve_mixed", "ens_philox_fill", "ens_surrogate_create", "ens_surrogate_destroy",
            "ens_surrogate_copy", "ens_surrogate_get_step", "ens_surrogate_set_step",
            "ens_surrogate_fit_norm", "ens_surrogate_train_step", "ens_surrogate_train",
            "ens_surrogate_predict", "ens_surrogate_solve", "ens_surrogate_save",
@@ -34,6 +34,14 @@ class EnsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"ens error {code}: {msg}")
         self.code = code
+
+
+class Group(ctypes.Structure):
+    """struct ens_group of include/ens.h."""
+    _fields_ = [("system_id", ctypes.c_int), ("tspan_broadcast", ctypes.c_int),
+                ("n_traj", ctypes.c_int64), ("params", ctypes.c_void_p),
+                ("u0", ctypes.c_void_p), ("tspan", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
 _lib = None
@@ -63,6 +71,8 @@ def lib() -> ctypes.CDLL:
     L.ens_autotune.argtypes = [vp, c_int, i64, vp, vp, vp, c_int, dbl, dbl, dp, c_int, vp, vp,
                                dp]
     L.ens_set_autotune_file.argtypes = [vp, ctypes.c_char_p]
+    L.ens_solve_mixed.argtypes = [vp, c_int, ctypes.POINTER(Group), c_int, dbl, dbl, dp, c_int,
+                                  vp]
     L.ens_philox_fill.argtypes = [vp, ctypes.c_uint64, i64, ctypes.c_uint32, vp, vp]
     u64 = ctypes.c_uint64
     L.ens_surrogate_create.argtypes = [vp, u64, ctypes.POINTER(vp)]

@@ -2,6 +2,7 @@
 // argument validation, launch-shape selection and the autotuner.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -17,6 +18,34 @@ int tsit5_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 int rodas4_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 int ros23_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
 int rodas5p_blocks_per_cu(int sys, int prec, int block, int form, int tpl);
+hipError_t launch_tsit5_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s);
+hipError_t launch_rodas4_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s);
+hipError_t launch_rodas5p_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s);
+hipError_t launch_ros23_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s);
+int tsit5_mixed_blocks(int prec);
+int rodas4_mixed_blocks(int prec);
+int rodas5p_mixed_blocks(int prec);
+int ros23_mixed_blocks(int prec);
+
+hipError_t launch_mixed(int alg, int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  switch (alg) {
+    case ENS_ALG_TSIT5: return launch_tsit5_mixed(prec, grid, m, s);
+    case ENS_ALG_RODAS4: return launch_rodas4_mixed(prec, grid, m, s);
+    case ENS_ALG_RODAS5P: return launch_rodas5p_mixed(prec, grid, m, s);
+    case ENS_ALG_ROS23: return launch_ros23_mixed(prec, grid, m, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+int mixed_blocks_per_cu(int alg, int prec) {
+  switch (alg) {
+    case ENS_ALG_TSIT5: return tsit5_mixed_blocks(prec);
+    case ENS_ALG_RODAS4: return rodas4_mixed_blocks(prec);
+    case ENS_ALG_RODAS5P: return rodas5p_mixed_blocks(prec);
+    case ENS_ALG_ROS23: return ros23_mixed_blocks(prec);
+  }
+  return 1;
+}
 
 __global__ void zero_counter(unsigned long long* q) {
   if (threadIdx.x == 0) *q = 0ull;
@@ -504,6 +533,80 @@ int ens_solve(ens_ctx* c, int sys, int64_t n, const void* params, const void* u0
   if (!g.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
   ens::LaunchArgs a = make_args(c, n, params, u0, tspan, atol, rtol, theta, n_save, out);
   return launch(c, sys, alg, a, current_cfg(c), static_cast<hipStream_t>(stream));
+}
+
+int ens_solve_mixed(ens_ctx* c, int n_groups, const ens_group* groups, int alg, double atol,
+                    double rtol, const double* theta, int n_save, void* stream) {
+  if (!c) return ENS_EINVAL;
+  c->err.clear();
+  if (n_groups < 1 || n_groups > ens::kMaxGroups || !groups)
+    return fail(c, ENS_EINVAL, "n_groups %d out of range [1, %d] (or null groups)", n_groups,
+                ens::kMaxGroups);
+  if (alg != ENS_ALG_TSIT5 && alg != ENS_ALG_RODAS4 && alg != ENS_ALG_RODAS5P &&
+      alg != ENS_ALG_ROS23)
+    return fail(c, ENS_EUNSUPPORTED, "mixed solves take an adaptive algorithm, not %d", alg);
+  ens::MixedArgs m;
+  std::memset(&m, 0, sizeof m);
+  int64_t chunks = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    const ens_group& G = groups[g];
+    const int sys = G.system_id;
+    const bool ok_sys = alg == ENS_ALG_TSIT5
+                            ? (sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR)
+                            : (sys == ENS_SYS_ROBERTSON || sys == ENS_SYS_OREGO ||
+                               sys == ENS_SYS_LORENZ || sys == ENS_SYS_LINEAR);
+    if (!ok_sys)
+      return fail(c, ENS_EUNSUPPORTED, "group %d: system %d is not in the mixed set of alg %d",
+                  g, sys, alg);
+    int rc = check_problem(c, sys, G.n_traj, G.params, G.u0, G.tspan, alg, atol, rtol, theta,
+                           n_save, G.out);
+    if (rc != ENS_OK) {
+      const std::string msg = c->err;
+      return fail(c, rc, "group %d: %s", g, msg.c_str());
+    }
+    if (G.tspan_broadcast != 0 && G.tspan_broadcast != 1)
+      return fail(c, ENS_EINVAL, "group %d: tspan_broadcast must be 0 or 1", g);
+    ens::GroupArgs& A = m.g[g];
+    A.sys = sys;
+    A.tspan_bcast = G.tspan_broadcast;
+    A.n = G.n_traj;
+    A.params = G.params;
+    A.u0 = G.u0;
+    A.tspan = G.tspan;
+    A.out = G.out;
+    A.status = G.status;
+    A.stats = G.stats;
+    A.chunks = (G.n_traj + ens::kMixedChunk - 1) / ens::kMixedChunk;
+    chunks += A.chunks;
+  }
+  m.n_groups = n_groups;
+  m.n_chunks = chunks;
+  // queue order: the groups with fewer chunks first (a stable sort), so a
+  // small group of long trajectories starts beside the large group instead
+  // of forming the launch's tail (measured: interleaving the groups through
+  // the queue instead is slower)
+  std::stable_sort(m.g, m.g + n_groups, [](const ens::GroupArgs& x, const ens::GroupArgs& y) {
+    return x.chunks < y.chunks;
+  });
+  for (int g = 0; g < n_groups; ++g) {
+    m.g[g].chunk0 = g == 0 ? 0 : m.g[g - 1].chunk0 + m.g[g - 1].chunks;
+  }
+  if (chunks == 0) return ENS_OK;
+  DeviceGuard dg(c->device);
+  if (!dg.ok) return fail(c, ENS_EDEVICE, "cannot make device %d current", c->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  m.c = make_args(c, 0, nullptr, nullptr, nullptr, atol, rtol, theta, n_save, nullptr);
+  // ENS_OPT_FORM 3: the persistent queue on a resident grid; otherwise one
+  // block per chunk (grid 0 below), which measured faster
+  const int grid = c->form != 3 ? 0
+                   : c->grid > 0 ? c->grid
+                                 : ens::mixed_blocks_per_cu(alg, c->precision) * c->num_cu;
+  if (grid == 0 && chunks > (int64_t)0xFFFFFFFF / ens::kMixedChunk)
+    return fail(c, ENS_EINVAL, "too many chunks for one block each: %lld", (long long)chunks);
+  hipError_t e = ens::reset_queue(c->queue, s);
+  if (e == hipSuccess) e = ens::launch_mixed(alg, c->precision, grid, m, s);
+  if (e != hipSuccess) return fail(c, ENS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return ENS_OK;
 }
 
 int ens_philox_fill(ens_ctx* c, uint64_t seed, int64_t n, uint32_t step, uint32_t* out,

@@ -281,6 +281,35 @@ __device__ inline void run_sorted(const LaunchArgs& a) {
 // a wave's lanes finish together.  The block then claims the next chunk:
 // blocks that drew cheap chunks take more of them.  Each item runs the same
 // lane code as in the other forms, so results are bit-identical.
+// One chunk of B items starting at work item `base`: every thread
+// initialises one item for its key, the block sorts, wave w integrates sorted
+// group w.  Ends with a barrier, so keys may be reused at once.
+template <class Lane, int B>
+__device__ inline void sorted_chunk(const LaunchArgs& a, int64_t base, int64_t n, int tid,
+                                    uint64_t* keys) {
+  float key = __builtin_inff();  // items past the end sort last
+  if (base + tid < n) {
+    typename Lane::Input in;
+    in.load(a, base + tid);
+    Lane L;
+    L.init(a, base + tid, in);
+    key = work_key(L);
+  }
+  keys[tid] = ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)tid;
+  __syncthreads();
+  block_sort<B, B>(keys, tid);
+  const int64_t k = base + (int)(uint32_t)keys[tid];
+  if (k < n) {
+    typename Lane::Input in;
+    in.load(a, k);
+    Lane L;
+    L.init(a, k, in);
+    while (!L.done) L.attempt(a, k);
+    L.finish(a, k);
+  }
+  __syncthreads();  // keys (and the claimed chunk) are reused by the next chunk
+}
+
 template <class Lane, int B>
 __device__ inline void run_chunked(const LaunchArgs& a) {
   __shared__ uint64_t keys[B];
@@ -294,27 +323,59 @@ __device__ inline void run_chunked(const LaunchArgs& a) {
     const int64_t base =
         (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)chunk) * (int64_t)B;
     if (base >= n) break;  // the same for the whole block
-    float key = __builtin_inff();  // items past the end sort last
-    if (base + tid < n) {
-      typename Lane::Input in;
-      in.load(a, base + tid);
-      Lane L;
-      L.init(a, base + tid, in);
-      key = work_key(L);
+    sorted_chunk<Lane, B>(a, base, n, tid, keys);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed systems: one persistent launch over several groups of trajectories,
+// each group an ensemble of its own system in its own arrays.  Every group is
+// cut into chunks of B trajectories (a group's last chunk may be short, so no
+// chunk holds two systems and no wave mixes them); the chunks of all groups
+// form one work queue, drained by a persistent grid through an atomic
+// counter as in form 3, or handed out one chunk per block of a grid of
+// chunk-count blocks.  A block that finishes a chunk of one system takes the
+// next chunk whatever its system, so the groups' uneven work is balanced
+// across the whole GPU in a single launch instead of running one launch's
+// tail after the other's.  Queue position c belongs to the group g with
+// chunk0[g] <= c < chunk0[g + 1] (the host orders the groups).
+// `body(sys, a, base, n, tid, keys)` runs one chunk of system `sys` with the
+// launch arguments of its group.
+// Persistent = false: block b takes queue position b.
+template <int B, bool Persistent, class Body>
+__device__ inline void run_mixed(const MixedArgs& m, Body&& body) {
+  __shared__ uint64_t keys[B];
+  __shared__ unsigned int chunk;
+  stage_theta(m.c);
+  const int tid = (int)threadIdx.x;
+  while (true) {
+    int64_t c;
+    if constexpr (Persistent) {
+      if (tid == 0) chunk = (unsigned int)atomicAdd(m.c.queue, 1ull);
+      __syncthreads();
+      c = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)chunk);
+    } else {
+      c = (int64_t)blockIdx.x;
     }
-    keys[tid] = ((uint64_t)__float_as_uint(key) << 32) | (uint32_t)tid;
-    __syncthreads();
-    block_sort<B, B>(keys, tid);
-    const int64_t k = base + (int)(uint32_t)keys[tid];
-    if (k < n) {
-      typename Lane::Input in;
-      in.load(a, k);
-      Lane L;
-      L.init(a, k, in);
-      while (!L.done) L.attempt(a, k);
-      L.finish(a, k);
-    }
-    __syncthreads();  // keys and chunk are reused by the next chunk
+    if (c >= m.n_chunks) break;  // the same for the whole block
+    int g = 0;
+    for (int h = 1; h < m.n_groups; ++h)
+      if (c >= m.g[h].chunk0) g = h;
+    const int64_t j = c - m.g[g].chunk0;
+    const GroupArgs& G = m.g[g];
+    LaunchArgs a = m.c;
+    a.n = G.n;
+    a.in_stride = G.n;
+    a.out_stride = G.n;
+    a.params = G.params;
+    a.u0 = G.u0;
+    a.tspan = G.tspan;
+    a.tspan_bcast = G.tspan_bcast;
+    a.out = G.out;
+    a.status = G.status;
+    a.stats = G.stats;
+    body(G.sys, a, j * B, G.n, tid, keys);
+    if constexpr (!Persistent) break;
   }
 }
 

@@ -44,6 +44,33 @@ struct LaunchArgs {
   double theta[kMaxSave];
 };
 
+// One group of a mixed-system launch (ens_solve_mixed): its own system and
+// arrays, and the index of its first chunk in the launch's work queue.
+struct GroupArgs {
+  int sys;
+  int tspan_bcast;
+  int64_t n;
+  const void* params;
+  const void* u0;
+  const double* tspan;
+  void* out;
+  uint8_t* status;
+  int32_t* stats;
+  int64_t chunks;  // ceil(n / kMixedChunk)
+  int64_t chunk0;  // queue position of its first chunk
+};
+constexpr int kMaxGroups = 8;
+constexpr int64_t kMixedChunk = 256;  // trajectories per chunk (the block size)
+
+// A mixed-system launch: the shared settings in `c` (queue, tolerances,
+// save times, ...), the groups, and the total number of chunks.
+struct MixedArgs {
+  LaunchArgs c;
+  GroupArgs g[kMaxGroups];
+  int n_groups;
+  int64_t n_chunks;  // sum of the groups' chunks
+};
+
 struct LaunchCfg {
   int form;   // 0 plain, 1 persistent, 2 cost-sorted, 3 persistent cost-sorted chunks
   int block;  // threads per block
@@ -64,6 +91,11 @@ hipError_t launch_em(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
 
 hipError_t launch_siea(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
                        hipStream_t s);
+
+// Mixed-system persistent launch of `alg` in blocks of 256 (grid 0: fill
+// every CU); blocks_per_cu gives the resident blocks of that kernel.
+hipError_t launch_mixed(int alg, int prec, int grid, const MixedArgs& m, hipStream_t s);
+int mixed_blocks_per_cu(int alg, int prec);
 
 hipError_t launch_philox_fill(uint64_t seed, int64_t n, uint32_t step, uint32_t* out,
                               hipStream_t s);

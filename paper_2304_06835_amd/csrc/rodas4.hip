@@ -62,6 +62,14 @@ hipError_t launch_rodas4(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, 
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_rodas4_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  return ros_launch_mixed<Rodas4, Robertson, Orego, Lorenz, Linear>(prec, grid, m, s);
+}
+
+int rodas4_mixed_blocks(int prec) {
+  return ros_mixed_blocks<Rodas4, Robertson, Orego, Lorenz, Linear>(prec);
+}
+
 int rodas4_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   switch (sys) {
     case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Rodas4>(prec, block, form, tpl);

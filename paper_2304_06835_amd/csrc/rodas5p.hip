@@ -67,6 +67,14 @@ hipError_t launch_rodas5p(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a,
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_rodas5p_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  return ros_launch_mixed<Rodas5P, Robertson, Orego, Lorenz, Linear>(prec, grid, m, s);
+}
+
+int rodas5p_mixed_blocks(int prec) {
+  return ros_mixed_blocks<Rodas5P, Robertson, Orego, Lorenz, Linear>(prec);
+}
+
 int rodas5p_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   switch (sys) {
     case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Rodas5P>(prec, block, form, tpl);

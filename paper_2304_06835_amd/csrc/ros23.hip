@@ -83,6 +83,14 @@ hipError_t launch_ros23(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, h
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_ros23_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  return ros_launch_mixed<Ros23, Robertson, Orego, Lorenz, Linear>(prec, grid, m, s);
+}
+
+int ros23_mixed_blocks(int prec) {
+  return ros_mixed_blocks<Ros23, Robertson, Orego, Lorenz, Linear>(prec);
+}
+
 int ros23_blocks_per_cu(int sys, int prec, int block, int form, int tpl) {
   switch (sys) {
     case ENS_SYS_ROBERTSON: return ros_occ_prec<Robertson, Ros23>(prec, block, form, tpl);

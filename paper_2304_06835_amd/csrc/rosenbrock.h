@@ -461,6 +461,61 @@ int ros_occupancy_typed(int block, int form, int tpl) {
   return nb > 0 ? nb : 1;
 }
 
+// Mixed-system launch (ens_solve_mixed) for a method M over the systems
+// whose lanes hold a whole trajectory in three components -- Robertson,
+// OREGO, Lorenz, Linear: one kernel holds all four lane types, so its
+// registers are the largest of theirs (the eight-component HIRES and the
+// grouped POLLU would take them for everyone and are left out).
+constexpr int kMixedBlock = 256;
+
+template <class R, class M, class S>
+__device__ inline bool mixed_chunk(int sys, int id, const LaunchArgs& a, int64_t base, int64_t n,
+                                   int tid, uint64_t* keys) {
+  if (sys != id) return false;
+  sorted_chunk<RosLane<R, S, M>, kMixedBlock>(a, base, n, tid, keys);
+  return true;
+}
+
+template <class R, class M, bool P, class S0, class S1, class S2, class S3>
+__global__ void __launch_bounds__(kMixedBlock) ros_mixed(const MixedArgs m) {
+  run_mixed<kMixedBlock, P>(m, [&](int sys, const LaunchArgs& a, int64_t base, int64_t n, int tid,
+                                   uint64_t* keys) {
+    mixed_chunk<R, M, S0>(sys, S0::kId, a, base, n, tid, keys) ||
+        mixed_chunk<R, M, S1>(sys, S1::kId, a, base, n, tid, keys) ||
+        mixed_chunk<R, M, S2>(sys, S2::kId, a, base, n, tid, keys) ||
+        mixed_chunk<R, M, S3>(sys, S3::kId, a, base, n, tid, keys);
+  });
+}
+
+// grid 0: one block per chunk, no queue; otherwise a persistent grid.
+template <class M, class S0, class S1, class S2, class S3>
+hipError_t ros_launch_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  const dim3 g((unsigned)(grid > 0 ? grid : m.n_chunks)), b(kMixedBlock);
+  if (prec == 64) {
+    if (grid > 0)
+      hipLaunchKernelGGL((ros_mixed<double, M, true, S0, S1, S2, S3>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((ros_mixed<double, M, false, S0, S1, S2, S3>), g, b, 0, s, m);
+  } else {
+    if (grid > 0)
+      hipLaunchKernelGGL((ros_mixed<float, M, true, S0, S1, S2, S3>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((ros_mixed<float, M, false, S0, S1, S2, S3>), g, b, 0, s, m);
+  }
+  return hipGetLastError();
+}
+
+template <class M, class S0, class S1, class S2, class S3>
+int ros_mixed_blocks(int prec) {
+  int nb = 0;
+  const hipError_t e =
+      prec == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &nb, ros_mixed<double, M, true, S0, S1, S2, S3>, kMixedBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                       &nb, ros_mixed<float, M, true, S0, S1, S2, S3>, kMixedBlock, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
 template <class S, class M>
 hipError_t ros_launch_prec(int prec, const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   return prec == 64 ? ros_launch_typed<double, S, M>(cfg, a, s)

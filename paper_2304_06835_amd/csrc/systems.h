@@ -12,12 +12,14 @@
 // configuration performs bit-identical operations.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "../../include/ens.h"
 #include "driver.h"  // Num<R>
 
 namespace ens {
 
 // du = A u, A row-major in p[0..8].
 struct Linear {
+  static constexpr int kId = ENS_SYS_LINEAR;
   static constexpr int N = 3, M = 9;
   template <class R>
   __device__ static inline void f(const R* p, const R* u, R* du) {
@@ -35,6 +37,7 @@ struct Linear {
 
 // Lorenz: (sigma (y - x), x (rho - z) - y, x y - beta z), p = (sigma, rho, beta).
 struct Lorenz {
+  static constexpr int kId = ENS_SYS_LORENZ;
   static constexpr int N = 3, M = 3;
   template <class R>
   __device__ static inline void f(const R* p, const R* u, R* du) {
@@ -56,6 +59,7 @@ struct Lorenz {
 // Robertson kinetics, p = (k1, k2, k3):
 // (-k1 y1 + k3 y2 y3, k1 y1 - k3 y2 y3 - k2 y2^2, k2 y2^2).
 struct Robertson {
+  static constexpr int kId = ENS_SYS_ROBERTSON;
   static constexpr int N = 3, M = 3;
   template <class R>
   __device__ static inline void f(const R* p, const R* u, R* du) {
@@ -82,6 +86,7 @@ struct Robertson {
 // y0 blow up): (k1 (y2 + y1 (1 - k2 y1 - y2)), (y3 - (1 + y1) y2) / k1,
 // k3 (y1 - y3)).
 struct Orego {
+  static constexpr int kId = ENS_SYS_OREGO;
   static constexpr int N = 3, M = 3;
   template <class R>
   __device__ static inline void f(const R* p, const R* u, R* du) {
@@ -108,6 +113,7 @@ struct Orego {
 // (1.71, 0.43, 8.32, 0.0007, 8.75, 10.03, 0.035, 1.12, 1.745, 280, 0.69,
 // 1.81), each standing for every occurrence of its value.
 struct Hires {
+  static constexpr int kId = ENS_SYS_HIRES;
   static constexpr int N = 8, M = 12;
   template <class R>
   __device__ static inline void f(const R* k, const R* y, R* d) {

@@ -392,7 +392,48 @@ int occupancy_typed(int block, int form, int tpl) {
   return nb > 0 ? nb : 1;
 }
 
+// Mixed-system launch (ens_solve_mixed) over the Tsit5 systems.
+constexpr int kMixedBlock = 256;
+
+template <class R, bool P>
+__global__ void __launch_bounds__(kMixedBlock) tsit5_mixed(const MixedArgs m) {
+  run_mixed<kMixedBlock, P>(m, [&](int sys, const LaunchArgs& a, int64_t base, int64_t n, int tid,
+                                   uint64_t* keys) {
+    if (sys == Lorenz::kId)
+      sorted_chunk<Tsit5Lane<R, Lorenz>, kMixedBlock>(a, base, n, tid, keys);
+    else
+      sorted_chunk<Tsit5Lane<R, Linear>, kMixedBlock>(a, base, n, tid, keys);
+  });
+}
+
 }  // namespace
+
+// grid 0: one block per chunk, no queue; otherwise a persistent grid.
+hipError_t launch_tsit5_mixed(int prec, int grid, const MixedArgs& m, hipStream_t s) {
+  const dim3 g((unsigned)(grid > 0 ? grid : m.n_chunks)), b(kMixedBlock);
+  if (prec == 64) {
+    if (grid > 0)
+      hipLaunchKernelGGL((tsit5_mixed<double, true>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((tsit5_mixed<double, false>), g, b, 0, s, m);
+  } else {
+    if (grid > 0)
+      hipLaunchKernelGGL((tsit5_mixed<float, true>), g, b, 0, s, m);
+    else
+      hipLaunchKernelGGL((tsit5_mixed<float, false>), g, b, 0, s, m);
+  }
+  return hipGetLastError();
+}
+
+int tsit5_mixed_blocks(int prec) {
+  int nb = 0;
+  const hipError_t e =
+      prec == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_mixed<double, true>,
+                                                                kMixedBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tsit5_mixed<float, true>,
+                                                                kMixedBlock, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
 
 hipError_t launch_tsit5(int sys, int prec, const LaunchCfg& cfg, LaunchArgs a, hipStream_t s) {
   if (sys == ENS_SYS_LORENZ)
