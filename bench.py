@@ -1,7 +1,7 @@
 """Benchmark: trajectories/s of one ensemble solve on one MI355X.
 
 Default workload (the headline): 2^24 Lorenz trajectories, rho ~ U[0,28],
-u0 = (1,0,0) + N(0, 0.01^2), FP32 state with compensated float-pair time, adaptive
+u0 = (1,0,0) + N(0, 0.01^2), FP32 state with FP64 compensated time, adaptive
 Tsit5 at reltol = abstol = 1e-6, 16 evenly spaced saves on t in [0, 1].
 One "step" = one ens_solve over the whole ensemble (inputs resident in HBM).
 
@@ -155,7 +155,7 @@ def make_workload(name, n, alg=""):
 
 def describe(e):
     if e.name == "lorenz_fp32":
-        return ("Lorenz 2^24-ensemble, rho~U[0,28], u0=(1,0,0)+N(0,0.01^2), FP32 state + float-pair "
+        return ("Lorenz 2^24-ensemble, rho~U[0,28], u0=(1,0,0)+N(0,0.01^2), FP32 state + FP64 "
                 "compensated time, Tsit5 rtol=atol=1e-6, 16 saves on [0,1]")
     if e.name == "lorenz_fp64":
         return "Lorenz 8192-ensemble, rho~U[0,21], FP64, Tsit5 rtol=atol=1e-8, final state"

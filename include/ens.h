@@ -109,10 +109,9 @@ typedef struct ens_ctx ens_ctx;
                             vectors, FSAL                    sec. 3.2.1, 5.2.1 */
 
 /* ---- scalar options (ens_set_option) ------------------------------------ */
-#define ENS_OPT_PRECISION 1 /* 32 (default): FP32 state, compensated time
-                               (a TwoSum float pair for TSIT5, an FP64 pair
-                               with FP64 W/LU/solves for RODAS4, RODAS5P and
-                               ROS23);
+#define ENS_OPT_PRECISION 1 /* 32 (default): FP32 state, FP64 time with a
+                               TwoSum compensation term (and FP64 W/LU/solves
+                               for RODAS4, RODAS5P and ROS23);
                                64: FP64 throughout.  Also the dtype of params,
                                u0 and out.                                      */
 #define ENS_OPT_FORM 2      /* 0 (default): one lane per trajectory;

@@ -57,55 +57,9 @@ struct CompTime {
   }
   // distance from the current time to `target`
   __device__ inline double to(double target) const { return (target - hi) - lo; }
-  // targets are plain doubles
-  using Mark = double;
-  __device__ static inline double mark(double v) { return v; }
   __device__ inline double value() const { return hi + lo; }
   // the current time has reached save time v
   __device__ inline bool reached(double v) const { return v <= hi + lo; }
-};
-
-// The same compensated time for FP32 lanes without FP64 instructions on the
-// step path: an unevaluated pair hi + lo of floats (about 48 significant
-// bits), advanced with TwoSum in FP32.  Targets (save and landing times) are
-// split into float pairs once, when they are set.
-struct PairTime {
-  float hi, lo;
-  struct Mark {
-    float hi, lo;
-  };
-  __device__ static inline Mark mark(double v) {
-    const float h = (float)v;
-    return {h, (float)(v - (double)h)};
-  }
-  __device__ inline void set(double v) {
-    const Mark m = mark(v);
-    hi = m.hi;
-    lo = m.lo;
-  }
-  __device__ inline void add(float h) {
-    const float s = hi + h;
-    const float bp = s - hi;
-    const float err = (hi - (s - bp)) + (h - bp);
-    hi = s;
-    lo += err;
-  }
-  // distance to `m`, to FP32 accuracy (exact near the target: Sterbenz)
-  __device__ inline float to(const Mark& m) const { return (m.hi - hi) + (m.lo - lo); }
-  __device__ inline double value() const { return (double)hi + (double)lo; }
-  // The current time has reached save time v, compared in the pair form that
-  // a step landing on v sets (set(v) == mark(v)): hi + lo of a split v can
-  // fall below v itself, so a plain `v <= value()` would miss the landing.
-  __device__ inline bool reached(double v) const { return to(mark(v)) <= 0.0f; }
-};
-
-template <class R>
-struct TimeOf {
-  using type = CompTime;
-};
-template <>
-struct TimeOf<float> {
-  using type = PairTime;
 };
 
 // Number of work items of a launch: `n`, or the device-side count when the

@@ -198,9 +198,9 @@ struct RosLane {
   using Input = typename V::template Input<R>;
   R p[NP], u[N];
   R f0[M::kFsal ? N : 1];  // f(u), carried from step to step by FSAL methods
-  // FP64 pair in both precisions: these lanes are FP64-heavy already, and the
-  // float pair of the FP32 Tsit5 lanes measured no faster for Rodas4 and 12%
-  // slower for Rosenbrock23's 512-thread sorted form
+  // FP64 time with a compensation term in both precisions (a TwoSum pair of
+  // floats measured no faster for Rodas4 and 12% slower for Rosenbrock23's
+  // 512-thread sorted form)
   using Time = CompTime;
   Time t;
   double t0, tf;

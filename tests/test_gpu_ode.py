@@ -134,9 +134,10 @@ def test_sorted_staged_saves_bitwise_equal(ens, precision, n_save):
 
 @pytest.mark.parametrize("mode", [0, 1])
 def test_fp32_landing_on_non_dyadic_times(ens, orc, mode):
-    """FP32 lanes keep time as a pair of floats.  Spans and save times that
-    no float pair holds exactly (per-trajectory t0 in [-0.7, 0.7], tf - t0 in
-    [0.31, 0.97], save fractions j/7) must still be landed on and written:
+    """FP32 lanes keep time in FP64 with a compensation term.  Spans and save
+    times that no binary fraction holds exactly (per-trajectory t0 in
+    [-0.7, 0.7], tf - t0 in [0.31, 0.97], save fractions j/7) must still be
+    landed on and written:
     every status 0, the oracle's accuracy and step counts, and the same bits
     in the plain and sorted forms."""
     e = W.lorenz_fp32(N=2051, seed=32)
