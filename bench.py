@@ -64,6 +64,9 @@ FLOPS = {("tsit5", "lorenz"): 260, ("rodas4", "robertson"): 427, ("rodas5p", "ro
 # n = 3: 3 x 15 -> 81.
 DENSE_FLOPS_PER_SAVE = 81
 MLP_FLOPS_PER_QUERY = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 48)  # 288,768
+# one training sample: the forward pass, the weight gradients (the same
+# products) and the input gradients of every layer but the first
+MLP_TRAIN_FLOPS_PER_SAMPLE = 2 * MLP_FLOPS_PER_QUERY + 2 * (256 * 256 + 256 * 256 + 256 * 48)
 
 # MI355X published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s, FP64
 # 78.6 TFLOP/s; dense bf16 MFMA 2.5 PFLOP/s.  The FP32 figure is reached by
@@ -110,6 +113,9 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--surrogate-epochs", type=int, default=160)
+    ap.add_argument("--surrogate-only", action="store_true",
+                    help="only train the surrogate for --surrogate-epochs epochs on 2^20 solver "
+                         "trajectories and run its inference on 2^24 queries (for profiling)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU-baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -280,6 +286,80 @@ def recorded_traffic(name, form, launches_units):
     return r.get("hbm_bytes_per_launch")
 
 
+# Vector-ALU instruction classes of the rocprofv3 SQ_INSTS_VALU_* counters and
+# the issue-rate probe kind (paper_2304_06835_amd/probe/valu_probe.hip) each
+# class is priced at; VALU instructions in no counted class (moves, compares,
+# selects, logic, lane permutes) are priced as 32-bit logic.
+PROBE_KINDS = {"fma_f32": 0, "add_f32": 1, "mul_f32": 2, "fma_f64": 3, "exp_f32": 4,
+               "mad_u64_u32": 5, "xor_b32": 6, "fma_f32_literal": 7, "fma_f32_sgpr": 8}
+VALU_CLASS_PROBE = {"FMA_F32": "fma_f32", "MUL_F32": "mul_f32", "ADD_F32": "add_f32",
+                    "TRANS_F32": "exp_f32", "F64": "fma_f64", "INT64": "mad_u64_u32",
+                    "INT32": "xor_b32", "CVT": "xor_b32", "OTHER": "xor_b32"}
+
+
+def issue_rates(device=0, iters=16384):
+    """Lane-operations per second of each probe kind, measured now on this GPU
+    (register-only dependency chains, 16 per lane, 2048 x 256 lanes)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2304_06835_amd", "libvaluprobe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2304_06835_amd.build`")
+    L = ctypes.CDLL(path)
+    L.valu_probe_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for name, kind in PROBE_KINDS.items():
+        r = ctypes.c_double(0.0)
+        rc = L.valu_probe_rate(device, kind, iters, ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"valu_probe_rate({name}) failed with {rc}")
+        out[name] = r.value
+    return out
+
+
+def recorded_valu_mix(key):
+    """Wave-level VALU instruction counts per launch by class, from a committed
+    rocprofv3 record (profiles/valu_mix.json) taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", "valu_mix.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    r = rec.get(key)
+    if not r or r.get("source_hash") != kernel_source_hash(r.get("sources")):
+        return None
+    return r
+
+
+_RATES = {}
+
+
+def probed_rates():
+    """issue_rates() once per process."""
+    if "r" not in _RATES:
+        _RATES["r"] = issue_rates()
+    return _RATES["r"]
+
+
+def issue_roofline(mix, rates, kernel_ms):
+    """The launch's VALU instruction stream against the issue ceiling: the
+    time the counted instructions need at the probed per-class rates (each
+    wave instruction is 64 lane-operations) over the measured kernel time."""
+    if mix is None or rates is None:
+        return None
+    classes = mix["per_launch"]
+    need_s = sum(classes[c] * 64.0 / rates[VALU_CLASS_PROBE[c]] for c in classes)
+    simd_clocks = 1024 * 2.4e9 * kernel_ms * 1e-3  # 256 CUs x 4 SIMDs at the rated clock
+    total = sum(classes.values())
+    return {"valu_wave_instr_per_launch": total,
+            "achieved_wave_instr_per_simd_clock": total / simd_clocks,
+            "ceiling_wave_instr_per_simd_clock": total / (1024 * 2.4e9 * need_s),
+            "frac": need_s / (kernel_ms * 1e-3),
+            "lanes_active_per_instr": mix.get("lanes_active_per_instr"),
+            "class_mix": {c: classes[c] / total for c in classes},
+            "probe_lane_ops_per_simd_clock": {k: v / (1024 * 2.4e9) for k, v in rates.items()}}
+
+
 def output_checks(e, out):
     """Checks on the whole GPU output that need no oracle: Robertson's
     conserved sum y1 + y2 + y3 = 1 (every Rosenbrock step preserves it up to
@@ -303,6 +383,31 @@ def output_checks(e, out):
         return {"em_mean_z_score": zs,
                 "em_second_moment_rel_dev": float(zv.sum() / (z.shape[0] * var.sum()))}
     return {}
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo) and the cores it offers."""
+    import os
+    import subprocess
+    name = None
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            if line.startswith("Model name:"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if name is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return {"model": name, "logical_cpus": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(e, gpu_out, seconds):
@@ -355,7 +460,8 @@ def cpu_baseline(e, gpu_out, seconds):
     dt = time.perf_counter() - t0
     res = {"value": len(idx) / dt, "unit": "trajectories/s", "cores": nth, "kind": "oracle",
            "sample": f"{len(idx)} of {e.n} trajectories (every {e.n // len(idx)}-th), "
-                     f"FP64 C oracle, OpenMP over trajectories, {dt:.1f} s"}
+                     f"FP64 C oracle, OpenMP over trajectories, {dt:.1f} s",
+           "cpu_model": cpu_model()}
     idx = W.sample_indices(e.n, 4096)
     g = gpu_out[:, :, idx].astype(np.float64)
     if e.alg in ("em", "siea"):
@@ -533,6 +639,9 @@ def config_variant(name, precision, steps, alg=""):
     fl = FLOPS[(e.alg, e.system)] * attempts / (ms * 1e-3) / 1e12
     res = {"workload": describe(e), "kernel_ms": ms, "traj_per_s": e.n / (ms * 1e-3),
            "achieved_tflops": fl, "frac_of_peak": fl / PEAK[precision]}
+    mix = recorded_valu_mix(f"{e.name}/{e.alg}/plain")
+    if mix is not None:
+        res["issue"] = issue_roofline(mix, probed_rates(), ms)
     if e.alg in ("em", "siea"):
         sid = {"gbm4": oracle.GBM4, "crn": oracle.CRN}[e.system]
         oalg = oracle.EM if e.alg == "em" else oracle.SIEA
@@ -585,6 +694,7 @@ def surrogate_variant(epochs, plain_ms_2p24):
                      seed=11)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    scaling = train_batch_scaling(s, P, U, y)
     del P, U, T, y
     q = W.lorenz_fp32(seed=W.SEEDS["surr_query"])
     Pq, Uq, Tq = dev(q.params), dev(q.u0), dev(q.tspan)
@@ -593,9 +703,13 @@ def surrogate_variant(epochs, plain_ms_2p24):
     rep = torch.zeros(4, dtype=torch.float32, device="cuda")
     _, pred_ms, _ = event_time(lambda: m.predict(Pq, Uq, out=out), 5, 2)
     mfma = MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12
+    train_tf = MLP_TRAIN_FLOPS_PER_SAMPLE * (1 << 20) * epochs / train_s / 1e12
     res = {
         "training": {"samples": 1 << 20, "epochs": epochs, "batch": 4096, "seconds": train_s,
-                     "final_loss": float(losses[-1].item())},
+                     "final_loss": float(losses[-1].item()),
+                     "mfma": {"achieved": train_tf, "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
+                              "frac": train_tf / PEAK_BF16_MFMA},
+                     "batch_scaling": scaling},
         "predict_ms": pred_ms,
         "predict_mfma": {"achieved": mfma, "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
                          "frac": mfma / PEAK_BF16_MFMA},
@@ -627,10 +741,69 @@ def surrogate_variant(epochs, plain_ms_2p24):
     return res
 
 
+def surrogate_only(epochs):
+    """Training and inference of the surrogate alone, no audit: the workload
+    of the MFMA counter profiles."""
+    import torch
+
+    import paper_2304_06835_amd as ens
+    from paper_2304_06835_amd import workloads as W
+    s = ens.Solver(0, precision=32)
+    tr = W.lorenz_fp32(N=1 << 20, seed=W.SEEDS["surr_train"])
+    P, U, T = dev(tr.params), dev(tr.u0), dev(tr.tspan)
+    y = s.solve("lorenz", P, U, T, "tsit5", tr.abstol, tr.reltol, tr.theta)
+    m = ens.Surrogate(s, seed=1)
+    m.fit_norm(P, U, y.view(48, -1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m.train(P, U, y.view(48, -1), epochs=epochs, batch=4096, lr_max=3e-3, lr_min=3e-5, seed=11)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    q = W.lorenz_fp32(seed=W.SEEDS["surr_query"])
+    Pq, Uq = dev(q.params), dev(q.u0)
+    out = torch.empty((16, 3, q.n), dtype=torch.float32, device="cuda")
+    _, pred_ms, _ = event_time(lambda: m.predict(Pq, Uq, out=out), 5, 2)
+    train_tf = MLP_TRAIN_FLOPS_PER_SAMPLE * (1 << 20) * epochs / train_s / 1e12
+    print(json.dumps({"surrogate_only": {
+        "train_epochs": epochs, "train_samples": 1 << 20, "train_seconds": train_s,
+        "train_tflops": train_tf, "predict_ms": pred_ms, "queries": q.n,
+        "predict_tflops": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12,
+        "train_batch_scaling": train_batch_scaling(s, P, U, y)}}), flush=True)
+
+
+def train_batch_scaling(s, P, U, y, batches=(4096, 16384, 65536), epochs=2):
+    """Training throughput of a fresh model at several minibatch sizes (the
+    same kernels; per-step launch and latency costs amortised over more
+    samples): MFMA TFLOP/s over `epochs` epochs of the 2^20 training set."""
+    import torch
+
+    import paper_2304_06835_amd as ens
+    out = {}
+    for b in batches:
+        m = ens.Surrogate(s, seed=1)
+        m.fit_norm(P, U, y.view(48, -1))
+        m.train(P, U, y.view(48, -1), epochs=1, batch=b, seed=3)  # warm-up, workspace
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = m.train(P, U, y.view(48, -1), epochs=epochs, batch=b, lr_max=3e-3, lr_min=3e-5,
+                         seed=11)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        steps = ((1 << 20) // b) * epochs
+        tf = MLP_TRAIN_FLOPS_PER_SAMPLE * steps * b / dt / 1e12
+        out[str(b)] = {"step_us": dt / steps * 1e6, "tflops": tf, "frac": tf / PEAK_BF16_MFMA,
+                       "loss_after": float(losses[-1].item())}
+        del m
+    return out
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.surrogate_only:
+        surrogate_only(args.surrogate_epochs)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -684,6 +857,8 @@ def main():
             "kernel_ms_avg": ker_ms, "kernel_ms_min": ker_min,
             "flops_per_launch": flops, "attempted_steps": attempts, "flops_per_attempt": fpa,
             "dense_output_saves": dense_saves, "flops_per_dense_save": DENSE_FLOPS_PER_SAVE}
+    mix = recorded_valu_mix(f"{e.name}/{e.alg}/{form}" + ("/dense" if save == "dense" else ""))
+    roof["issue"] = issue_roofline(mix, probed_rates(), ker_ms) if mix is not None else None
     st = stats.cpu().numpy()
     steps_per = st.sum(axis=0)
     config = {"workload": describe(e), "name": e.name, "n_traj": e.n, "alg": e.alg,

@@ -22,6 +22,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libens.so")
+# The vector-ALU issue-rate probe the benchmark measures its ceiling with: a
+# shared object of its own, not part of the solver library.
+PROBE_SRC = os.path.join(PKG, "probe", "valu_probe.hip")
+PROBE_LIB = os.path.join(PKG, "libvaluprobe.so")
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -63,7 +67,20 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int = 8) 
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB} from {len(srcs)} sources")
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose: bool = False) -> str:
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, "-shared", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print(f"built {PROBE_LIB}")
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

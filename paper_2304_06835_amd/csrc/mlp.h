@@ -48,11 +48,19 @@ struct MlpActs {
   uint16_t* act[kMlpMaxLayers];
   float* g[2];          // gradient ping-pong, FP32
   uint16_t* gb[2];      // and bf16
-  float* split;         // kSplits x (largest weight matrix) split-K partials
 };
 
 // Split-K factor of the weight-gradient products (K = batch).
 constexpr int kSplits = 16;
+
+// Gradient partials of one training step, summed by the Adam kernel:
+// w[l] [kSplits][dims[l+1] * dims[l]] split-K partials of dW_l, b[l]
+// [tiles][dims[l+1]] partials of db_l over 64-row blocks of the batch.
+struct GradParts {
+  float* w[kMlpMaxLayers];
+  float* b[kMlpMaxLayers];
+  int tiles;
+};
 
 struct RowSet {
   const float* ptr[64];
@@ -60,8 +68,9 @@ struct RowSet {
 
 hipError_t mlp_init(float* w, uint16_t* wb, const MlpLayout& L, uint64_t seed, hipStream_t s);
 hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s);
-hipError_t mlp_adam(float* w, float* m, float* v, const float* g, uint16_t* wb, int64_t n,
-                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, const MlpLayout& L,
+                    const GradParts& parts, float lr, float b1, float b2, float eps, float c1,
+                    float c2, hipStream_t s);
 hipError_t mlp_gather(const float* params, const float* u0, const float* y, int64_t n, int64_t q0,
                       int64_t count, uint64_t mult, uint64_t add, const float* norm, uint16_t* a0,
                       float* T, int nout, hipStream_t s);
@@ -71,7 +80,7 @@ hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, c
                        const uint16_t* a0, int64_t count, MlpActs& acts, float* Y,
                        float* soa_out, int64_t soa_stride, int64_t q0, hipStream_t s);
 hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
-                        MlpActs& acts, const float* Y, const float* T, float* grad,
+                        MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                         double* partial, float* loss, hipStream_t s);
 
 // Fused inference kernel (mlp_fused.hip): weights re-laid out fragment-major

@@ -15,7 +15,10 @@
 // be stored K-contiguous or K-strided; the staging transposes), and each of
 // the four waves issues 2 x 2 v_mfma_f32_16x16x32_bf16 per K step.  Layer
 // epilogues (bias, SiLU, bf16 rounding, SiLU', de-normalisation into the
-// structure-of-arrays output) are fused into the tile's store.
+// structure-of-arrays output, the bias gradient's column sums) are fused into
+// the tile's store; the weight gradients' split-K partials and the bias
+// partials are summed inside the Adam kernel, so a training step is eleven
+// products and three small kernels (gather, loss, Adam).
 #include "../../include/ens.h"
 #include "ens_internal.h"
 #include "mlp.h"
@@ -41,47 +44,69 @@ __device__ inline float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-constexpr int BM = 64, BN = 64, BK = 32, LDW = BK + 8;  // LDS row: 40 bf16 = 80 B
+constexpr int BM = 64, BN = 64;
+constexpr int KB = 32, LDW = KB + 8;  // K per LDS round; LDS row: 40 bf16 = 80 B
+constexpr int kChunks = KB / 32;       // 8-element fragments per thread per operand per round
 
-// Stage rows [r0, r0+64) x K [k0, k0+32) of an operand into LDS as [row][k].
-// kRowK: element (r, k) at src[r * ld + k]; kKRow: at src[k * ld + r].
+// One round of an operand tile, rows [r0, r0+64) x K [k0, k0+KB), is 64 x KB
+// bf16 = kChunks fragments of 8 per thread.  Fragment c of thread tid:
+// kRowK (element (r, k) at src[r * ld + k]): row tid/4, k 8 (tid%4) + 32 c;
+// kKRow (element (r, k) at src[k * ld + r]): k tid/8 + 32 c, rows
+// 8 (tid%8) .. 8 (tid%8) + 7, so eight consecutive lanes read 128 contiguous
+// bytes of one k row.  The load is one 16-byte access where the fragment is
+// whole and aligned, element loads with zero fill at the edges.
 template <int LAY>
-__device__ inline void stage(uint16_t (*dst)[LDW], const uint16_t* __restrict__ src, int64_t ld,
-                             int64_t rows, int64_t K, int64_t r0, int64_t k0, int tid) {
-  uint16_t t[8];
+__device__ inline uint4 load_frag(const uint16_t* __restrict__ src, int64_t ld, int64_t rows,
+                                  int64_t K, int64_t r0, int64_t k0, int tid, int c) {
+  int64_t gr, gk;
+  const uint16_t* p;
+  bool whole;
   if (LAY == kRowK) {
-    const int r = tid >> 2, kk = (tid & 3) * 8;
-    const int64_t gr = r0 + r, gk = k0 + kk;
-    const uint16_t* p = src + gr * ld + gk;
-    if (gr < rows && gk + 8 <= K && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
-      *reinterpret_cast<uint4*>(&dst[r][kk]) = *reinterpret_cast<const uint4*>(p);
-      return;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) t[e] = (gr < rows && gk + e < K) ? p[e] : (uint16_t)0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) dst[r][kk + e] = t[e];
+    gr = r0 + (tid >> 2);
+    gk = k0 + (tid & 3) * 8 + 32 * c;
+    p = src + gr * ld + gk;
+    whole = gr < rows && gk + 8 <= K;
   } else {
-    const int kk = tid >> 3, r = (tid & 7) * 8;
-    const int64_t gk = k0 + kk, gr = r0 + r;
-    const uint16_t* p = src + gk * ld + gr;
-    if (gk < K && gr + 8 <= rows && ((reinterpret_cast<uintptr_t>(p) & 15) == 0)) {
-      const uint4 v = *reinterpret_cast<const uint4*>(p);
-      const uint16_t* q = reinterpret_cast<const uint16_t*>(&v);
+    gk = k0 + (tid >> 3) + 32 * c;
+    gr = r0 + (tid & 7) * 8;
+    p = src + gk * ld + gr;
+    whole = gk < K && gr + 8 <= rows;
+  }
+  if (whole && (reinterpret_cast<uintptr_t>(p) & 15) == 0) return *reinterpret_cast<const uint4*>(p);
+  uint16_t t[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) t[e] = q[e];
-    } else {
+  for (int e = 0; e < 8; ++e) {
+    const bool in = LAY == kRowK ? (gr < rows && gk + e < K) : (gk < K && gr + e < rows);
+    t[e] = in ? p[e] : (uint16_t)0;
+  }
+  uint4 v;
+  uint16_t* q = reinterpret_cast<uint16_t*>(&v);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) t[e] = (gk < K && gr + e < rows) ? p[e] : (uint16_t)0;
-    }
+  for (int e = 0; e < 8; ++e) q[e] = t[e];
+  return v;
+}
+
+// Fragment c of thread tid into the LDS tile dst[row][k] (row stride LDW).
+template <int LAY>
+__device__ inline void store_frag(uint16_t (*dst)[LDW], uint4 v, int tid, int c) {
+  if (LAY == kRowK) {
+    *reinterpret_cast<uint4*>(&dst[tid >> 2][(tid & 3) * 8 + 32 * c]) = v;
+  } else {
+    const uint16_t* q = reinterpret_cast<const uint16_t*>(&v);
+    const int kk = (tid >> 3) + 32 * c, r = (tid & 7) * 8;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dst[r + e][kk] = t[e];
+    for (int e = 0; e < 8; ++e) dst[r + e][kk] = q[e];
   }
 }
 
 // C[M x N] = A[M x K] B[K x N]; A stored per LA, B per LB (with "rows" = N).
 // blockIdx.z selects the K range [z kc, min(K, (z+1) kc)) of a split-K
 // product; the epilogue sees blockIdx.z and writes that split's partial.
+// K is consumed in rounds of KB through LDS; the next round's global loads
+// are issued before the current round's products, so they overlap them.  An epilogue with kColSums also
+// receives, per output column, the sum over the block's 64 rows of the
+// values it returned (fixed order: rows within a lane, then the four row
+// groups of a wave, then the two waves).
 template <int LA, int LB, class Epi>
 __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A, int64_t lda,
                                                  const uint16_t* __restrict__ B, int64_t ldb,
@@ -99,24 +124,48 @@ __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A,
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const int64_t kbeg = (int64_t)blockIdx.z * kc;
   const int64_t kend = kbeg + kc < K ? kbeg + kc : K;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-    stage<LA>(As, A, lda, M, kend, m0, k0, tid);
-    stage<LB>(Bs, B, ldb, N, kend, n0, k0, tid);
-    __syncthreads();
-    bf16x8_t af[2], bfr[2];
+  uint4 fa[kChunks], fb[kChunks];
+  if (kbeg < kend) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      af[t] = *reinterpret_cast<const bf16x8_t*>(&As[wm * 32 + t * 16 + (lane & 15)][(lane >> 4) * 8]);
-      bfr[t] = *reinterpret_cast<const bf16x8_t*>(&Bs[wn * 32 + t * 16 + (lane & 15)][(lane >> 4) * 8]);
+    for (int c = 0; c < kChunks; ++c) {
+      fa[c] = load_frag<LA>(A, lda, M, kend, m0, kbeg, tid, c);
+      fb[c] = load_frag<LB>(B, ldb, N, kend, n0, kbeg, tid, c);
+    }
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += KB) {
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      store_frag<LA>(As, fa[c], tid, c);
+      store_frag<LB>(Bs, fb[c], tid, c);
+    }
+    __syncthreads();
+    if (k0 + KB < kend) {
+#pragma unroll
+      for (int c = 0; c < kChunks; ++c) {
+        fa[c] = load_frag<LA>(A, lda, M, kend, m0, k0 + KB, tid, c);
+        fb[c] = load_frag<LB>(B, ldb, N, kend, n0, k0 + KB, tid, c);
+      }
     }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int ks = 0; ks < KB; ks += 32) {
+      bf16x8_t af[2], bfr[2];
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+      for (int t = 0; t < 2; ++t) {
+        af[t] = *reinterpret_cast<const bf16x8_t*>(
+            &As[wm * 32 + t * 16 + (lane & 15)][ks + (lane >> 4) * 8]);
+        bfr[t] = *reinterpret_cast<const bf16x8_t*>(
+            &Bs[wn * 32 + t * 16 + (lane & 15)][ks + (lane >> 4) * 8]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
     __syncthreads();
   }
   // lane holds D[4*(lane/16) + r][lane % 16] of each 16 x 16 tile
+  float cs[2] = {0.0f, 0.0f};
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -125,64 +174,99 @@ __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A,
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm * 32 + a * 16 + (lane >> 4) * 4 + r;
         const int64_t n = n0 + wn * 32 + b * 16 + (lane & 15);
-        if (m < M && n < N) epi(m, n, acc[a][b][r]);
+        if (m < M && n < N) cs[b] += epi(m, n, acc[a][b][r]);
       }
+  if constexpr (Epi::kColSums) {
+    __shared__ float red[2][BN];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      float v = cs[b];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) red[wm][wn * 32 + b * 16 + lane] = v;
+    }
+    __syncthreads();
+    if (tid < BN && n0 + tid < N) epi.colsum(blockIdx.y, n0 + tid, red[0][tid] + red[1][tid]);
+  }
 }
 
 // ---- epilogues -------------------------------------------------------------
+// operator() stores one output element and returns the value whose column
+// sums an epilogue with kColSums receives through colsum().
 struct EpiHidden {  // Z = acc + b (kept for the backward pass), A = bf16(silu(Z))
+  static constexpr bool kColSums = false;
   const float* bias;
   float* z;
   uint16_t* act;
   int64_t ld;
-  __device__ void operator()(int64_t m, int64_t n, float v) const {
+  __device__ float operator()(int64_t m, int64_t n, float v) const {
     const float zz = v + bias[n];
     if (z) z[m * ld + n] = zz;
     act[m * ld + n] = f2bf(silu(zz));
+    return 0.0f;
   }
+  __device__ void colsum(int64_t, int64_t, float) const {}
 };
 struct EpiLinear {  // Y = acc + b
+  static constexpr bool kColSums = false;
   const float* bias;
   float* y;
   int64_t ld;
-  __device__ void operator()(int64_t m, int64_t n, float v) const { y[m * ld + n] = v + bias[n]; }
+  __device__ float operator()(int64_t m, int64_t n, float v) const {
+    y[m * ld + n] = v + bias[n];
+    return 0.0f;
+  }
+  __device__ void colsum(int64_t, int64_t, float) const {}
 };
 struct EpiSoA {  // de-normalised output into out[n][q0 + m] (structure of arrays)
+  static constexpr bool kColSums = false;
   const float* bias;
   const float* mean;
   const float* stdv;
   float* out;
   int64_t stride, q0;
-  __device__ void operator()(int64_t m, int64_t n, float v) const {
+  __device__ float operator()(int64_t m, int64_t n, float v) const {
     out[n * stride + q0 + m] = fmaf(v + bias[n], stdv[n], mean[n]);
+    return 0.0f;
   }
+  __device__ void colsum(int64_t, int64_t, float) const {}
 };
-struct EpiBack {  // G = acc * silu'(Z), kept in FP32 (bias gradient) and bf16
+// G = acc * silu'(Z) in FP32 and bf16; the FP32 column sums of each 64-row
+// block are that block's partial of the layer's bias gradient, stored at
+// colpart[blockIdx.y][n].
+struct EpiBack {
+  static constexpr bool kColSums = true;
   const float* z;
   float* g;
   uint16_t* gb;
   int64_t ld;
-  __device__ void operator()(int64_t m, int64_t n, float v) const {
+  float* colpart;
+  __device__ float operator()(int64_t m, int64_t n, float v) const {
     const float gg = v * dsilu(z[m * ld + n]);
     g[m * ld + n] = gg;
     gb[m * ld + n] = f2bf(gg);
+    return gg;
   }
+  __device__ void colsum(int64_t by, int64_t n, float s) const { colpart[by * ld + n] = s; }
 };
 struct EpiStore {  // partial product of split blockIdx.z at c + z * zstride
+  static constexpr bool kColSums = false;
   float* c;
   int64_t ld, zstride;
-  __device__ void operator()(int64_t m, int64_t n, float v) const {
+  __device__ float operator()(int64_t m, int64_t n, float v) const {
     c[(int64_t)blockIdx.z * zstride + m * ld + n] = v;
+    return 0.0f;
   }
+  __device__ void colsum(int64_t, int64_t, float) const {}
 };
 
-// `splits` > 1: K is cut into that many ranges of a multiple of BK each.
+// `splits` > 1: K is cut into that many ranges of a multiple of 32 each.
 template <int LA, int LB, class Epi>
 hipError_t gemm(const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, int64_t M,
                 int64_t N, int64_t K, Epi epi, hipStream_t s, int splits = 1) {
   if (M <= 0 || N <= 0) return hipSuccess;
   int64_t kc = (K + splits - 1) / splits;
-  kc = (kc + BK - 1) / BK * BK;
+  kc = (kc + 31) / 32 * 32;
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM), (unsigned)splits);
   hipLaunchKernelGGL((gemm_bf16<LA, LB, Epi>), grid, dim3(256), 0, s, A, lda, B, ldb, M, N, K,
                      kc, epi);
@@ -215,12 +299,40 @@ __global__ void to_bf16(const float* w, uint16_t* wb, int64_t n) {
   if (p < n) wb[p] = f2bf(w[p]);
 }
 
-// Adam with bias correction c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t).
-__global__ void adam_step(float* w, float* m, float* v, const float* g, uint16_t* wb, int64_t n,
-                          float lr, float b1, float b2, float eps, float c1, float c2) {
+// Adam with bias correction c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t), on the
+// gradient summed here from the partials a backward pass left (fixed order:
+// split 0, 1, ... of a weight; row block 0, 1, ... of a bias); the sum is
+// also stored in g.
+__global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb, int64_t n,
+                          GradParts P, MlpLayout L, float lr, float b1, float b2, float eps,
+                          float c1, float c2) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const float gg = g[p];
+  float gg = 0.0f;
+  for (int l = 0; l < L.layers; ++l) {
+    const int64_t nw = (int64_t)L.dims[l] * L.dims[l + 1], nb = L.dims[l + 1];
+    if (p >= L.w_off[l] && p < L.w_off[l] + nw) {
+      const float* q = P.w[l] + (p - L.w_off[l]);
+      float t[kSplits];  // all loads in flight, then the fixed-order sum
+#pragma unroll
+      for (int z = 0; z < kSplits; ++z) t[z] = q[(int64_t)z * nw];
+      gg = t[0];
+#pragma unroll
+      for (int z = 1; z < kSplits; ++z) gg += t[z];
+    } else if (p >= L.b_off[l] && p < L.b_off[l] + nb) {
+      const float* q = P.b[l] + (p - L.b_off[l]);
+      int t = 0;
+      for (; t + 16 <= P.tiles; t += 16) {  // 16 loads in flight per round, summed in order
+        float u[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) u[j] = q[(int64_t)(t + j) * nb];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) gg += u[j];
+      }
+      for (; t < P.tiles; ++t) gg += q[(int64_t)t * nb];
+    }
+  }
+  g[p] = gg;
   const float mm = b1 * m[p] + (1.0f - b1) * gg;
   const float vv = b2 * v[p] + (1.0f - b2) * gg * gg;
   m[p] = mm;
@@ -232,42 +344,60 @@ __global__ void adam_step(float* w, float* m, float* v, const float* g, uint16_t
 
 // Normalised network inputs of work items [q0, q0 + count): item b is
 // trajectory (q0 + b) or, for training, the affine permutation
-// (mult * (q0 + b) + add) mod n.  Writes A0 [count][4] bf16 and, when y is
-// given, the normalised targets T [count][48].
+// (mult * (q0 + b) + add) mod n.  One wave per item, one lane per value:
+// lanes 0-3 write A0 [count][4] bf16 (rho, x0, y0, z0), lanes 4 .. 3 + nout
+// (nout <= 60) the normalised targets T [count][nout] when y is given.
 __global__ void gather_batch(const float* params, const float* u0, const float* y, int64_t n,
                              int64_t q0, int64_t count, uint64_t mult, uint64_t add,
                              const float* norm, uint16_t* a0, float* T, int nout) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int r = threadIdx.x & 63;
   if (b >= count) return;
   const int64_t i = (int64_t)(((unsigned __int128)mult * (uint64_t)(q0 + b) + add) % (uint64_t)n);
-  const float x[4] = {params[n + i], u0[i], u0[n + i], u0[2 * n + i]};  // rho, x0, y0, z0
-#pragma unroll
-  for (int f = 0; f < 4; ++f) a0[b * 4 + f] = f2bf((x[f] - norm[kInMean + f]) * norm[kInIStd + f]);
-  if (y)
-    for (int o = 0; o < nout; ++o)
-      T[b * nout + o] = (y[(int64_t)o * n + i] - norm[kOutMean + o]) * norm[kOutIStd + o];
+  if (r < 4) {
+    const float x = r == 0 ? params[n + i] : u0[(int64_t)(r - 1) * n + i];
+    a0[b * 4 + r] = f2bf((x - norm[kInMean + r]) * norm[kInIStd + r]);
+  } else if (y && r - 4 < nout) {
+    const int o = r - 4;
+    T[b * nout + o] = (y[(int64_t)o * n + i] - norm[kOutMean + o]) * norm[kOutIStd + o];
+  }
 }
 
-// G = scale (Y - T) in FP32 and bf16; per-block partial sums of (Y - T)^2.
-__global__ void loss_grad(const float* Y, const float* T, float* g, uint16_t* gb, int64_t cnt,
-                          float scale, double* partial) {
+// G = scale (Y - T) in FP32 and bf16 for rows [64 t, 64 t + 64) of block t
+// (cols <= 64 outputs per row); the block's sum of (Y - T)^2 goes to
+// partial[t] and its FP32 column sums of G, the output layer's bias-gradient
+// partial, to colpart[t][c].  Fixed summation order.
+__global__ void loss_grad(const float* Y, const float* T, float* g, uint16_t* gb, int64_t rows,
+                          int cols, float scale, double* partial, float* colpart) {
   __shared__ double red[256];
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float cred[4][64];
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
   double e2 = 0.0;
-  if (p < cnt) {
-    const float d = Y[p] - T[p];
-    const float gg = scale * d;
-    g[p] = gg;
-    gb[p] = f2bf(gg);
-    e2 = (double)d * d;
+  float cs = 0.0f;
+  if (c < cols) {
+    for (int k = rg; k < 64; k += 4) {
+      const int64_t r = r0 + k;
+      if (r >= rows) break;
+      const int64_t p = r * cols + c;
+      const float d = Y[p] - T[p];
+      const float gg = scale * d;
+      g[p] = gg;
+      gb[p] = f2bf(gg);
+      e2 += (double)d * d;
+      cs += gg;
+    }
   }
   red[threadIdx.x] = e2;
+  cred[rg][c] = cs;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  if (rg == 0 && c < cols)
+    colpart[(int64_t)blockIdx.x * cols + c] = (cred[0][c] + cred[1][c]) + (cred[2][c] + cred[3][c]);
 }
 
 // out[0] = factor * sum(partial[0..count)), one block, fixed order.
@@ -282,34 +412,6 @@ __global__ void finish_sum(const double* partial, int64_t count, double factor, 
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = (float)(factor * red[0]);
-}
-
-// part[y][c] = sum of G[r][c] over the y-th range of rows: 64 columns per
-// block, four row lanes per column (strided), combined in LDS in a fixed
-// order.
-__global__ void col_sums(const float* G, int64_t rows, int64_t cols, int64_t rows_per,
-                         float* part) {
-  __shared__ float red[4][64];
-  const int cl = threadIdx.x & 63, rl = threadIdx.x >> 6;
-  const int64_t c = (int64_t)blockIdx.x * 64 + cl;
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per;
-  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
-  float s = 0.0f;
-  if (c < cols)
-    for (int64_t r = r0 + rl; r < r1; r += 4) s += G[r * cols + c];
-  red[rl][cl] = s;
-  __syncthreads();
-  if (rl == 0 && c < cols)
-    part[(int64_t)blockIdx.y * cols + c] = (red[0][cl] + red[1][cl]) + (red[2][cl] + red[3][cl]);
-}
-
-// out[i] = sum over z of part[z][i] in increasing z (deterministic).
-__global__ void sum_splits(const float* part, int splits, int64_t count, float* out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  float s = part[i];
-  for (int z = 1; z < splits; ++z) s += part[(int64_t)z * count + i];
-  out[i] = s;
 }
 
 // Mean, 1/std and std (population, std floored at 1e-6) of `nrows` rows of
@@ -370,10 +472,11 @@ hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_adam(float* w, float* m, float* v, const float* g, uint16_t* wb, int64_t n,
-                    float lr, float b1, float b2, float eps, float c1, float c2, hipStream_t s) {
-  hipLaunchKernelGGL(adam_step, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g,
-                     wb, n, lr, b1, b2, eps, c1, c2);
+hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, const MlpLayout& L,
+                    const GradParts& parts, float lr, float b1, float b2, float eps, float c1,
+                    float c2, hipStream_t s) {
+  hipLaunchKernelGGL(adam_step, dim3((unsigned)((L.total + 255) / 256)), dim3(256), 0, s, w, m, v,
+                     g, wb, L.total, parts, L, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 
@@ -381,8 +484,9 @@ hipError_t mlp_gather(const float* params, const float* u0, const float* y, int6
                       int64_t count, uint64_t mult, uint64_t add, const float* norm, uint16_t* a0,
                       float* T, int nout, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_batch, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, params,
-                     u0, y, n, q0, count, mult, add, norm, a0, T, nout);
+  if (nout > 60) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gather_batch, dim3((unsigned)((count + 3) / 4)), dim3(256), 0, s, params, u0,
+                     y, n, q0, count, mult, add, norm, a0, T, nout);
   return hipGetLastError();
 }
 
@@ -424,21 +528,25 @@ hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, c
   return e;
 }
 
-// Loss and gradient of a training batch whose forward pass is in acts / Y.
+// Loss and gradient partials of a training batch whose forward pass is in
+// acts / Y: per layer, the kSplits split-K partials of dW into parts.w[l] and
+// the 64-row block partials of db into parts.b[l] (the Adam kernel sums
+// them).  Needs cols of the output layer <= 64.
 hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
-                        MlpActs& acts, const float* Y, const float* T, float* grad,
+                        MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                         double* partial, float* loss, hipStream_t s) {
   const int nl = L.layers;
   const int nout = L.dims[nl];
-  const int64_t cnt = B * nout;
-  const unsigned nb = (unsigned)((cnt + 255) / 256);
-  hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(256), 0, s, Y, T, acts.g[0], acts.gb[0], cnt,
-                     (float)(2.0 / (double)cnt), partial);
+  if (nout > 64) return hipErrorInvalidValue;
+  const unsigned tiles = (unsigned)((B + 63) / 64);
+  parts.tiles = (int)tiles;
+  hipLaunchKernelGGL(loss_grad, dim3(tiles), dim3(256), 0, s, Y, T, acts.g[0], acts.gb[0], B, nout,
+                     (float)(2.0 / (double)(B * nout)), partial, parts.b[nl - 1]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (loss) {
-    hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, s, partial, (int64_t)nb,
-                       1.0 / (double)cnt, loss);
+    hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, s, partial, (int64_t)tiles,
+                       1.0 / (double)(B * nout), loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   int cur = 0;
@@ -446,26 +554,18 @@ hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* 
     const int nin = L.dims[l], no = L.dims[l + 1];
     const uint16_t* prev = l > 0 ? acts.act[l - 1] : a0;
     // dW_l [no][nin] = G^T [no x B] . A_{l-1} [B x nin], K = B cut into
-    // kSplits ranges (partials summed in a fixed order)
+    // kSplits ranges
     const int64_t cnt_w = (int64_t)no * nin;
     e = gemm<kKRow, kKRow>(acts.gb[cur], no, prev, nin, no, nin, B,
-                           EpiStore{acts.split, nin, cnt_w}, s, kSplits);
+                           EpiStore{parts.w[l], nin, cnt_w}, s, kSplits);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_splits, dim3((unsigned)((cnt_w + 255) / 256)), dim3(256), 0, s,
-                       acts.split, kSplits, cnt_w, grad + L.w_off[l]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // db_l = column sums of G
-    const int64_t rows_per = (B + kSplits - 1) / kSplits;
-    hipLaunchKernelGGL(col_sums, dim3((unsigned)((no + 63) / 64), (unsigned)kSplits), dim3(256), 0,
-                       s, acts.g[cur], B, (int64_t)no, rows_per, acts.split);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(sum_splits, dim3((unsigned)((no + 255) / 256)), dim3(256), 0, s, acts.split,
-                       kSplits, (int64_t)no, grad + L.b_off[l]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
     if (l > 0) {
-      // G_{l-1} [B x nin] = (G [B x no] . W_l [no x nin]) * silu'(Z_{l-1})
+      // G_{l-1} [B x nin] = (G [B x no] . W_l [no x nin]) * silu'(Z_{l-1}),
+      // with the bias-gradient partials of layer l-1
       e = gemm<kRowK, kKRow>(acts.gb[cur], no, wb + L.w_off[l], nin, B, nin, no,
-                             EpiBack{acts.z[l - 1], acts.g[cur ^ 1], acts.gb[cur ^ 1], nin}, s);
+                             EpiBack{acts.z[l - 1], acts.g[cur ^ 1], acts.gb[cur ^ 1], nin,
+                                     parts.b[l - 1]},
+                             s);
       if (e != hipSuccess) return e;
       cur ^= 1;
     }

@@ -166,8 +166,9 @@ struct ens_surrogate {
   float* T = nullptr;
   float* g[2] = {};
   uint16_t* gb[2] = {};
-  double* partial = nullptr;
-  float* split = nullptr;  // split-K partials of the weight gradients
+  double* partial = nullptr;  // per 64-row block loss sums
+  float* wparts = nullptr;    // split-K partials of the weight gradients, every layer
+  float* bparts = nullptr;    // 64-row block partials of the bias gradients, every layer
   // inference workspace (chunk capacity)
   int64_t cap_chunk = 0;
   uint16_t* ia0 = nullptr;
@@ -187,23 +188,44 @@ namespace {
 void free_all(ens_surrogate* s) {
   void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
                 s->act[0], s->act[1], s->act[2], s->Y, s->T, s->g[0], s->g[1], s->gb[0],
-                s->gb[1], s->partial, s->split, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
+                s->gb[1], s->partial, s->wparts, s->bparts, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
                 s->scratch, s->used, s->counts, s->words};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
 
+int64_t weight_count(const ens::MlpLayout& L) {
+  int64_t w = 0;
+  for (int l = 0; l < L.layers; ++l) w += (int64_t)L.dims[l] * L.dims[l + 1];
+  return w;
+}
+
+// Where the step's gradient partials go inside the model's two buffers.
+ens::GradParts grad_parts(const ens_surrogate* s, int64_t B) {
+  ens::GradParts P{};
+  int64_t wo = 0, bo = 0;
+  const int64_t tiles = (B + 63) / 64;
+  for (int l = 0; l < s->L.layers; ++l) {
+    P.w[l] = s->wparts + wo;
+    P.b[l] = s->bparts + bo;
+    wo += (int64_t)ens::kSplits * s->L.dims[l] * s->L.dims[l + 1];
+    bo += tiles * s->L.dims[l + 1];
+  }
+  return P;
+}
+
 int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   if (B <= s->cap_batch) return ENS_OK;
   void* old[] = {s->a0, s->z[0], s->z[1], s->z[2], s->act[0], s->act[1], s->act[2], s->Y, s->T,
-                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial, s->split};
+                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial, s->wparts, s->bparts};
   for (void* p : old)
     if (p) (void)hipFree(p);
   const int H = kDims[1], O = kDims[4];
   bool ok = alloc(&s->a0, B * kDims[0]) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
             alloc(&s->T, B * O) == hipSuccess &&
-            alloc(&s->partial, (B * H + 255) / 256 + 1) == hipSuccess &&
-            alloc(&s->split, (int64_t)ens::kSplits * H * H) == hipSuccess;
+            alloc(&s->partial, (B + 63) / 64) == hipSuccess &&
+            alloc(&s->wparts, (int64_t)ens::kSplits * weight_count(s->L)) == hipSuccess &&
+            alloc(&s->bparts, (B + 63) / 64 * (s->L.total - weight_count(s->L))) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
     ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
   for (int l = 0; l < 2 && ok; ++l)
@@ -284,18 +306,18 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     acts.g[l] = s->g[l];
     acts.gb[l] = s->gb[l];
   }
-  acts.split = s->split;
   hipError_t e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T,
                                  kDims[4], st);
   if (e == hipSuccess)
     e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->a0, B, acts, s->Y, nullptr, 0, 0, st);
+  ens::GradParts parts = grad_parts(s, B);
   if (e == hipSuccess)
-    e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, s->grad, s->partial, loss, st);
+    e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, parts, s->partial, loss, st);
   if (e == hipSuccess) {
     s->step += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)kAdamB1, (double)s->step));
     const double c2 = 1.0 / (1.0 - std::pow((double)kAdamB2, (double)s->step));
-    e = ens::mlp_adam(s->w, s->m, s->v, s->grad, s->wb, s->L.total, (float)lr, kAdamB1, kAdamB2,
+    e = ens::mlp_adam(s->w, s->m, s->v, s->grad, s->wb, s->L, parts, (float)lr, kAdamB1, kAdamB2,
                       kAdamEps, (float)c1, (float)c2, st);
   }
   if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate train step: %s", hipGetErrorString(e));

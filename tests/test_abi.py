@@ -97,3 +97,20 @@ def test_binding_constants_match_header():
     assert {k: surr[k] for k in _native.SURR_BUFFERS} == _native.SURR_BUFFERS
     assert surr["nparam"] == _native.SURR_NPARAM
 
+
+
+def test_valu_probe_library_loads_and_rejects_bad_kinds():
+    """The issue-rate probe the benchmark prices instruction streams with is a
+    separate shared object; it loads, exports its one entry point and rejects
+    an unknown kind or a null result pointer before touching a device."""
+    path = os.path.join(ROOT, "paper_2304_06835_amd", "libvaluprobe.so")
+    if not os.path.exists(path):
+        pytest.skip("libvaluprobe.so not built")
+    L = ctypes.CDLL(path)
+    f = L.valu_probe_rate
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    r = ctypes.c_double(0.0)
+    assert f(0, 99, 16, ctypes.byref(r)) == -1
+    assert f(0, -1, 16, ctypes.byref(r)) == -1
+    assert f(0, 0, 0, ctypes.byref(r)) == -1
+    assert f(0, 0, 16, None) == -1
