@@ -69,10 +69,10 @@ MLP_FLOPS_PER_QUERY = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 48)  # 288,76
 MLP_TRAIN_FLOPS_PER_SAMPLE = 2 * MLP_FLOPS_PER_QUERY + 2 * (256 * 256 + 256 * 256 + 256 * 48)
 
 # MI355X published vector peaks (256 CUs, 2.4 GHz): FP32 157.3 TFLOP/s, FP64
-# 78.6 TFLOP/s; dense bf16 MFMA 2.5 PFLOP/s.  The FP32 figure is reached by
-# ordinary (non-packed) FP32 instructions on gfx950: a microbenchmark of
-# independent v_fma/v_mul/v_add_f32 chains issues 21-23 lane-ops per SIMD
-# clock, above the 16 of a 16-lane SIMD (FP64 FMA: 12.3; exp/rcp: ~7).
+# 78.6 TFLOP/s; dense bf16 MFMA 2.5 PFLOP/s.  The FP32 figure counts 32 FMA
+# lanes per SIMD clock; ordinary (non-packed) FP32 instructions issue fewer
+# (the probe, issue_rates(), measures about 23 lane-ops per SIMD per rated
+# clock), which the issue roofline accounts for.
 PEAK = {32: 157.3, 64: 78.6}
 PEAK_BF16_MFMA = 2500.0
 
@@ -116,6 +116,8 @@ def parse():
     ap.add_argument("--surrogate-only", action="store_true",
                     help="only train the surrogate for --surrogate-epochs epochs on 2^20 solver "
                          "trajectories and run its inference on 2^24 queries (for profiling)")
+    ap.add_argument("--surrogate-scaling", action="store_true",
+                    help="with --surrogate-only: also time training at several batch sizes")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target wall time of the CPU-baseline sample")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -741,7 +743,7 @@ def surrogate_variant(epochs, plain_ms_2p24):
     return res
 
 
-def surrogate_only(epochs):
+def surrogate_only(epochs, scaling=False):
     """Training and inference of the surrogate alone, no audit: the workload
     of the MFMA counter profiles."""
     import torch
@@ -768,7 +770,8 @@ def surrogate_only(epochs):
         "train_epochs": epochs, "train_samples": 1 << 20, "train_seconds": train_s,
         "train_tflops": train_tf, "predict_ms": pred_ms, "queries": q.n,
         "predict_tflops": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12,
-        "train_batch_scaling": train_batch_scaling(s, P, U, y)}}), flush=True)
+        "train_batch_scaling": train_batch_scaling(s, P, U, y) if scaling else None}}),
+        flush=True)
 
 
 def train_batch_scaling(s, P, U, y, batches=(4096, 16384, 65536), epochs=2):
@@ -803,7 +806,7 @@ def main():
         copy_calibration()
         return
     if args.surrogate_only:
-        surrogate_only(args.surrogate_epochs)
+        surrogate_only(args.surrogate_epochs, args.surrogate_scaling)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "

@@ -46,8 +46,7 @@ struct MlpActs {
   bool keep_all;        // training: every hidden layer's Z and A are kept
   float* z[kMlpMaxLayers];
   uint16_t* act[kMlpMaxLayers];
-  float* g[2];          // gradient ping-pong, FP32
-  uint16_t* gb[2];      // and bf16
+  uint16_t* gb[kMlpMaxLayers];  // training: bf16 output gradient G_l of every layer
 };
 
 // Split-K factor of the weight-gradient products (K = batch).

@@ -99,31 +99,28 @@ __device__ inline void store_frag(uint16_t (*dst)[LDW], uint4 v, int tid, int c)
   }
 }
 
-// C[M x N] = A[M x K] B[K x N]; A stored per LA, B per LB (with "rows" = N).
-// blockIdx.z selects the K range [z kc, min(K, (z+1) kc)) of a split-K
-// product; the epilogue sees blockIdx.z and writes that split's partial.
-// K is consumed in rounds of KB through LDS; the next round's global loads
-// are issued before the current round's products, so they overlap them.  An epilogue with kColSums also
-// receives, per output column, the sum over the block's 64 rows of the
-// values it returned (fixed order: rows within a lane, then the four row
-// groups of a wave, then the two waves).
+// One 64 x 64 tile of C[M x N] = A[M x K] B[K x N] over the K range
+// [kbeg, kend), rows from m0 and columns from n0; A stored per LA, B per LB
+// (with "rows" = N).  K is consumed in rounds of KB through LDS; the next
+// round's global loads are issued before the current round's products, so
+// they overlap them.  An epilogue with kColSums also receives, per output
+// column, the sum over the tile's 64 rows of the values it returned (fixed
+// order: rows within a lane, then the four row groups of a wave, then the
+// two waves), tagged with the tile's row index `tile_m`.
 template <int LA, int LB, class Epi>
-__global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A, int64_t lda,
-                                                 const uint16_t* __restrict__ B, int64_t ldb,
-                                                 int64_t M, int64_t N, int64_t K, int64_t kc,
-                                                 Epi epi) {
+__device__ inline void gemm_tile(const uint16_t* __restrict__ A, int64_t lda,
+                                 const uint16_t* __restrict__ B, int64_t ldb, int64_t M, int64_t N,
+                                 int64_t kbeg, int64_t kend, int64_t m0, int64_t n0, int64_t tile_m,
+                                 const Epi& epi) {
   __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDW];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
   f32x4_t acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int64_t kbeg = (int64_t)blockIdx.z * kc;
-  const int64_t kend = kbeg + kc < K ? kbeg + kc : K;
   uint4 fa[kChunks], fb[kChunks];
   if (kbeg < kend) {
 #pragma unroll
@@ -186,8 +183,22 @@ __global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A,
       if (lane < 16) red[wm][wn * 32 + b * 16 + lane] = v;
     }
     __syncthreads();
-    if (tid < BN && n0 + tid < N) epi.colsum(blockIdx.y, n0 + tid, red[0][tid] + red[1][tid]);
+    if (tid < BN && n0 + tid < N) epi.colsum(tile_m, n0 + tid, red[0][tid] + red[1][tid]);
   }
+}
+
+// Grid-mapped product: blockIdx.x / .y pick the column / row tile, and
+// blockIdx.z the K range [z kc, min(K, (z+1) kc)) of a split-K product.
+template <int LA, int LB, class Epi>
+__global__ void __launch_bounds__(256) gemm_bf16(const uint16_t* __restrict__ A, int64_t lda,
+                                                 const uint16_t* __restrict__ B, int64_t ldb,
+                                                 int64_t M, int64_t N, int64_t K, int64_t kc,
+                                                 Epi epi) {
+  const int64_t kbeg = (int64_t)blockIdx.z * kc;
+  const int64_t kend = kbeg + kc < K ? kbeg + kc : K;
+  epi.split = blockIdx.z;
+  gemm_tile<LA, LB>(A, lda, B, ldb, M, N, kbeg, kend, (int64_t)blockIdx.y * BM,
+                    (int64_t)blockIdx.x * BN, blockIdx.y, epi);
 }
 
 // ---- epilogues -------------------------------------------------------------
@@ -199,6 +210,7 @@ struct EpiHidden {  // Z = acc + b (kept for the backward pass), A = bf16(silu(Z
   float* z;
   uint16_t* act;
   int64_t ld;
+  int split = 0;  // K range of a split-K product (set by the kernel)
   __device__ float operator()(int64_t m, int64_t n, float v) const {
     const float zz = v + bias[n];
     if (z) z[m * ld + n] = zz;
@@ -212,6 +224,7 @@ struct EpiLinear {  // Y = acc + b
   const float* bias;
   float* y;
   int64_t ld;
+  int split = 0;  // K range of a split-K product (set by the kernel)
   __device__ float operator()(int64_t m, int64_t n, float v) const {
     y[m * ld + n] = v + bias[n];
     return 0.0f;
@@ -225,40 +238,73 @@ struct EpiSoA {  // de-normalised output into out[n][q0 + m] (structure of array
   const float* stdv;
   float* out;
   int64_t stride, q0;
+  int split = 0;  // K range of a split-K product (set by the kernel)
   __device__ float operator()(int64_t m, int64_t n, float v) const {
     out[n * stride + q0 + m] = fmaf(v + bias[n], stdv[n], mean[n]);
     return 0.0f;
   }
   __device__ void colsum(int64_t, int64_t, float) const {}
 };
-// G = acc * silu'(Z) in FP32 and bf16; the FP32 column sums of each 64-row
+// G = acc * silu'(Z), stored in bf16; the FP32 column sums of each 64-row
 // block are that block's partial of the layer's bias gradient, stored at
-// colpart[blockIdx.y][n].
+// colpart[row tile][n].
 struct EpiBack {
   static constexpr bool kColSums = true;
   const float* z;
-  float* g;
   uint16_t* gb;
   int64_t ld;
   float* colpart;
+  int split = 0;  // K range of a split-K product (set by the kernel)
   __device__ float operator()(int64_t m, int64_t n, float v) const {
     const float gg = v * dsilu(z[m * ld + n]);
-    g[m * ld + n] = gg;
     gb[m * ld + n] = f2bf(gg);
     return gg;
   }
   __device__ void colsum(int64_t by, int64_t n, float s) const { colpart[by * ld + n] = s; }
 };
-struct EpiStore {  // partial product of split blockIdx.z at c + z * zstride
+struct EpiStore {  // partial product of K range `split` at c + split * zstride
   static constexpr bool kColSums = false;
   float* c;
   int64_t ld, zstride;
+  int split = 0;  // K range of a split-K product (set by the kernel)
   __device__ float operator()(int64_t m, int64_t n, float v) const {
-    c[(int64_t)blockIdx.z * zstride + m * ld + n] = v;
+    c[(int64_t)split * zstride + m * ld + n] = v;
     return 0.0f;
   }
   __device__ void colsum(int64_t, int64_t, float) const {}
 };
+
+// The split-K weight-gradient products of every layer in one launch.  Block
+// b belongs to the last problem whose block0 <= b; its index within the
+// problem picks the K range (split), then the row tile, then the column tile.
+struct GemmProblem {
+  const uint16_t* A;  // kKRow: element (r, k) at A[k * lda + r]
+  const uint16_t* B;  // kKRow
+  float* C;           // [splits][M][N] partials
+  int64_t lda, ldb, M, N, K, kc, block0;
+  int tiles_m, tiles_n;
+};
+struct GemmGroup {
+  GemmProblem p[kMlpMaxLayers];
+  int count;
+};
+
+__global__ void __launch_bounds__(256) gemm_grouped_store(GemmGroup G) {
+  int q = 0;
+  for (int i = 1; i < G.count; ++i)
+    if ((int64_t)blockIdx.x >= G.p[i].block0) q = i;
+  const GemmProblem& P = G.p[q];
+  const int64_t local = (int64_t)blockIdx.x - P.block0;
+  const int64_t per_split = (int64_t)P.tiles_m * P.tiles_n;
+  const int split = (int)(local / per_split);
+  const int64_t rem = local - split * per_split;
+  const int64_t tm = rem / P.tiles_n, tn = rem - tm * P.tiles_n;
+  const int64_t kbeg = split * P.kc;
+  const int64_t kend = kbeg + P.kc < P.K ? kbeg + P.kc : P.K;
+  EpiStore epi{P.C, P.N, P.M * P.N};
+  epi.split = split;
+  gemm_tile<kKRow, kKRow>(P.A, P.lda, P.B, P.ldb, P.M, P.N, kbeg, kend, tm * BM, tn * BN, tm, epi);
+}
 
 // `splits` > 1: K is cut into that many ranges of a multiple of 32 each.
 template <int LA, int LB, class Epi>
@@ -363,12 +409,12 @@ __global__ void gather_batch(const float* params, const float* u0, const float* 
   }
 }
 
-// G = scale (Y - T) in FP32 and bf16 for rows [64 t, 64 t + 64) of block t
+// G = scale (Y - T), stored in bf16, for rows [64 t, 64 t + 64) of block t
 // (cols <= 64 outputs per row); the block's sum of (Y - T)^2 goes to
 // partial[t] and its FP32 column sums of G, the output layer's bias-gradient
 // partial, to colpart[t][c].  Fixed summation order.
-__global__ void loss_grad(const float* Y, const float* T, float* g, uint16_t* gb, int64_t rows,
-                          int cols, float scale, double* partial, float* colpart) {
+__global__ void loss_grad(const float* Y, const float* T, uint16_t* gb, int64_t rows, int cols,
+                          float scale, double* partial, float* colpart) {
   __shared__ double red[256];
   __shared__ float cred[4][64];
   const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
@@ -382,7 +428,6 @@ __global__ void loss_grad(const float* Y, const float* T, float* g, uint16_t* gb
       const int64_t p = r * cols + c;
       const float d = Y[p] - T[p];
       const float gg = scale * d;
-      g[p] = gg;
       gb[p] = f2bf(gg);
       e2 += (double)d * d;
       cs += gg;
@@ -529,18 +574,20 @@ hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, c
 }
 
 // Loss and gradient partials of a training batch whose forward pass is in
-// acts / Y: per layer, the kSplits split-K partials of dW into parts.w[l] and
-// the 64-row block partials of db into parts.b[l] (the Adam kernel sums
-// them).  Needs cols of the output layer <= 64.
+// acts / Y: the output gradient and the input gradients of layers 3..1 in
+// sequence (each product's epilogue leaving the bias-gradient partials of
+// its layer in parts.b), then the kSplits split-K partials of every
+// layer's dW in one grouped launch into parts.w (the Adam kernel sums both).
+// Needs the output layer's width <= 64.
 hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
                         MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                         double* partial, float* loss, hipStream_t s) {
   const int nl = L.layers;
   const int nout = L.dims[nl];
-  if (nout > 64) return hipErrorInvalidValue;
+  if (nout > 64 || nl > kMlpMaxLayers) return hipErrorInvalidValue;
   const unsigned tiles = (unsigned)((B + 63) / 64);
   parts.tiles = (int)tiles;
-  hipLaunchKernelGGL(loss_grad, dim3(tiles), dim3(256), 0, s, Y, T, acts.g[0], acts.gb[0], B, nout,
+  hipLaunchKernelGGL(loss_grad, dim3(tiles), dim3(256), 0, s, Y, T, acts.gb[nl - 1], B, nout,
                      (float)(2.0 / (double)(B * nout)), partial, parts.b[nl - 1]);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -549,28 +596,38 @@ hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* 
                        1.0 / (double)(B * nout), loss);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  int cur = 0;
-  for (int l = nl - 1; l >= 0; --l) {
+  // G_{l-1} [B x nin] = (G_l [B x no] . W_l [no x nin]) * silu'(Z_{l-1})
+  for (int l = nl - 1; l > 0; --l) {
     const int nin = L.dims[l], no = L.dims[l + 1];
-    const uint16_t* prev = l > 0 ? acts.act[l - 1] : a0;
-    // dW_l [no][nin] = G^T [no x B] . A_{l-1} [B x nin], K = B cut into
-    // kSplits ranges
-    const int64_t cnt_w = (int64_t)no * nin;
-    e = gemm<kKRow, kKRow>(acts.gb[cur], no, prev, nin, no, nin, B,
-                           EpiStore{parts.w[l], nin, cnt_w}, s, kSplits);
+    e = gemm<kRowK, kKRow>(acts.gb[l], no, wb + L.w_off[l], nin, B, nin, no,
+                           EpiBack{acts.z[l - 1], acts.gb[l - 1], nin, parts.b[l - 1]}, s);
     if (e != hipSuccess) return e;
-    if (l > 0) {
-      // G_{l-1} [B x nin] = (G [B x no] . W_l [no x nin]) * silu'(Z_{l-1}),
-      // with the bias-gradient partials of layer l-1
-      e = gemm<kRowK, kKRow>(acts.gb[cur], no, wb + L.w_off[l], nin, B, nin, no,
-                             EpiBack{acts.z[l - 1], acts.g[cur ^ 1], acts.gb[cur ^ 1], nin,
-                                     parts.b[l - 1]},
-                             s);
-      if (e != hipSuccess) return e;
-      cur ^= 1;
-    }
   }
-  return hipSuccess;
+  // dW_l [no][nin] = G_l^T [no x B] . A_{l-1} [B x nin], K = B in kSplits ranges
+  GemmGroup G{};
+  G.count = nl;
+  int64_t blocks = 0;
+  int64_t kc = (B + kSplits - 1) / kSplits;
+  kc = (kc + 31) / 32 * 32;
+  for (int l = 0; l < nl; ++l) {
+    const int nin = L.dims[l], no = L.dims[l + 1];
+    GemmProblem& P = G.p[l];
+    P.A = acts.gb[l];
+    P.lda = no;
+    P.B = l > 0 ? acts.act[l - 1] : a0;
+    P.ldb = nin;
+    P.C = parts.w[l];
+    P.M = no;
+    P.N = nin;
+    P.K = B;
+    P.kc = kc;
+    P.tiles_m = (no + BM - 1) / BM;
+    P.tiles_n = (nin + BN - 1) / BN;
+    P.block0 = blocks;
+    blocks += (int64_t)P.tiles_m * P.tiles_n * kSplits;
+  }
+  hipLaunchKernelGGL(gemm_grouped_store, dim3((unsigned)blocks), dim3(256), 0, s, G);
+  return hipGetLastError();
 }
 
 }  // namespace ens

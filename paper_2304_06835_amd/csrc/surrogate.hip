@@ -164,8 +164,7 @@ struct ens_surrogate {
   uint16_t* act[3] = {};
   float* Y = nullptr;
   float* T = nullptr;
-  float* g[2] = {};
-  uint16_t* gb[2] = {};
+  uint16_t* gb[4] = {};  // bf16 output gradient of every layer
   double* partial = nullptr;  // per 64-row block loss sums
   float* wparts = nullptr;    // split-K partials of the weight gradients, every layer
   float* bparts = nullptr;    // 64-row block partials of the bias gradients, every layer
@@ -187,8 +186,8 @@ namespace {
 
 void free_all(ens_surrogate* s) {
   void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
-                s->act[0], s->act[1], s->act[2], s->Y, s->T, s->g[0], s->g[1], s->gb[0],
-                s->gb[1], s->partial, s->wparts, s->bparts, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
+                s->act[0], s->act[1], s->act[2], s->Y, s->T, s->gb[0], s->gb[1], s->gb[2],
+                s->gb[3], s->partial, s->wparts, s->bparts, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
                 s->scratch, s->used, s->counts, s->words};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -217,7 +216,7 @@ ens::GradParts grad_parts(const ens_surrogate* s, int64_t B) {
 int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   if (B <= s->cap_batch) return ENS_OK;
   void* old[] = {s->a0, s->z[0], s->z[1], s->z[2], s->act[0], s->act[1], s->act[2], s->Y, s->T,
-                 s->g[0], s->g[1], s->gb[0], s->gb[1], s->partial, s->wparts, s->bparts};
+                 s->gb[0], s->gb[1], s->gb[2], s->gb[3], s->partial, s->wparts, s->bparts};
   for (void* p : old)
     if (p) (void)hipFree(p);
   const int H = kDims[1], O = kDims[4];
@@ -228,8 +227,7 @@ int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
             alloc(&s->bparts, (B + 63) / 64 * (s->L.total - weight_count(s->L))) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
     ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
-  for (int l = 0; l < 2 && ok; ++l)
-    ok = alloc(&s->g[l], B * H) == hipSuccess && alloc(&s->gb[l], B * H) == hipSuccess;
+  for (int l = 0; l < 4 && ok; ++l) ok = alloc(&s->gb[l], B * kDims[l + 1]) == hipSuccess;
   if (!ok) {
     s->cap_batch = 0;
     return fail(c, ENS_ENOMEM, "cannot allocate the training workspace for batch %lld",
@@ -302,10 +300,7 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     acts.z[l] = s->z[l];
     acts.act[l] = s->act[l];
   }
-  for (int l = 0; l < 2; ++l) {
-    acts.g[l] = s->g[l];
-    acts.gb[l] = s->gb[l];
-  }
+  for (int l = 0; l < 4; ++l) acts.gb[l] = s->gb[l];
   hipError_t e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T,
                                  kDims[4], st);
   if (e == hipSuccess)
