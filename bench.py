@@ -319,10 +319,10 @@ def issue_rates(device=0, iters=16384):
     return out
 
 
-def recorded_valu_mix(key):
+def recorded_valu_mix(key, path=None):
     """Wave-level VALU instruction counts per launch by class, from a committed
     rocprofv3 record (profiles/valu_mix.json) taken on the current sources."""
-    path = os.path.join(ROOT, "profiles", "valu_mix.json")
+    path = path or os.path.join(ROOT, "profiles", "valu_mix.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:

@@ -1,0 +1,85 @@
+"""Host-side arithmetic of bench.py's measurement objects (no GPU): the
+issue roofline, the recorded instruction mixes and the CPU description."""
+import json
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_issue_roofline_prices_each_class_at_its_rate():
+    """A launch of 1e9 FMA and 1e9 transcendental wave instructions, probed
+    at 32 and 8 lane-ops per SIMD per rated clock: it needs
+    1e9 * 64 / (32 c) + 1e9 * 64 / (8 c) seconds with c = 1024 SIMDs x 2.4 GHz;
+    timed at exactly that, the fraction is 1 and the ceiling rate is the
+    harmonic combination 2 / (64/32 + 64/8) = 0.2 wave instructions per
+    SIMD-clock."""
+    c = 1024 * 2.4e9
+    rates = {k: 16.0 * c for k in bench.PROBE_KINDS}
+    rates["fma_f32"] = 32.0 * c
+    rates["exp_f32"] = 8.0 * c
+    mix = {"per_launch": {"FMA_F32": 1e9, "TRANS_F32": 1e9}, "lanes_active_per_instr": 0.9}
+    need = 1e9 * 64 / (32 * c) + 1e9 * 64 / (8 * c)
+    r = bench.issue_roofline(mix, rates, need * 1e3)
+    assert r["frac"] == pytest.approx(1.0, rel=1e-12)
+    assert r["ceiling_wave_instr_per_simd_clock"] == pytest.approx(0.2, rel=1e-12)
+    assert r["achieved_wave_instr_per_simd_clock"] == pytest.approx(0.2, rel=1e-12)
+    assert r["class_mix"] == pytest.approx({"FMA_F32": 0.5, "TRANS_F32": 0.5})
+    # twice as long: half the ceiling
+    assert bench.issue_roofline(mix, rates, 2 * need * 1e3)["frac"] == pytest.approx(0.5)
+    assert bench.issue_roofline(None, rates, 1.0) is None
+
+
+def test_every_counted_class_has_a_probe_kind():
+    assert set(bench.VALU_CLASS_PROBE.values()) <= set(bench.PROBE_KINDS)
+
+
+def test_recorded_mixes_are_consistent():
+    """Each record of profiles/valu_mix.json: classes sum to SQ_INSTS_VALU,
+    every class is priced, the sources it names exist."""
+    path = os.path.join(ROOT, "profiles", "valu_mix.json")
+    rec = json.load(open(path))
+    keys = [k for k in rec if not k.startswith("_")]
+    assert keys
+    for k in keys:
+        r = rec[k]
+        tot = sum(r["per_launch"].values())
+        raw = r["sq_insts_valu_raw"]
+        assert tot == pytest.approx(sum(raw) / len(raw), rel=1e-9), k
+        assert set(r["per_launch"]) <= set(bench.VALU_CLASS_PROBE), k
+        assert all(v >= 0 for v in r["per_launch"].values()), k
+        assert 0 < r["lanes_active_per_instr"] <= 1.0, k
+        for f in r["sources"]:
+            assert os.path.exists(os.path.join(ROOT, "paper_2304_06835_amd", "csrc", f)), (k, f)
+
+
+def test_recorded_mix_is_ignored_once_sources_change(tmp_path):
+    good = bench.kernel_source_hash(["tsit5.hip"])
+    rec = {"w/a/f": {"sources": ["tsit5.hip"], "source_hash": "0000000000000000",
+                     "per_launch": {"FMA_F32": 1.0}},
+           "w/a/g": {"sources": ["tsit5.hip"], "source_hash": good,
+                     "per_launch": {"FMA_F32": 1.0}}}
+    path = tmp_path / "valu_mix.json"
+    path.write_text(json.dumps(rec))
+    assert bench.recorded_valu_mix("w/a/f", str(path)) is None
+    assert bench.recorded_valu_mix("w/a/g", str(path))["per_launch"] == {"FMA_F32": 1.0}
+    assert bench.recorded_valu_mix("missing", str(path)) is None
+
+
+def test_cpu_model_reports_the_host():
+    m = bench.cpu_model()
+    assert m["logical_cpus"] and m["logical_cpus"] >= 1
+    assert 1 <= m["affinity"] <= m["logical_cpus"]
+    assert m["model"] is None or isinstance(m["model"], str)
+
+
+def test_training_flops_per_sample():
+    """Forward 2 (4*256 + 2*256^2 + 256*48), the weight gradients the same,
+    the input gradients of layers 2..4 2 (2*256^2 + 256*48)."""
+    fwd = 2 * (4 * 256 + 2 * 256 * 256 + 256 * 48)
+    assert bench.MLP_FLOPS_PER_QUERY == fwd == 288768
+    assert bench.MLP_TRAIN_FLOPS_PER_SAMPLE == 2 * fwd + 2 * (2 * 256 * 256 + 256 * 48) == 864256
