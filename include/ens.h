@@ -417,16 +417,20 @@ int ens_surrogate_predict(ens_ctx *ctx, ens_surrogate *s, const float *params,
 
 /*
  * Audited surrogate solve of n Lorenz queries (same arguments as ens_solve
- * for ENS_SYS_LORENZ / ENS_ALG_TSIT5 at precision 32, n_save must be 16):
- *   1. the surrogate answers every query;
- *   2. each query is audited with probability audit_frac (Philox4x32-10 on
- *      the query id and audit_seed) and re-solved by the FP32 Tsit5 kernel;
- *      an audited query always returns the solver's answer;
- *   3. if an audited query's normwise error (max over save times of
+ * for ENS_SYS_LORENZ / ENS_ALG_TSIT5 at precision 32, n_save must be 16; the
+ * solver runs in the context's ENS_OPT_SAVE_MODE):
+ *   1. each query is audited with probability audit_frac (Philox4x32-10 on
+ *      the query id and audit_seed): the surrogate and the FP32 Tsit5 kernel
+ *      both answer it, and it returns the solver's answer;
+ *   2. if an audited query's normwise error (max over save times of
  *      ||surrogate - solver||_inf / ||solver||_inf) exceeds fallback_tol, its
  *      rho bin (28 equal bins over the training range of rho) is flagged;
- *   4. every query in a flagged bin, or outside the training box (any input
- *      outside its training min / max), is re-solved by the solver.
+ *   3. every other query in a flagged bin, or outside the training box (any
+ *      input outside its training min / max), is solved by the solver;
+ *   4. the surrogate answers the rest.
+ * With the fused inference kernel (ENS_OPT_MLP_TILE != 0) the network is
+ * evaluated only on the audited queries and those of step 4; with the tiled
+ * path it answers every query first (answers later replaced).
  * used_solver (device uint8 [n], may be NULL): 0 surrogate, 1 audited,
  * 2 fallback.  report (device float [4], may be NULL): audited count,
  * fallback count, flagged bins, max audited error.  Asynchronous.
@@ -444,7 +448,7 @@ int ens_surrogate_solve(ens_ctx *ctx, ens_surrogate *s, const float *params,
  * loops, harnesses that forbid hipMalloc.  Same arguments, results and
  * report as ens_surrogate_solve (the same kernels), but its workspace --
  * audit and fallback lists, the audited answers, per-query flags, counters
- * and bin flags -- is one static device array per GPU of about 18 MiB,
+ * and bin flags -- is one static device array per GPU of about 25 MiB,
  * held from the first ens_create on that GPU until the process ends,
  * instead of buffers the model allocates on demand.  Limits: n at most
  * ENS_STATIC_MAX_QUERIES, an audit list of at most 40960 entries (audit_frac

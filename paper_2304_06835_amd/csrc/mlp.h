@@ -89,5 +89,11 @@ hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hi
 hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const float* w,
                              const float* norm, const float* params, const float* u0, int64_t n,
                              float* out, int64_t stride, int num_cu, int ns, hipStream_t s);
+hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, const float* w,
+                                  const float* norm, const float* params, const float* u0,
+                                  int64_t n, int64_t in_stride, const int64_t* idx,
+                                  int64_t idx_step, const unsigned long long* n_dev,
+                                  int out_compact, float* out, int64_t stride, int num_cu, int ns,
+                                  hipStream_t s);
 
 }  // namespace ens

@@ -96,10 +96,17 @@ struct FusedArgs {
   const uint16_t* packed;
   const float* w;  // FP32 master parameters (biases)
   const float* norm;
-  const float* params;  // [3][n]: sigma, rho, beta
-  const float* u0;      // [3][n]
+  const float* params;  // [3][in_stride]: sigma, rho, beta
+  const float* u0;      // [3][in_stride]
   float* out;           // [48][stride]
-  int64_t n, stride;
+  int64_t n, stride, in_stride;
+  // optional query list: work item q reads row idx[q * idx_step] of params /
+  // u0 and writes that column of out (or column q with out_compact); the
+  // item count is then *n_dev (at most n) when n_dev is given
+  const int64_t* idx;
+  int64_t idx_step;
+  const unsigned long long* n_dev;
+  int out_compact;
   int64_t b_off[4];
 };
 
@@ -234,7 +241,10 @@ mlp_fused_fwd(const FusedArgs a) {
   __syncthreads();
 
   const float* bs = reinterpret_cast<const float*>(lds + kLdsBias);
-  const int64_t n = a.n, tq = 16 * NS * NW;
+  const int64_t n = a.n_dev ? (int64_t)(*a.n_dev < (unsigned long long)a.n ? *a.n_dev
+                                                                           : (unsigned long long)a.n)
+                            : a.n;
+  const int64_t tq = 16 * NS * NW, ns = a.in_stride;
   const int64_t ntiles = (n + tq - 1) / tq;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t qw = tile * tq + (int64_t)wave * 16 * NS;  // this wave's first query
@@ -248,10 +258,11 @@ mlp_fused_fwd(const FusedArgs a) {
         const int64_t q = qw + 16 * s + col;
         float f[4] = {0.f, 0.f, 0.f, 0.f};
         if (g == 0 && q < n) {
-          f[0] = a.params[n + q];
-          f[1] = a.u0[q];
-          f[2] = a.u0[n + q];
-          f[3] = a.u0[2 * n + q];
+          const int64_t i = a.idx ? a.idx[q * a.idx_step] : q;
+          f[0] = a.params[ns + i];
+          f[1] = a.u0[i];
+          f[2] = a.u0[ns + i];
+          f[3] = a.u0[2 * ns + i];
 #pragma unroll
           for (int k = 0; k < 4; ++k) f[k] = (f[k] - bs[kBInMean + k]) * bs[kBInIStd + k];
         }
@@ -313,10 +324,11 @@ mlp_fused_fwd(const FusedArgs a) {
       for (int s = 0; s < NS; ++s) {
         const int64_t q = qw + 16 * s + col;
         if (q < n) {
+          const int64_t oc = (a.idx && !a.out_compact) ? a.idx[q * a.idx_step] : q;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int o = 16 * rb + 4 * g + r;
-            a.out[(int64_t)o * a.stride + q] = fmaf(acc[s][r], bs[kBStd + o], bs[kBMean + o]);
+            a.out[(int64_t)o * a.stride + oc] = fmaf(acc[s][r], bs[kBStd + o], bs[kBMean + o]);
           }
         }
       }
@@ -339,6 +351,19 @@ hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hi
 hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const float* w,
                              const float* norm, const float* params, const float* u0, int64_t n,
                              float* out, int64_t stride, int num_cu, int ns, hipStream_t s) {
+  return mlp_forward_fused_list(L, packed, w, norm, params, u0, n, n, nullptr, 1, nullptr, 0, out,
+                                stride, num_cu, ns, s);
+}
+
+// Queries from a list: item q < min(n, *n_dev) is row idx[q * idx_step] of
+// the [.][in_stride] inputs; its answer goes to column q of out
+// (out_compact) or to the row's own column.  idx = null: item q is row q.
+hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, const float* w,
+                                  const float* norm, const float* params, const float* u0,
+                                  int64_t n, int64_t in_stride, const int64_t* idx,
+                                  int64_t idx_step, const unsigned long long* n_dev,
+                                  int out_compact, float* out, int64_t stride, int num_cu, int ns,
+                                  hipStream_t s) {
   if (n <= 0) return hipSuccess;
   FusedArgs a{};
   a.packed = packed;
@@ -349,6 +374,11 @@ hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const f
   a.out = out;
   a.n = n;
   a.stride = stride;
+  a.in_stride = in_stride;
+  a.idx = idx;
+  a.idx_step = idx_step;
+  a.n_dev = n_dev;
+  a.out_compact = out_compact;
   for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
   // ns = NS (one wave per SIMD, 4-wave blocks) or 10 + NS (two waves per
   // SIMD, 8-wave blocks)

@@ -24,6 +24,7 @@ using ens::fail;
 
 constexpr int kDims[5] = {4, 256, 256, 256, 48};
 constexpr int kBins = 28;  // rho bins of the audit / fallback rule
+static_assert(kBins <= 32, "audit_compare gathers a block's flagged bins in one word");
 constexpr float kAdamB1 = 0.9f, kAdamB2 = 0.999f, kAdamEps = 1e-8f;
 
 template <class T>
@@ -33,19 +34,37 @@ hipError_t alloc(T** p, int64_t count) {
 
 // ---- audit / fallback kernels ----------------------------------------------
 
-__device__ inline void wave_append(bool take, int64_t value, int64_t* list, int64_t cap,
-                                   unsigned long long* count) {
+// Append `value` to list[0, cap) where `take`, one atomic per block: the
+// waves' ballot counts are combined in LDS and thread 0 reserves the block's
+// slots, so a block's entries are contiguous and in thread order.  Every
+// thread of the block must call it.
+// With step -1 the entries are stored at list[0], list[-1], ... (a list
+// that grows from the back of a buffer whose last element `list` points to).
+template <int B>
+__device__ inline void block_append(bool take, int64_t value, int64_t* list, int64_t cap,
+                                    unsigned long long* count, int64_t step = 1) {
+  __shared__ unsigned int woff[B / 64];
+  __shared__ unsigned long long base;
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
   const unsigned long long m = __ballot(take);
-  if (m == 0ull) return;
-  const int lane = (int)(threadIdx.x & 63);
-  const int leader = __ffsll((long long)m) - 1;
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(m));
-  base = __shfl(base, leader);
+  if (lane == 0) woff[wave] = (unsigned int)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int tot = 0;
+    for (int w = 0; w < B / 64; ++w) {
+      const unsigned int c = woff[w];
+      woff[w] = tot;
+      tot += c;
+    }
+    base = tot ? atomicAdd(count, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
   const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t slot = (int64_t)base + __popcll(m & below);
-  if (take && slot < cap) list[slot] = value;
+  const int64_t slot = (int64_t)(base + woff[wave] + (unsigned long long)__popcll(m & below));
+  if (take && slot < cap) list[slot * step] = value;
 }
+
+constexpr int kSelBlock = 1024;  // threads per block of the selection kernels
 
 __device__ inline int rho_bin(float rho, const float* norm) {
   const float lo = norm[ens::kInLo], hi = norm[ens::kInHi];
@@ -64,8 +83,9 @@ __device__ inline bool in_box(const float* params, const float* u0, int64_t n, i
 }
 
 // Bernoulli(frac) audit draw per query from Philox4x32-10 (counter = query id).
-__global__ void select_audit(int64_t n, uint32_t thr, uint64_t seed, int64_t* list, int64_t cap,
-                             unsigned long long* count) {
+__global__ void __launch_bounds__(kSelBlock) select_audit(int64_t n, uint32_t thr, uint64_t seed,
+                                                          int64_t* list, int64_t cap,
+                                                          unsigned long long* count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool take = false;
   if (i < n) {
@@ -73,52 +93,79 @@ __global__ void select_audit(int64_t n, uint32_t thr, uint64_t seed, int64_t* li
                                               (uint32_t)seed, (uint32_t)(seed >> 32));
     take = r.x0 < thr;
   }
-  wave_append(take, i, list, cap, count);
+  block_append<kSelBlock>(take, i, list, cap, count);
 }
 
-// For each audited query: normwise error of the surrogate against the solver
-// answer (max over save times of ||surr - sol||_inf / ||sol||_inf); a bin
-// with any error above tol (or non-finite) is flagged; the solver answer is
-// returned for the audited query itself.
+// For each audited query k (list entry i): normwise error of the network's
+// answer net[.][k] against the solver's sol[.][k] (max over save times of
+// ||net - sol||_inf / ||sol||_inf); a bin with any error above tol (or
+// non-finite) is flagged; the solver answer goes to out[.][i].
 __global__ void audit_compare(const int64_t* list, const unsigned long long* count, int64_t cap,
-                              const float* sol, float* out, int64_t n, int n_save, int ncomp,
+                              const float* sol, const float* net, float* out, int64_t n,
+                              int n_save, int ncomp,
                               const float* params, const float* norm, float tol,
                               unsigned int* bins, uint8_t* used, unsigned int* max_err_bits) {
+  __shared__ unsigned int bmax, bflag;
+  if (threadIdx.x == 0) bmax = bflag = 0u;
+  __syncthreads();
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t cnt = (int64_t)(*count < (unsigned long long)cap ? *count : cap);
+  if (k < cnt) {
+    const int64_t i = list[k];
+    float err = 0.0f;
+    for (int j = 0; j < n_save; ++j) {
+      float num = 0.0f, den = 0.0f;
+      for (int c = 0; c < ncomp; ++c) {
+        const int64_t row = (int64_t)j * ncomp + c;
+        const float s = sol[row * cap + k];
+        const float g = net[row * cap + k];
+        num = fmaxf(num, fabsf(g - s));
+        den = fmaxf(den, fabsf(s));
+        out[row * n + i] = s;
+      }
+      const float e = num / den;
+      err = (e == e) ? fmaxf(err, e) : 3.0e38f;
+    }
+    if (!(err <= tol)) atomicOr(&bflag, 1u << rho_bin(params[n + i], norm));
+    if (used) used[i] = 1;
+    atomicMax(&bmax, __float_as_uint(err));  // err >= 0: the bits order as the floats
+  }
+  __syncthreads();  // one global update per block
+  if (threadIdx.x == 0) {
+    if (bmax) atomicMax(max_err_bits, bmax);
+    for (int b = 0; b < kBins; ++b)
+      if (bflag & (1u << b)) atomicOr(&bins[b], 1u);
+  }
+}
+
+// The queries left after the audit: to the solver (outside the training box
+// or in a flagged rho bin; flag 2, list front, count[0]) or to the network
+// (list back, count[1]).
+__global__ void __launch_bounds__(kSelBlock) select_split(int64_t n, const float* params,
+                                                          const float* u0, const float* norm,
+                                                          const unsigned int* bins,
+                                                          uint8_t* used, int64_t* list,
+                                                          unsigned long long* count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool fb = false, nw = false;
+  if (i < n && used[i] == 0) {
+    fb = !in_box(params, u0, n, i, norm) || bins[rho_bin(params[n + i], norm)] != 0u;
+    nw = !fb;
+    if (fb) used[i] = 2;
+  }
+  block_append<kSelBlock>(fb, i, list, n, count);
+  block_append<kSelBlock>(nw, i, list + (n - 1), n, count + 1, -1);
+}
+
+// net[row][k] = out[row][list[k]] for the first count[0] entries (rows of
+// 48 outputs, row strides cap and n).
+__global__ void gather_answers(const int64_t* list, const unsigned long long* count, int64_t cap,
+                               const float* out, int64_t n, float* net) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t cnt = (int64_t)(*count < (unsigned long long)cap ? *count : cap);
   if (k >= cnt) return;
   const int64_t i = list[k];
-  float err = 0.0f;
-  for (int j = 0; j < n_save; ++j) {
-    float num = 0.0f, den = 0.0f;
-    for (int c = 0; c < ncomp; ++c) {
-      const int64_t row = (int64_t)j * ncomp + c;
-      const float s = sol[row * cap + k];
-      const float g = out[row * n + i];
-      num = fmaxf(num, fabsf(g - s));
-      den = fmaxf(den, fabsf(s));
-      out[row * n + i] = s;
-    }
-    const float e = num / den;
-    err = (e == e) ? fmaxf(err, e) : 3.0e38f;
-  }
-  if (!(err <= tol)) atomicOr(&bins[rho_bin(params[n + i], norm)], 1u);
-  if (used) used[i] = 1;
-  atomicMax(max_err_bits, __float_as_uint(err));
-}
-
-// Queries that go to the solver: not audited, and outside the training box
-// or in a flagged rho bin.
-__global__ void select_fallback(int64_t n, const float* params, const float* u0,
-                                const float* norm, const unsigned int* bins, uint8_t* used,
-                                int64_t* list, unsigned long long* count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool take = false;
-  if (i < n && used[i] == 0) {
-    take = !in_box(params, u0, n, i, norm) || bins[rho_bin(params[n + i], norm)] != 0u;
-    if (take) used[i] = 2;
-  }
-  wave_append(take, i, list, n, count);
+  for (int row = 0; row < kDims[4]; ++row) net[row * cap + k] = out[row * n + i];
 }
 
 __global__ void zero_u8(uint8_t* p, int64_t n) {
@@ -143,6 +190,7 @@ __global__ void write_report(const unsigned long long* counts, const unsigned in
 }
 
 unsigned grid_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+unsigned sel_grid(int64_t n) { return (unsigned)((n + kSelBlock - 1) / kSelBlock); }
 
 }  // namespace
 
@@ -176,9 +224,10 @@ struct ens_surrogate {
   int64_t cap_n = 0, cap_audit = 0;
   int64_t* alist = nullptr;
   int64_t* flist = nullptr;
-  float* scratch = nullptr;
+  float* scratch = nullptr;  // the solver's answers for the audited queries
+  float* netans = nullptr;   // the network's answers for them
   uint8_t* used = nullptr;
-  unsigned long long* counts = nullptr;  // [0] audited, [1] fallback
+  unsigned long long* counts = nullptr;  // [0] audited, [1] fallback, [2] network
   unsigned int* words = nullptr;         // [0, kBins) bins, [kBins] max error bits
 };
 
@@ -188,7 +237,7 @@ void free_all(ens_surrogate* s) {
   void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
                 s->act[0], s->act[1], s->act[2], s->Y, s->T, s->gb[0], s->gb[1], s->gb[2],
                 s->gb[3], s->partial, s->wparts, s->bparts, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
-                s->scratch, s->used, s->counts, s->words};
+                s->scratch, s->netans, s->used, s->counts, s->words};
   for (void* p : ps)
     if (p) (void)hipFree(p);
 }
@@ -339,16 +388,18 @@ uint64_t gcd(uint64_t a, uint64_t b) {
 
 namespace {
 
-// Workspace of one audited solve: audit list, fallback list, the solver's
-// answers for the audited queries, per-query flags, the two list counters and
-// the bin flags (+ max error bits).  The model's own lazily grown buffers, or
-// views into the static workspace below.
+// Workspace of one audited solve: audit list, the split list (fallback
+// queries from the front, network queries from the back), the solver's and
+// the network's answers for the audited queries, per-query flags, the three
+// list counters and the bin flags (+ max error bits).  The model's own lazily
+// grown buffers, or views into the static workspace below.
 struct AuditWs {
   int64_t* alist;
   int64_t* flist;
   float* answers;
+  float* net;                  // network answers of the audited queries [48][cap_audit]
   uint8_t* used;
-  unsigned long long* counts;  // [0] audited, [1] fallback
+  unsigned long long* counts;  // [0] audited, [1] fallback, [2] network
   unsigned int* words;         // [0, kBins) bins, [kBins] max error bits
   int64_t cap_audit;
 };
@@ -381,18 +432,21 @@ int check_solve_args(ens_ctx* c, ens_surrogate* s, const float* params, const fl
 
 // ---- the static workspace of ens_surrogate_solve_static ---------------------
 // One copy per GPU, held until the process ends; every static call on a GPU
-// shares it.  Layout (bytes): fallback list int64 [Q], audit list int64 [A],
-// audited answers float [48][A], flags uint8 [Q], counters uint64 [2], bin
-// words uint32 [kBins + 1], with Q = ENS_STATIC_MAX_QUERIES, A = kStaticAudit.
+// shares it.  Layout (bytes): split list int64 [Q], audit list int64 [A],
+// audited answers of the solver and of the network float [48][A] each, flags
+// uint8 [Q], counters uint64 [3], bin words uint32 [kBins + 1], with
+// Q = ENS_STATIC_MAX_QUERIES, A = kStaticAudit.
 constexpr int64_t kStaticAudit = 40960;  // audit_frac up to 2% at the largest n
 constexpr int64_t kOffFlist = 0;
 constexpr int64_t kOffAlist = kOffFlist + 8 * ENS_STATIC_MAX_QUERIES;
 constexpr int64_t kOffAnswers = kOffAlist + 8 * kStaticAudit;
-constexpr int64_t kOffUsed = kOffAnswers + 4 * 48 * kStaticAudit;
+constexpr int64_t kOffNet = kOffAnswers + 4 * 48 * kStaticAudit;
+constexpr int64_t kOffUsed = kOffNet + 4 * 48 * kStaticAudit;
 constexpr int64_t kOffCounts = (kOffUsed + ENS_STATIC_MAX_QUERIES + 255) / 256 * 256;
-constexpr int64_t kOffWords = kOffCounts + 16;
+constexpr int64_t kOffWords = kOffCounts + 24;
 constexpr int64_t kScratchBytes = kOffWords + 4 * (kBins + 1);
-static_assert(kOffCounts % 8 == 0 && kOffAnswers % 4 == 0, "aligned counters and answers");
+static_assert(kOffCounts % 8 == 0 && kOffAnswers % 4 == 0 && kOffNet % 4 == 0,
+              "aligned counters and answers");
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
@@ -443,21 +497,35 @@ int audited_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, ws.words, kBins + 1);
   ENS_TRY(hipGetLastError());
   hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st,
-                     reinterpret_cast<unsigned int*>(ws.counts), 4);
+                     reinterpret_cast<unsigned int*>(ws.counts), 6);
   ENS_TRY(hipGetLastError());
 
-  // 1. surrogate answers for every query
-  int rc = predict(c, s, params, u0, n, out, st);
-  if (rc != ENS_OK) return rc;
-
-  // 2. audit sample: Bernoulli(audit_frac) per query
+  // 1. audit sample: Bernoulli(audit_frac) per query
   const double thr_d = std::floor(audit_frac * 4294967296.0);
   const uint32_t thr = thr_d >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)thr_d;
-  hipLaunchKernelGGL(select_audit, dim3(grid_of(n)), dim3(256), 0, st, n, thr, audit_seed,
+  hipLaunchKernelGGL(select_audit, dim3(sel_grid(n)), dim3(kSelBlock), 0, st, n, thr, audit_seed,
                      ws.alist, ws.cap_audit, ws.counts);
   ENS_TRY(hipGetLastError());
 
-  // 3. solve the audited queries (sorted-form Tsit5, FP32, count read on the device)
+  // 2. the network's answers for the audited queries (fused kernel: only
+  // those; tiled path: every query into out, the audited ones gathered)
+  const bool fused = c->mlp_tile != 0;
+  int rc = ENS_OK;
+  if (fused) {
+    ENS_TRY(ens::mlp_pack(s->wb, s->L, s->packed, st));
+    ENS_TRY(ens::mlp_forward_fused_list(s->L, s->packed, s->w, s->norm, params, u0,
+                                        ws.cap_audit, n, ws.alist, 1, ws.counts, 1, ws.net,
+                                        ws.cap_audit, c->num_cu, c->mlp_tile, st));
+  } else {
+    rc = predict(c, s, params, u0, n, out, st);
+    if (rc != ENS_OK) return rc;
+    hipLaunchKernelGGL(gather_answers, dim3(grid_of(ws.cap_audit)), dim3(256), 0, st, ws.alist,
+                       ws.counts, ws.cap_audit, out, n, ws.net);
+    ENS_TRY(hipGetLastError());
+  }
+
+  // 3. the solver's answers for the audited queries (sorted-form Tsit5, FP32,
+  // count read on the device)
   ens::LaunchArgs a{};
   a.n = ws.cap_audit;
   a.in_stride = n;
@@ -478,6 +546,7 @@ int audited_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float
   a.tspan_bcast = c->tspan_bcast;
   a.refill = c->refill;
   a.tpl = 1;
+  a.dense = c->save_mode == 1;  // the context's save mode, as in ens_solve
   for (int j = 0; j < n_save; ++j) a.theta[j] = save_times[j];
   const int saved_prec = c->precision;
   c->precision = 32;
@@ -492,16 +561,24 @@ int audited_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float
 
   // 4. compare, flag bins, return the solver's answer for audited queries
   hipLaunchKernelGGL(audit_compare, dim3(grid_of(ws.cap_audit)), dim3(256), 0, st, ws.alist,
-                     ws.counts, ws.cap_audit, ws.answers, out, n, n_save, 3, params, s->norm,
-                     (float)fallback_tol, ws.words, ws.used, ws.words + kBins);
+                     ws.counts, ws.cap_audit, ws.answers, ws.net, out, n, n_save, 3, params,
+                     s->norm, (float)fallback_tol, ws.words, ws.used, ws.words + kBins);
   ENS_TRY(hipGetLastError());
 
-  // 5. fallback set: outside the box or in a flagged bin
-  hipLaunchKernelGGL(select_fallback, dim3(grid_of(n)), dim3(256), 0, st, n, params, u0, s->norm,
-                     ws.words, ws.used, ws.flist, ws.counts + 1);
+  // 5. the rest: fallback set (outside the box or in a flagged bin) from the
+  // front of the split list, the network's queries from its back
+  hipLaunchKernelGGL(select_split, dim3(sel_grid(n)), dim3(kSelBlock), 0, st, n, params, u0,
+                     s->norm, ws.words, ws.used, ws.flist, ws.counts + 1);
   ENS_TRY(hipGetLastError());
 
-  // 6. solve them straight into out
+  // 6. the network answers its queries straight into out (already there on
+  // the tiled path)
+  if (fused)
+    ENS_TRY(ens::mlp_forward_fused_list(s->L, s->packed, s->w, s->norm, params, u0, n, n,
+                                        ws.flist + (n - 1), -1, ws.counts + 2, 0, out, n,
+                                        c->num_cu, c->mlp_tile, st));
+
+  // 7. the solver answers the fallback set straight into out
   a.n = n;
   a.out = out;
   a.out_stride = n;
@@ -541,7 +618,7 @@ int ens_surrogate_create(ens_ctx* c, uint64_t seed, ens_surrogate** out) {
             alloc(&s->packed, ens::mlp_packed_elems()) == hipSuccess &&
             alloc(&s->m, P) == hipSuccess && alloc(&s->v, P) == hipSuccess &&
             alloc(&s->grad, P) == hipSuccess && alloc(&s->norm, ens::kNormSize) == hipSuccess &&
-            alloc(&s->counts, 2) == hipSuccess && alloc(&s->words, kBins + 1) == hipSuccess;
+            alloc(&s->counts, 3) == hipSuccess && alloc(&s->words, kBins + 1) == hipSuccess;
   if (ok) ok = hipMemset(s->m, 0, sizeof(float) * P) == hipSuccess &&
                hipMemset(s->v, 0, sizeof(float) * P) == hipSuccess &&
                hipMemset(s->grad, 0, sizeof(float) * P) == hipSuccess;
@@ -779,21 +856,22 @@ int ens_surrogate_solve(ens_ctx* c, ens_surrogate* s, const float* params, const
   // workspace for n queries, grown on demand and kept by the model
   const int64_t cap_a = audit_capacity(audit_frac, n);
   if (n > s->cap_n || cap_a > s->cap_audit) {
-    void* old[] = {s->alist, s->flist, s->scratch, s->used};
+    void* old[] = {s->alist, s->flist, s->scratch, s->netans, s->used};
     for (void* p : old)
       if (p) (void)hipFree(p);
     s->alist = s->flist = nullptr;
-    s->scratch = nullptr;
+    s->scratch = s->netans = nullptr;
     s->used = nullptr;
     s->cap_n = s->cap_audit = 0;
     if (alloc(&s->alist, cap_a) != hipSuccess || alloc(&s->flist, n) != hipSuccess ||
-        alloc(&s->scratch, cap_a * kDims[4]) != hipSuccess || alloc(&s->used, n) != hipSuccess)
+        alloc(&s->scratch, cap_a * kDims[4]) != hipSuccess ||
+        alloc(&s->netans, cap_a * kDims[4]) != hipSuccess || alloc(&s->used, n) != hipSuccess)
       return fail(c, ENS_ENOMEM, "cannot allocate the audit workspace");
     s->cap_n = n;
     s->cap_audit = cap_a;
   }
-  AuditWs ws{s->alist, s->flist, s->scratch, used_solver ? used_solver : s->used, s->counts,
-             s->words, s->cap_audit};
+  AuditWs ws{s->alist, s->flist, s->scratch, s->netans, used_solver ? used_solver : s->used,
+             s->counts, s->words, s->cap_audit};
   return audited_solve(c, s, params, u0, tspan, abstol, reltol, save_times, n_save, n,
                        audit_frac, fallback_tol, audit_seed, out, report, ws,
                        static_cast<hipStream_t>(stream));
@@ -827,6 +905,7 @@ int ens_surrogate_solve_static(ens_ctx* c, ens_surrogate* s, const float* params
   AuditWs ws{reinterpret_cast<int64_t*>(base + kOffAlist),
              reinterpret_cast<int64_t*>(base + kOffFlist),
              reinterpret_cast<float*>(base + kOffAnswers),
+             reinterpret_cast<float*>(base + kOffNet),
              used_solver ? used_solver : base + kOffUsed,
              reinterpret_cast<unsigned long long*>(base + kOffCounts),
              reinterpret_cast<unsigned int*>(base + kOffWords), kStaticAudit};
