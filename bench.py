@@ -673,7 +673,7 @@ def config_variant(name, precision, steps, alg=""):
     return res
 
 
-def surrogate_variant(epochs, plain_ms_2p24):
+def surrogate_variant(epochs, plain_ms_2p24, headline_ms_2p24=None):
     """Learned surrogate (4 -> 256 -> 256 -> 256 -> 48, bf16 MFMA): trained on
     2^20 solver trajectories, then the audited solve of 2^24 fresh queries
     (1% audit by the FP32 solver, fallback where audited error > 1e-3) timed
@@ -698,6 +698,7 @@ def surrogate_variant(epochs, plain_ms_2p24):
     train_s = time.perf_counter() - t0
     scaling = train_batch_scaling(s, P, U, y)
     del P, U, T, y
+    s.set(save_mode=1)  # the audited solve's solver part saves as the headline does
     q = W.lorenz_fp32(seed=W.SEEDS["surr_query"])
     Pq, Uq, Tq = dev(q.params), dev(q.u0), dev(q.tspan)
     out = torch.empty((16, 3, q.n), dtype=torch.float32, device="cuda")
@@ -735,6 +736,8 @@ def surrogate_variant(epochs, plain_ms_2p24):
         res[f"audited_solve_tol_{tol:g}"] = {
             "ms": solve_ms, "traj_per_s": q.n / (solve_ms * 1e-3),
             "speedup_vs_plain": plain_ms_2p24 / solve_ms,
+            "speedup_vs_headline_solver": (headline_ms_2p24 / solve_ms
+                                           if headline_ms_2p24 else None),
             "audited": int(rep_h[0]), "fallback": int(rep_h[1]), "flagged_bins": int(rep_h[2]),
             "max_audit_err": float(rep_h[3]),
             "network_answered_frac": float((used_h == 0).mean()),
@@ -928,7 +931,8 @@ def main():
             variants["stiff_appendix_b1_8192"] = stiff_variant(args.steps)
             variants["mixed_systems_one_launch"] = mixed_variant(args.steps)
             if not args.no_surrogate:
-                variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms)
+                variants["surrogate"] = surrogate_variant(args.surrogate_epochs, plain_ms,
+                                                          ker_ms)
 
     res = {"metric": METRIC, "value": value, "unit": "trajectories/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
