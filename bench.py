@@ -747,8 +747,8 @@ def surrogate_variant(epochs, plain_ms_2p24, headline_ms_2p24=None):
 
 
 def surrogate_only(epochs, scaling=False):
-    """Training and inference of the surrogate alone, no audit: the workload
-    of the MFMA counter profiles."""
+    """Training and inference of the surrogate and one audited solve at
+    tolerance 1e-3: the workload of the MFMA counter and kernel profiles."""
     import torch
 
     import paper_2304_06835_amd as ens
@@ -768,8 +768,15 @@ def surrogate_only(epochs, scaling=False):
     Pq, Uq = dev(q.params), dev(q.u0)
     out = torch.empty((16, 3, q.n), dtype=torch.float32, device="cuda")
     _, pred_ms, _ = event_time(lambda: m.predict(Pq, Uq, out=out), 5, 2)
+    # the audited solve at tolerance 1e-3 (every bin fails its audit there)
+    s.set(save_mode=1)
+    Tq = dev(q.tspan)
+    _, audit_ms, _ = event_time(
+        lambda: m.solve(Pq, Uq, Tq, q.abstol, q.reltol, q.theta, audit_frac=0.01,
+                        fallback_tol=1e-3, audit_seed=W.SEEDS["surr_audit"], out=out), 3, 1)
     train_tf = MLP_TRAIN_FLOPS_PER_SAMPLE * (1 << 20) * epochs / train_s / 1e12
     print(json.dumps({"surrogate_only": {
+        "audited_solve_tol_0.001_ms": audit_ms,
         "train_epochs": epochs, "train_samples": 1 << 20, "train_seconds": train_s,
         "train_tflops": train_tf, "predict_ms": pred_ms, "queries": q.n,
         "predict_tflops": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12,
