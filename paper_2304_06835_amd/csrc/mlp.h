@@ -67,9 +67,11 @@ struct RowSet {
 
 hipError_t mlp_init(float* w, uint16_t* wb, const MlpLayout& L, uint64_t seed, hipStream_t s);
 hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s);
-hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, const MlpLayout& L,
-                    const GradParts& parts, float lr, float b1, float b2, float eps, float c1,
-                    float c2, hipStream_t s);
+// packed (may be null; the 4-256-256-256-48 network only) receives each
+// updated bf16 weight at its packed_pos as well.
+hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, uint16_t* packed,
+                    const MlpLayout& L, const GradParts& parts, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s);
 hipError_t mlp_gather(const float* params, const float* u0, const float* y, int64_t n, int64_t q0,
                       int64_t count, uint64_t mult, uint64_t add, const float* norm, uint16_t* a0,
                       float* T, int nout, hipStream_t s);
@@ -81,6 +83,41 @@ hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, c
 hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
                         MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                         double* partial, float* loss, hipStream_t s);
+
+// Fragment-major weights of the fused kernels (mlp_fused.hip), for the
+// 4 -> 256 -> 256 -> 256 -> 48 network only.  A fragment is 64 lanes x 8
+// bf16: the A operand of one 16 x 32 block of W_l for
+// v_mfma_f32_16x16x32_bf16; lane 16 g + r holds row r of the block and
+// k-slots 8 g .. 8 g + 7, slot 8 g + e holding column perm32(8 g + e) of the
+// 32-wide k-block.  Layer 1 (4 inputs) has one k-block, columns 0..3 in
+// group 0 and zeros elsewhere; layers 2, 3 have 16 x 8 fragments, layer 4
+// 3 x 8, each row block's k-blocks consecutive.
+constexpr int kPackFrag = 512;
+constexpr int64_t kPackL1 = 0;
+constexpr int64_t kPackL2 = kPackL1 + 16 * kPackFrag;
+constexpr int64_t kPackL3 = kPackL2 + 128 * kPackFrag;
+constexpr int64_t kPackL4 = kPackL3 + 128 * kPackFrag;
+constexpr int64_t kPackTotal = kPackL4 + 24 * kPackFrag;
+
+// Logical k-slot (0..31) -> feature inside a 32-wide k-block: lane group g
+// holds features 4g..4g+3 of the first 16-row accumulator tile and
+// 16+4g..16+4g+3 of the second, so one layer's accumulators are the next
+// layer's operands without a shuffle.
+__host__ __device__ constexpr int perm32(int k) {
+  return (k & 7) < 4 ? 4 * (k >> 3) + (k & 7) : 16 + 4 * (k >> 3) + (k & 7) - 4;
+}
+
+// Position of element (row, col) of layer l's W in the packed weights (the
+// inverse of the packing: feature j of a k-block sits in group (j & 15) / 4,
+// slot j & 3, plus 4 for the second half).
+__host__ __device__ inline int64_t packed_pos(int l, int row, int col) {
+  const int r16 = row & 15, rb = row >> 4;
+  if (l == 0) return kPackL1 + (int64_t)rb * kPackFrag + r16 * 8 + col;
+  const int j = col & 31, kb = col >> 5;
+  const int g = (j & 15) >> 2, e = (j < 16 ? 0 : 4) + (j & 3);
+  const int64_t base = l == 1 ? kPackL2 : (l == 2 ? kPackL3 : kPackL4);
+  return base + (int64_t)(rb * 8 + kb) * kPackFrag + (16 * g + r16) * 8 + e;
+}
 
 // Fused inference kernel (mlp_fused.hip): weights re-laid out fragment-major
 // by mlp_pack into a buffer of mlp_packed_elems() bf16 values.
@@ -95,5 +132,15 @@ hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, co
                                   int64_t idx_step, const unsigned long long* n_dev,
                                   int out_compact, float* out, int64_t stride, int num_cu, int ns,
                                   hipStream_t s);
+// Training forward of a minibatch in one launch: item b < B is trajectory
+// (mult * (first + b) + add) mod n of params / u0 [3][n] and y [48][n]; keeps
+// the normalised inputs a0 [B][4] bf16, Z_l [B][256] FP32 and A_l [B][256]
+// bf16 of the hidden layers, the normalised outputs Y [B][48] and targets
+// T [B][48] in the layouts mlp_forward / mlp_gather leave them.
+hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
+                             const float* norm, const float* params, const float* u0,
+                             const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
+                             uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
+                             hipStream_t s);
 
 }  // namespace ens

@@ -348,16 +348,20 @@ __global__ void to_bf16(const float* w, uint16_t* wb, int64_t n) {
 // Adam with bias correction c1 = 1/(1 - b1^t), c2 = 1/(1 - b2^t), on the
 // gradient summed here from the partials a backward pass left (fixed order:
 // split 0, 1, ... of a weight; row block 0, 1, ... of a bias); the sum is
-// also stored in g.
-__global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb, int64_t n,
-                          GradParts P, MlpLayout L, float lr, float b1, float b2, float eps,
-                          float c1, float c2) {
+// also stored in g.  A weight's new bf16 value also goes to its place in the
+// fused kernels' packed copy when `packed` is given.
+__global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
+                          uint16_t* packed, int64_t n, GradParts P, MlpLayout L, float lr,
+                          float b1, float b2, float eps, float c1, float c2) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   float gg = 0.0f;
+  int64_t pk = -1;
   for (int l = 0; l < L.layers; ++l) {
     const int64_t nw = (int64_t)L.dims[l] * L.dims[l + 1], nb = L.dims[l + 1];
     if (p >= L.w_off[l] && p < L.w_off[l] + nw) {
+      const int64_t e = p - L.w_off[l];
+      pk = packed_pos(l, (int)(e / L.dims[l]), (int)(e % L.dims[l]));
       const float* q = P.w[l] + (p - L.w_off[l]);
       float t[kSplits];  // all loads in flight, then the fixed-order sum
 #pragma unroll
@@ -385,7 +389,9 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb, 
   v[p] = vv;
   const float ww = w[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
   w[p] = ww;
-  wb[p] = f2bf(ww);
+  const uint16_t h = f2bf(ww);
+  wb[p] = h;
+  if (packed && pk >= 0) packed[pk] = h;
 }
 
 // Normalised network inputs of work items [q0, q0 + count): item b is
@@ -517,11 +523,11 @@ hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, const MlpLayout& L,
-                    const GradParts& parts, float lr, float b1, float b2, float eps, float c1,
-                    float c2, hipStream_t s) {
+hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, uint16_t* packed,
+                    const MlpLayout& L, const GradParts& parts, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s) {
   hipLaunchKernelGGL(adam_step, dim3((unsigned)((L.total + 255) / 256)), dim3(256), 0, s, w, m, v,
-                     g, wb, L.total, parts, L, lr, b1, b2, eps, c1, c2);
+                     g, wb, packed, L.total, parts, L, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 

@@ -31,13 +31,13 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kH = 256, kNO = 48;
-constexpr int kFrag = 512;  // bf16 elements of one fragment (64 lanes x 8)
-// packed fragment-major weights (bf16 elements)
-constexpr int64_t kP1 = 0;                  // layer 1: 16 row blocks
-constexpr int64_t kP2 = kP1 + 16 * kFrag;   // layer 2: 16 row blocks x 8 k-blocks
-constexpr int64_t kP3 = kP2 + 128 * kFrag;  // layer 3: same
-constexpr int64_t kP4 = kP3 + 128 * kFrag;  // layer 4: 3 row blocks x 8 k-blocks
-constexpr int64_t kPTotal = kP4 + 24 * kFrag;
+constexpr int kFrag = kPackFrag;  // bf16 elements of one fragment (64 lanes x 8)
+// packed fragment-major weights (bf16 elements), the layout of mlp.h
+constexpr int64_t kP1 = kPackL1;  // layer 1: 16 row blocks
+constexpr int64_t kP2 = kPackL2;  // layer 2: 16 row blocks x 8 k-blocks
+constexpr int64_t kP3 = kPackL3;  // layer 3: same
+constexpr int64_t kP4 = kPackL4;  // layer 4: 3 row blocks x 8 k-blocks
+constexpr int64_t kPTotal = kPackTotal;
 constexpr int kChunkBytes = 32 * kFrag * 2;  // 4 row blocks x 8 k-blocks
 
 // LDS map (bytes).  The ring comes first so that every fragment of either
@@ -53,13 +53,6 @@ static_assert(2 * kChunkBytes <= 65536, "ring fragments must be immediate offset
 constexpr int kBB1 = 0, kBB2 = 256, kBB3 = 512, kBB4 = 768, kBMean = 816, kBStd = 864,
               kBInMean = 912, kBInIStd = 916, kBCount = 920;
 constexpr int kLdsBytes = kLdsBias + kBCount * 4;
-
-// Logical k (0..31) of a lane's B-operand slot -> feature inside the 32-block:
-// lane group g holds features 4g..4g+3 of the first 16-row accumulator tile
-// and 16+4g..16+4g+3 of the second.
-__host__ __device__ constexpr int perm32(int k) {
-  return (k & 7) < 4 ? 4 * (k >> 3) + (k & 7) : 16 + 4 * (k >> 3) + (k & 7) - 4;
-}
 
 __global__ void pack_weights(const uint16_t* __restrict__ wb, MlpLayout L,
                              uint16_t* __restrict__ out) {
@@ -108,6 +101,18 @@ struct FusedArgs {
   const unsigned long long* n_dev;
   int out_compact;
   int64_t b_off[4];
+  // training launches: item q is row (mult * (first + q) + add) mod
+  // in_stride; they keep the inputs a0 [n][4], Z_l and A_l [n][256] of the
+  // hidden layers, Y [n][48] (normalised) and the targets T [n][48]
+  // normalised from y [48][in_stride]
+  const float* y;
+  uint64_t mult, add;
+  int64_t first;
+  uint16_t* a0;
+  float* z[3];
+  uint16_t* act[3];
+  float* Y;
+  float* T;
 };
 
 __device__ inline float silu(float z) {
@@ -153,7 +158,34 @@ __device__ inline void load_chunk(const uint16_t* src, uint8_t* slot, int wave, 
   }
 }
 
+// The per-block copies of the layer-1 and layer-4 fragments (40, contiguous
+// in LDS from kLdsW1), this wave's share, as direct global -> LDS loads: all
+// in flight at once rather than a register round trip each.
+template <int NW>
+__device__ inline void load_fixed(const uint16_t* packed, uint8_t* lds, int wave, int lane) {
+  static_assert(40 % NW == 0, "fragments per wave");
+  uint32_t voff = (uint32_t)lane * 16u;
+  asm volatile("" : "+v"(voff));
+  const int w = __builtin_amdgcn_readfirstlane(wave);
+  const char* base = reinterpret_cast<const char*>(packed);
+#pragma unroll
+  for (int j = 0; j < 40 / NW; ++j) {
+    const int fi = w * (40 / NW) + j;
+    const int64_t src = fi < 16 ? kP1 + (int64_t)fi * kFrag : kP4 + (int64_t)(fi - 16) * kFrag;
+    __builtin_amdgcn_global_load_lds(
+        reinterpret_cast<const void*>(base + src * 2 + voff),
+        (__attribute__((address_space(3))) void*)(lds + kLdsW1 + fi * kFrag * 2), 16, 0, 0);
+  }
+}
+
 __device__ inline void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Row of minibatch item b, (mult * b + add) mod n, for mult, add < n (the
+// host reduces them): 64-bit arithmetic while n <= 2^32, else 128-bit.
+__device__ inline int64_t affine_row(uint64_t mult, uint64_t add, uint64_t b, uint64_t n) {
+  if (n <= (1ull << 32)) return (int64_t)((mult * (b % n) + add) % n);
+  return (int64_t)(((unsigned __int128)mult * b + add) % n);
+}
 
 // Products of one pair of 16-row output blocks (rb, rb+1) of a 256 x 256
 // layer for every subtile, the accumulators starting from the bias.
@@ -337,6 +369,210 @@ mlp_fused_fwd(const FusedArgs a) {
   wait_vm();  // no global->LDS load may land after the block has left
 }
 
+// ---- training forward ------------------------------------------------------
+// A training minibatch is small (a few thousand items), so the inference
+// kernel's decomposition -- each wave takes whole queries through all 256
+// features, the weights staged once per block in LDS -- leaves most CUs idle
+// and each busy wave with a long serial chain of SiLU evaluations
+// (transcendentals at a quarter of the vector rate, one wave per SIMD).
+// Here a block takes 16 items and its four waves split every layer's
+// features: wave w computes rows 64 w .. 64 w + 63 (row blocks 4w .. 4w+3),
+// reading exactly those weight fragments (32 KiB of a hidden layer,
+// contiguous in the packed layout) straight from global memory into
+// registers, each fragment used once.  The activations are exchanged through
+// LDS, one barrier per layer; lane (g, col) writes the pair it produced and
+// reads back the eight pairs that are its next operands.  So a 4096-item
+// batch makes 256 blocks and each wave does a quarter of the serial work.
+// The kernel keeps what the backward pass reads: a0, Z_l and A_l of the
+// hidden layers, Y and the normalised targets T.
+
+// LDS: two activation buffers [pair K][lane] of 16 bytes (layer outputs
+// alternate between them), then the biases and normalisation.
+constexpr int kTAct = 8 * 64 * 16;
+constexpr int kTBias = 2 * kTAct;
+constexpr int kTB1 = 0, kTB2 = 256, kTB3 = 512, kTB4 = 768, kTOutMean = 816, kTOutIStd = 864,
+              kTInMean = 912, kTInIStd = 916, kTBCount = 920;
+constexpr int kTLdsBytes = kTBias + kTBCount * 4;
+
+__device__ inline bf16x8_t* act_slot(uint8_t* lds, int buf, int K, int lane) {
+  return reinterpret_cast<bf16x8_t*>(lds + buf * kTAct + (K * 64 + lane) * 16);
+}
+
+// One fragment of the packed weights, straight from global memory.
+__device__ inline bf16x8_t gfrag(const uint16_t* packed, int64_t frag_index, int lane) {
+  return *reinterpret_cast<const bf16x8_t*>(packed + frag_index * kFrag + lane * 8);
+}
+
+// Z and A of pair K (features 32 K + 4 g + {0..3} and 32 K + 16 + 4 g + {0..3})
+// into this lane's item rows (null: an item past the end of the batch).
+__device__ inline void keep_pair(f32x4_t z0, f32x4_t z1, bf16x8_t v, int K, int g, float* zrow,
+                                 uint16_t* arow) {
+  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+  if (!zrow) return;
+  float* zp = zrow + 32 * K + 4 * g;
+  *reinterpret_cast<f32x4_t*>(zp) = z0;
+  *reinterpret_cast<f32x4_t*>(zp + 16) = z1;
+  uint16_t* ap = arow + 32 * K + 4 * g;
+  *reinterpret_cast<bf16x4_t*>(ap) = bf16x4_t{v[0], v[1], v[2], v[3]};
+  *reinterpret_cast<bf16x4_t*>(ap + 16) = bf16x4_t{v[4], v[5], v[6], v[7]};
+}
+
+// This wave's 64 rows of a layer: four 16-row blocks, their SiLU into the
+// output buffer (pairs 2w, 2w+1) and Z / A into the item's rows.
+__device__ inline void train_rows(f32x4_t (&acc)[4], uint8_t* lds, int out_buf, int wave, int g,
+                                  int lane, float* zrow, uint16_t* arow) {
+#pragma unroll
+  for (int pp = 0; pp < 2; ++pp) {
+    const bf16x8_t v = silu_pack(acc[2 * pp], acc[2 * pp + 1]);
+    *act_slot(lds, out_buf, 2 * wave + pp, lane) = v;
+    keep_pair(acc[2 * pp], acc[2 * pp + 1], v, 2 * wave + pp, g, zrow, arow);
+  }
+}
+
+__global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kTLdsBytes];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, col = lane & 15;
+  const int64_t ns = a.in_stride;
+  const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
+  const bool live = q < a.n;
+  float* bw = reinterpret_cast<float*>(lds + kTBias);
+
+  // biases and normalisation first, so that their wait before the LDS
+  // stores does not wait for the loads issued after them
+  const float bh0 = a.w[a.b_off[0] + tid], bh1 = a.w[a.b_off[1] + tid],
+              bh2 = a.w[a.b_off[2] + tid];
+  float b4 = 0.f, om = 0.f, ois = 0.f, im = 0.f, iis = 0.f;
+  if (tid < kNO) {
+    b4 = a.w[a.b_off[3] + tid];
+    om = a.norm[kOutMean + tid];
+    ois = a.norm[kOutIStd + tid];
+  }
+  if (tid < 4) {
+    im = a.norm[kInMean + tid];
+    iis = a.norm[kInIStd + tid];
+  }
+  // the item's row, raw inputs (lane group 0) and, in waves 0..2, the four
+  // targets of outputs 16 w + 4 g + r this lane writes
+  int64_t row = 0;
+  float f[4] = {0.f, 0.f, 0.f, 0.f}, yt[4] = {0.f, 0.f, 0.f, 0.f};
+  if (live) {
+    row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
+    if (g == 0) {
+      f[0] = a.params[ns + row];
+      f[1] = a.u0[row];
+      f[2] = a.u0[ns + row];
+      f[3] = a.u0[2 * ns + row];
+    }
+    if (wave < 3) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+    }
+  }
+  // this wave's weights of layers 1 and 2
+  bf16x8_t w1[4], w[4][8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w1[j] = gfrag(a.packed, kP1 / kFrag + 4 * wave + j, lane);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+      w[j][kb] = gfrag(a.packed, kP2 / kFrag + (4 * wave + j) * 8 + kb, lane);
+  bw[kTB1 + tid] = bh0;
+  bw[kTB2 + tid] = bh1;
+  bw[kTB3 + tid] = bh2;
+  if (tid < kNO) {
+    bw[kTB4 + tid] = b4;
+    bw[kTOutMean + tid] = om;
+    bw[kTOutIStd + tid] = ois;
+  }
+  if (tid < 4) {
+    bw[kTInMean + tid] = im;
+    bw[kTInIStd + tid] = iis;
+  }
+  __syncthreads();
+  float* zrow[3];
+  uint16_t* arow[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    zrow[l] = live ? a.z[l] + q * kH : nullptr;
+    arow[l] = live ? a.act[l] + q * kH : nullptr;
+  }
+  const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+
+  // ---- layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane group 0
+  {
+    bf16x8_t xin;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float v = (g == 0 && live) ? (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k] : 0.f;
+      xin[k] = (__bf16)v;
+      xin[4 + k] = (__bf16)0.0f;
+    }
+    if (wave == 0 && g == 0 && live) {
+      typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+      *reinterpret_cast<bf16x4_t*>(a.a0 + q * 4) = bf16x4_t{xin[0], xin[1], xin[2], xin[3]};
+    }
+    f32x4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          w1[j], xin, *reinterpret_cast<const f32x4_t*>(bw + kTB1 + r0 + 16 * j), 0, 0, 0);
+    train_rows(acc, lds, 0, wave, g, lane, zrow[0], arow[0]);
+  }
+  __syncthreads();
+
+  // ---- layers 2 and 3
+  bf16x8_t x[8];
+#pragma unroll
+  for (int layer = 0; layer < 2; ++layer) {
+    const int in_buf = layer, out_buf = layer ^ 1;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, in_buf, kb, lane);
+    f32x4_t acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = *reinterpret_cast<const f32x4_t*>(bw + (layer ? kTB3 : kTB2) + r0 + 16 * j);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
+    if (layer == 0) {  // layer 3's rows, in flight while layer 2 finishes
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+          w[j][kb] = gfrag(a.packed, kP3 / kFrag + (4 * wave + j) * 8 + kb, lane);
+    } else if (wave < 3) {  // layer 4's row block `wave`
+#pragma unroll
+      for (int kb = 0; kb < 8; ++kb) w[0][kb] = gfrag(a.packed, kP4 / kFrag + wave * 8 + kb, lane);
+    }
+    train_rows(acc, lds, out_buf, wave, g, lane, zrow[layer + 1], arow[layer + 1]);
+    __syncthreads();
+  }
+
+  // ---- layer 4: waves 0..2 take output rows 16 w .. 16 w + 15: normalised
+  // outputs Y and targets T, [item][48]
+  if (wave < 3) {
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, 0, kb, lane);
+    const int o0 = 16 * wave + 4 * g;
+    f32x4_t out = *reinterpret_cast<const f32x4_t*>(bw + kTB4 + o0);
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][kb], x[kb], out, 0, 0, 0);
+    if (live) {
+      *reinterpret_cast<f32x4_t*>(a.Y + q * kNO + o0) = out;
+      f32x4_t t;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t[r] = (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
+      *reinterpret_cast<f32x4_t*>(a.T + q * kNO + o0) = t;
+    }
+  }
+}
+
 }  // namespace
 
 int64_t mlp_packed_elems() { return kPTotal; }
@@ -394,6 +630,42 @@ hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, co
     case 13: hipLaunchKernelGGL((mlp_fused_fwd<3, 8>), dim3(grid), blk, 0, s, a); break;
     default: hipLaunchKernelGGL((mlp_fused_fwd<4, 4>), dim3(grid), blk, 0, s, a); break;
   }
+  return hipGetLastError();
+}
+
+// The training forward: one block per 16 items.
+hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
+                             const float* norm, const float* params, const float* u0,
+                             const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
+                             uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
+                             hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
+      L.dims[3] != kH || L.dims[4] != kNO || n <= 0)
+    return hipErrorInvalidValue;
+  FusedArgs a{};
+  a.packed = packed;
+  a.w = w;
+  a.norm = norm;
+  a.params = params;
+  a.u0 = u0;
+  a.n = B;
+  a.in_stride = n;
+  a.y = y;
+  a.mult = mult % (uint64_t)n;
+  a.add = add % (uint64_t)n;
+  a.first = first;
+  a.a0 = a0;
+  for (int l = 0; l < 3; ++l) {
+    a.z[l] = acts.z[l];
+    a.act[l] = acts.act[l];
+  }
+  a.Y = Y;
+  a.T = T;
+  for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
+  const int64_t blocks = (B + 15) / 16;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp_train_fwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -199,7 +199,9 @@ struct ens_surrogate {
   ens::MlpLayout L{};
   float* w = nullptr;
   uint16_t* wb = nullptr;
-  uint16_t* packed = nullptr;  // fragment-major copy of wb for the fused kernel
+  // fragment-major copy of wb for the fused kernels, rewritten by every writer
+  // of wb (create, copy, load, Adam) so it never goes stale
+  uint16_t* packed = nullptr;
   float* m = nullptr;
   float* v = nullptr;
   float* grad = nullptr;
@@ -312,11 +314,9 @@ int check_model(ens_ctx* c, ens_surrogate* s) {
 
 int predict(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0, int64_t n,
             float* out, hipStream_t st) {
-  if (c->mlp_tile != 0) {  // fused kernel on weights re-packed from the current bf16 copy
-    hipError_t e = ens::mlp_pack(s->wb, s->L, s->packed, st);
-    if (e == hipSuccess)
-      e = ens::mlp_forward_fused(s->L, s->packed, s->w, s->norm, params, u0, n, out, n, c->num_cu,
-                                 c->mlp_tile, st);
+  if (c->mlp_tile != 0) {  // fused kernel on the packed copy of the bf16 weights
+    hipError_t e = ens::mlp_forward_fused(s->L, s->packed, s->w, s->norm, params, u0, n, out, n,
+                                          c->num_cu, c->mlp_tile, st);
     if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate forward: %s", hipGetErrorString(e));
     return ENS_OK;
   }
@@ -350,10 +350,15 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     acts.act[l] = s->act[l];
   }
   for (int l = 0; l < 4; ++l) acts.gb[l] = s->gb[l];
-  hipError_t e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T,
-                                 kDims[4], st);
-  if (e == hipSuccess)
-    e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->a0, B, acts, s->Y, nullptr, 0, 0, st);
+  hipError_t e;
+  if (c->mlp_tile != 0) {  // minibatch gather and forward in one launch
+    e = ens::mlp_forward_train(s->packed, s->w, s->L, s->norm, params, u0, y, n, first, B, mult,
+                               add, s->a0, acts, s->Y, s->T, st);
+  } else {
+    e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T, kDims[4], st);
+    if (e == hipSuccess)
+      e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->a0, B, acts, s->Y, nullptr, 0, 0, st);
+  }
   ens::GradParts parts = grad_parts(s, B);
   if (e == hipSuccess)
     e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, parts, s->partial, loss, st);
@@ -361,8 +366,8 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     s->step += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)kAdamB1, (double)s->step));
     const double c2 = 1.0 / (1.0 - std::pow((double)kAdamB2, (double)s->step));
-    e = ens::mlp_adam(s->w, s->m, s->v, s->grad, s->wb, s->L, parts, (float)lr, kAdamB1, kAdamB2,
-                      kAdamEps, (float)c1, (float)c2, st);
+    e = ens::mlp_adam(s->w, s->m, s->v, s->grad, s->wb, s->packed, s->L, parts, (float)lr,
+                      kAdamB1, kAdamB2, kAdamEps, (float)c1, (float)c2, st);
   }
   if (e != hipSuccess) return fail(c, ENS_EDEVICE, "surrogate train step: %s", hipGetErrorString(e));
   return ENS_OK;
@@ -512,7 +517,6 @@ int audited_solve(ens_ctx* c, ens_surrogate* s, const float* params, const float
   const bool fused = c->mlp_tile != 0;
   int rc = ENS_OK;
   if (fused) {
-    ENS_TRY(ens::mlp_pack(s->wb, s->L, s->packed, st));
     ENS_TRY(ens::mlp_forward_fused_list(s->L, s->packed, s->w, s->norm, params, u0,
                                         ws.cap_audit, n, ws.alist, 1, ws.counts, 1, ws.net,
                                         ws.cap_audit, c->num_cu, c->mlp_tile, st));
@@ -635,6 +639,7 @@ int ens_surrogate_create(ens_ctx* c, uint64_t seed, ens_surrogate** out) {
     ok = hipMemcpy(s->norm, nh, sizeof nh, hipMemcpyHostToDevice) == hipSuccess;
   }
   if (ok) ok = ens::mlp_init(s->w, s->wb, s->L, seed, nullptr) == hipSuccess &&
+               ens::mlp_pack(s->wb, s->L, s->packed, nullptr) == hipSuccess &&
                hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     free_all(s);
@@ -677,6 +682,8 @@ int ens_surrogate_copy(ens_ctx* c, ens_surrogate* s, int which, void* p, int to_
                           : hipMemcpyAsync(p, buf, bytes, hipMemcpyDeviceToDevice, st);
   if (e == hipSuccess && to_model && which == ENS_SURR_MASTER)
     e = ens::mlp_to_bf16(s->w, s->wb, s->L.total, st);
+  if (e == hipSuccess && to_model && (which == ENS_SURR_MASTER || which == ENS_SURR_WEIGHTS_BF16))
+    e = ens::mlp_pack(s->wb, s->L, s->packed, st);
   return e == hipSuccess ? ENS_OK : fail(c, ENS_EDEVICE, "%s", hipGetErrorString(e));
 }
 
@@ -749,6 +756,7 @@ int ens_surrogate_load(ens_ctx* c, ens_surrogate* s, const char* path) {
        hipMemcpy(s->v, h + 2 * P, sizeof(float) * P, hipMemcpyHostToDevice) == hipSuccess &&
        hipMemcpy(s->norm, h + 3 * P, sizeof(float) * nn, hipMemcpyHostToDevice) == hipSuccess &&
        ens::mlp_to_bf16(s->w, s->wb, s->L.total, nullptr) == hipSuccess &&
+       ens::mlp_pack(s->wb, s->L, s->packed, nullptr) == hipSuccess &&
        hipDeviceSynchronize() == hipSuccess;
   std::free(h);
   if (!ok) return fail(c, ENS_EDEVICE, "cannot write the model to the device");

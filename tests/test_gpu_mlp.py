@@ -127,27 +127,34 @@ def test_fused_forward_matches_tiled_path_across_many_tiles(ens, tile):
     assert np.abs(g - Y).max() / np.abs(Y).max() <= FWD_BAR
 
 
-@pytest.mark.parametrize("B", [777, 65])
-def test_gradient_and_adam_match_oracle(ens, B):
+@pytest.mark.parametrize("tile", [13, 0])
+@pytest.mark.parametrize("B,N,mult,add", [(777, 1500, 1, 0), (65, 1500, 1, 0),
+                                          (4096, 1 << 18, 100003, 12345)])
+def test_gradient_and_adam_match_oracle(ens, B, N, mult, add, tile):
     """One training step: loss, every gradient element (B = 777: twelve
     64-sample tiles and a 9-sample tail; B = 65: one tile and a 1-sample
     tail, so the edge handling of the products and of the split-K weight
-    gradients is pinned), and Adam's update from the GPU's own gradient."""
+    gradients is pinned; B = 4096: the training minibatch, drawn by an
+    affine permutation of 2^18 trajectories), and Adam's update from the
+    GPU's own gradient.  tile 13: the minibatch gather and forward pass in
+    one fused launch; 0: the gather kernel and layer-by-layer products."""
     th = random_theta(2, scale=0.5)
-    e = W.lorenz_fp32(N=1500, seed=12)
+    e = W.lorenz_fp32(N=N, seed=12)
     rng = np.random.default_rng(3)
     y = rng.normal(0, 1, (48, e.n)).astype(np.float32)
-    banner(f"mlp gradient B={B}")
+    banner(f"mlp gradient B={B} n={N} tile={tile}")
     s, m = make_model(ens, th)
+    s.set(mlp_tile=tile)
     P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
     import torch
     loss = torch.zeros(1, device="cuda")
     lr = 0.01
-    m.train_step(P, U, Y, first=0, batch=B, mult=1, add=0, lr=lr, loss=loss)
+    m.train_step(P, U, Y, first=0, batch=B, mult=mult, add=add, lr=lr, loss=loss)
     g = to_host(m.buffer("grad")).astype(np.float64)
     w1 = to_host(m.buffer("master")).astype(np.float64)
-    X = features(e.params, e.u0)[:B]
-    T = y[:, :B].T.astype(np.float64)
+    idx = (mult * np.arange(B, dtype=np.int64) + add) % N
+    X = features(e.params, e.u0)[idx]
+    T = y[:, idx].T.astype(np.float64)
     L, go, _ = mlp.loss_and_grad(th, X, T, bf16=True)
     print("loss gpu %.6f oracle %.6f" % (loss.item(), L))
     assert abs(loss.item() - L) <= 1e-3 * L
@@ -200,6 +207,29 @@ def test_save_load_round_trip_and_resume(ens, tmp_path):
     with pytest.raises(ens.EnsError, match="not a surrogate file"):
         m2.load_file(bad)
     assert np.array_equal(to_host(m2.buffer("master")), before) and m2.step == 3
+    torch.cuda.synchronize()
+
+
+def test_packed_weights_follow_every_update(ens):
+    """The fused kernels read a fragment-major copy of the bf16 weights that
+    Adam rewrites in place: after training steps, predictions from it are
+    bit-identical to those after re-deriving the copy from the master
+    weights, and agree with the layer-by-layer path on the bf16 weights."""
+    import torch
+    banner("packed weights after Adam")
+    e = W.lorenz_fp32(N=4096, seed=16)
+    y = np.random.default_rng(9).normal(0, 1, (48, e.n)).astype(np.float32)
+    P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
+    s, m = make_model(ens, random_theta(7, scale=0.5))
+    m.fit_norm(P, U, Y)
+    for k in range(3):
+        m.train_step(P, U, Y, first=1024 * k, batch=1024, mult=3, add=1, lr=3e-3)
+    after_adam = to_host(m.predict(P, U))
+    m.load("master", m.buffer("master"))   # re-derives bf16 weights and the packed copy
+    assert np.array_equal(bits(after_adam), bits(to_host(m.predict(P, U))))
+    s.set(mlp_tile=0)
+    tiled = to_host(m.predict(P, U))
+    assert np.abs(after_adam - tiled).max() / np.abs(tiled).max() <= FWD_BAR
     torch.cuda.synchronize()
 
 
