@@ -68,7 +68,8 @@ struct RowSet {
 hipError_t mlp_init(float* w, uint16_t* wb, const MlpLayout& L, uint64_t seed, hipStream_t s);
 hipError_t mlp_to_bf16(const float* w, uint16_t* wb, int64_t n, hipStream_t s);
 // packed (may be null; the 4-256-256-256-48 network only) receives each
-// updated bf16 weight at its packed_pos as well.
+// updated bf16 weight at its packed_pos, and those of layers 2..4 at their
+// packed_pos_t as well.
 hipError_t mlp_adam(float* w, float* m, float* v, float* g, uint16_t* wb, uint16_t* packed,
                     const MlpLayout& L, const GradParts& parts, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
@@ -83,6 +84,23 @@ hipError_t mlp_forward(const MlpLayout& L, const uint16_t* wb, const float* w, c
 hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* a0, int64_t B,
                         MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                         double* partial, float* loss, hipStream_t s);
+// The split-K weight-gradient partials of every layer (the last launch of
+// mlp_backward), from acts.gb and the kept activations.
+hipError_t mlp_weight_grads(const MlpLayout& L, const uint16_t* a0, int64_t B, MlpActs& acts,
+                            GradParts& parts, hipStream_t s);
+// *loss = factor * sum(partial[0 .. count)), one block, fixed order.
+hipError_t mlp_loss_sum(const double* partial, int64_t count, double factor, float* loss,
+                        hipStream_t s);
+// Fused backward of a minibatch whose forward pass mlp_forward_train kept
+// in acts / Y / T (4-256-256-256-48 network, packed weights with the
+// transposed part): the output gradient, the loss partials (partial [nb],
+// nb = ceil(B / 16) blocks of 16 items) and the input gradients of layers
+// 3..1 into acts.gb, with the bias-gradient partials of every layer in
+// parts.b ([nb][width]; parts.tiles = nb).  The weight gradients follow with
+// mlp_weight_grads.
+hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_t B,
+                              MlpActs& acts, const float* Y, const float* T, GradParts& parts,
+                              double* partial, hipStream_t s);
 
 // Fragment-major weights of the fused kernels (mlp_fused.hip), for the
 // 4 -> 256 -> 256 -> 256 -> 48 network only.  A fragment is 64 lanes x 8
@@ -119,8 +137,28 @@ __host__ __device__ inline int64_t packed_pos(int l, int row, int col) {
   return base + (int64_t)(rb * 8 + kb) * kPackFrag + (16 * g + r16) * 8 + e;
 }
 
+// The fused backward pass reads W_l^T (l = 2, 3, 4) packed the same way
+// after them: rows = the layer's 256 inputs, k = its outputs (perm32 order
+// inside each 32-wide block; layer 4's 48 outputs zero-padded to two blocks).
+constexpr int64_t kPackT2 = kPackTotal;                 // 16 row blocks x 8 k-blocks
+constexpr int64_t kPackT3 = kPackT2 + 128 * kPackFrag;  // same
+constexpr int64_t kPackT4 = kPackT3 + 128 * kPackFrag;  // 16 row blocks x 2 k-blocks
+constexpr int64_t kPackAll = kPackT4 + 32 * kPackFrag;
+
+// Position of element (row, col) of W_l (l = 1, 2, 3: the second to fourth
+// layers) in the transposed copy, i.e. of element (col, row) of W_l^T.
+__host__ __device__ inline int64_t packed_pos_t(int l, int row, int col) {
+  const int r16 = col & 15, rb = col >> 4;
+  const int j = row & 31, kb = row >> 5;
+  const int g = (j & 15) >> 2, e = (j < 16 ? 0 : 4) + (j & 3);
+  const int nkb = l == 3 ? 2 : 8;
+  const int64_t base = l == 1 ? kPackT2 : (l == 2 ? kPackT3 : kPackT4);
+  return base + (int64_t)(rb * nkb + kb) * kPackFrag + (16 * g + r16) * 8 + e;
+}
+
 // Fused inference kernel (mlp_fused.hip): weights re-laid out fragment-major
-// by mlp_pack into a buffer of mlp_packed_elems() bf16 values.
+// by mlp_pack into a buffer of mlp_packed_elems() bf16 values (the forward
+// layout, then the transposed one).
 int64_t mlp_packed_elems();
 hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hipStream_t s);
 hipError_t mlp_forward_fused(const MlpLayout& L, const uint16_t* packed, const float* w,

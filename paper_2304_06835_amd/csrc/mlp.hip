@@ -356,12 +356,14 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   float gg = 0.0f;
-  int64_t pk = -1;
+  int64_t pk = -1, pt = -1;
   for (int l = 0; l < L.layers; ++l) {
     const int64_t nw = (int64_t)L.dims[l] * L.dims[l + 1], nb = L.dims[l + 1];
     if (p >= L.w_off[l] && p < L.w_off[l] + nw) {
       const int64_t e = p - L.w_off[l];
-      pk = packed_pos(l, (int)(e / L.dims[l]), (int)(e % L.dims[l]));
+      const int row = (int)(e / L.dims[l]), col = (int)(e % L.dims[l]);
+      pk = packed_pos(l, row, col);
+      if (l > 0) pt = packed_pos_t(l, row, col);
       const float* q = P.w[l] + (p - L.w_off[l]);
       float t[kSplits];  // all loads in flight, then the fixed-order sum
 #pragma unroll
@@ -372,7 +374,14 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
     } else if (p >= L.b_off[l] && p < L.b_off[l] + nb) {
       const float* q = P.b[l] + (p - L.b_off[l]);
       int t = 0;
-      for (; t + 16 <= P.tiles; t += 16) {  // 16 loads in flight per round, summed in order
+      for (; t + 64 <= P.tiles; t += 64) {  // 64 loads in flight per round, summed in order
+        float u[64];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) u[j] = q[(int64_t)(t + j) * nb];
+#pragma unroll
+        for (int j = 0; j < 64; ++j) gg += u[j];
+      }
+      for (; t + 16 <= P.tiles; t += 16) {
         float u[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) u[j] = q[(int64_t)(t + j) * nb];
@@ -392,6 +401,7 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
   const uint16_t h = f2bf(ww);
   wb[p] = h;
   if (packed && pk >= 0) packed[pk] = h;
+  if (packed && pt >= 0) packed[pt] = h;
 }
 
 // Normalised network inputs of work items [q0, q0 + count): item b is
@@ -609,7 +619,20 @@ hipError_t mlp_backward(const MlpLayout& L, const uint16_t* wb, const uint16_t* 
                            EpiBack{acts.z[l - 1], acts.gb[l - 1], nin, parts.b[l - 1]}, s);
     if (e != hipSuccess) return e;
   }
-  // dW_l [no][nin] = G_l^T [no x B] . A_{l-1} [B x nin], K = B in kSplits ranges
+  return mlp_weight_grads(L, a0, B, acts, parts, s);
+}
+
+hipError_t mlp_loss_sum(const double* partial, int64_t count, double factor, float* loss,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(finish_sum, dim3(1), dim3(256), 0, s, partial, count, factor, loss);
+  return hipGetLastError();
+}
+
+// dW_l [no][nin] = G_l^T [no x B] . A_{l-1} [B x nin], K = B in kSplits
+// ranges, every layer in one grouped launch.
+hipError_t mlp_weight_grads(const MlpLayout& L, const uint16_t* a0, int64_t B, MlpActs& acts,
+                            GradParts& parts, hipStream_t s) {
+  const int nl = L.layers;
   GemmGroup G{};
   G.count = nl;
   int64_t blocks = 0;

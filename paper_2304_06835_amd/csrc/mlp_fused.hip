@@ -37,7 +37,6 @@ constexpr int64_t kP1 = kPackL1;  // layer 1: 16 row blocks
 constexpr int64_t kP2 = kPackL2;  // layer 2: 16 row blocks x 8 k-blocks
 constexpr int64_t kP3 = kPackL3;  // layer 3: same
 constexpr int64_t kP4 = kPackL4;  // layer 4: 3 row blocks x 8 k-blocks
-constexpr int64_t kPTotal = kPackTotal;
 constexpr int kChunkBytes = 32 * kFrag * 2;  // 4 row blocks x 8 k-blocks
 
 // LDS map (bytes).  The ring comes first so that every fragment of either
@@ -57,12 +56,19 @@ constexpr int kLdsBytes = kLdsBias + kBCount * 4;
 __global__ void pack_weights(const uint16_t* __restrict__ wb, MlpLayout L,
                              uint16_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= kPTotal) return;
+  if (i >= kPackAll) return;
   const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
   const int64_t f = i >> 9;
   const int r16 = lane & 15, g = lane >> 4;
   uint16_t v = 0;
-  if (i < kP2) {  // A operand of layer 1: row 16f + r16, k = 8g + e (< 4 real)
+  if (i >= kPackT2) {  // W_l^T of layers 2..4: row = input 16 rb + r16, k = output
+    const int layer = i < kPackT3 ? 1 : (i < kPackT4 ? 2 : 3);
+    const int nkb = layer == 3 ? 2 : 8;
+    const int64_t ff = f - (layer == 1 ? kPackT2 : (layer == 2 ? kPackT3 : kPackT4)) / kFrag;
+    const int rb = (int)(ff / nkb), kb = (int)(ff % nkb);
+    const int in = 16 * rb + r16, o = 32 * kb + perm32(8 * g + e);
+    if (o < L.dims[layer + 1]) v = wb[L.w_off[layer] + (int64_t)o * kH + in];
+  } else if (i < kP2) {  // A operand of layer 1: row 16f + r16, k = 8g + e (< 4 real)
     const int row = 16 * (int)f + r16, k = 8 * g + e;
     if (k < 4) v = wb[L.w_off[0] + row * 4 + k];
   } else {
@@ -573,12 +579,212 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
   }
 }
 
+// ---- training backward -----------------------------------------------------
+// The same decomposition for the input gradients: a block takes 16 items,
+// wave w computes features 64 w .. 64 w + 63 of G_3, G_2 and G_1 from the
+// transposed weights (its 64 rows of W_l^T, contiguous in the packed copy,
+// straight into registers) and the previous gradient's eight k-blocks, read
+// back from LDS after one barrier per layer.  Each G is scaled by SiLU' of
+// the kept pre-activation, rounded to bf16 for the weight-gradient products
+// and the next layer, and summed over the block's 16 items (butterfly over
+// the lane group, FP32) into the bias-gradient partial of the block.  The
+// output gradient G_4 = scale (Y - T) and the loss partial (FP64) come from
+// the kept Y and T.
+struct BwdArgs {
+  const uint16_t* packed;
+  const float* Y;  // [n][48]
+  const float* T;  // [n][48]
+  const float* z[3];
+  uint16_t* gb[4];     // G_l [n][width] bf16
+  float* bpart[4];     // [blocks][width]
+  double* partial;     // [blocks]
+  int64_t n;
+  float scale;
+};
+
+__device__ inline float dsilu(float z) {
+  const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// Sum over the 16 lanes of a lane group (the block's 16 items), butterfly.
+__device__ inline float sum16(float v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+// G = acc * silu'(Z) for this wave's 64 features (row blocks 4w + j): bf16
+// pairs into LDS (out_buf >= 0), bf16 into the item's row of gb (null: an
+// item past the end), the FP32 column sums into the block's partial row.
+__device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4], uint8_t* lds,
+                                int out_buf, int wave, int g, int col, int lane, int r0,
+                                uint16_t* grow, float* bp) {
+  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+  f32x4_t G[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) G[j][r] = acc[j][r] * dsilu(zv[j][r]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const bf16x4_t h = bf16x4_t{(__bf16)G[j][0], (__bf16)G[j][1], (__bf16)G[j][2], (__bf16)G[j][3]};
+    if (grow) *reinterpret_cast<bf16x4_t*>(grow + r0 + 16 * j) = h;
+  }
+  if (out_buf >= 0) {
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      bf16x8_t v;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = (__bf16)G[2 * pp][r];
+        v[4 + r] = (__bf16)G[2 * pp + 1][r];
+      }
+      *act_slot(lds, out_buf, 2 * wave + pp, lane) = v;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float t = sum16(G[j][r]);
+      if (col == 0) bp[r0 + 16 * j + r] = t;
+    }
+}
+
+__global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kTAct];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, col = lane & 15;
+  const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
+  const bool live = q < a.n;
+  const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+
+  // the output gradient's operands (outputs 16 h + 4 g + r), the kept
+  // pre-activations of this wave's features, the transposed weights of
+  // layers 4 and 3
+  f32x4_t yv[3], tv[3], zv[3][4];
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    yv[h] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    tv[h] = yv[h];
+  }
+#pragma unroll
+  for (int l = 0; l < 3; ++l)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) zv[l][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  if (live) {
+#pragma unroll
+    for (int h = 0; h < 3; ++h) {
+      yv[h] = *reinterpret_cast<const f32x4_t*>(a.Y + q * kNO + 16 * h + 4 * g);
+      tv[h] = *reinterpret_cast<const f32x4_t*>(a.T + q * kNO + 16 * h + 4 * g);
+    }
+#pragma unroll
+    for (int l = 2; l >= 0; --l)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        zv[l][j] = *reinterpret_cast<const f32x4_t*>(a.z[l] + q * kH + r0 + 16 * j);
+  }
+  bf16x8_t w4[4][2], w[4][8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) w4[j][kb] = gfrag(a.packed, kPackT4 / kFrag + (4 * wave + j) * 2 + kb, lane);
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+      w[j][kb] = gfrag(a.packed, kPackT3 / kFrag + (4 * wave + j) * 8 + kb, lane);
+
+  // ---- G_4 = scale (Y - T): k-blocks 0 (outputs 0..31) and 1 (32..47, zero
+  // padded) of the first product, the loss and the output bias partial
+  float gv[12];
+  double d2 = 0.0;
+#pragma unroll
+  for (int h = 0; h < 3; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float d = yv[h][r] - tv[h][r];
+      gv[4 * h + r] = a.scale * d;
+      d2 += (double)d * d;
+    }
+  bf16x8_t x4[2];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    x4[0][e] = (__bf16)gv[e];
+    x4[1][e] = e < 4 ? (__bf16)gv[8 + e] : (__bf16)0.0f;
+  }
+  if (wave == 0) {
+    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+    if (live) {
+#pragma unroll
+      for (int h = 0; h < 3; ++h)
+        *reinterpret_cast<bf16x4_t*>(a.gb[3] + q * kNO + 16 * h + 4 * g) =
+            bf16x4_t{(__bf16)gv[4 * h], (__bf16)gv[4 * h + 1], (__bf16)gv[4 * h + 2],
+                     (__bf16)gv[4 * h + 3]};
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) d2 += __shfl_xor(d2, m);
+    if (lane == 0) a.partial[blockIdx.x] = d2;
+    float* bp = a.bpart[3] + (int64_t)blockIdx.x * kNO;
+#pragma unroll
+    for (int h = 0; h < 3; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float t = sum16(gv[4 * h + r]);
+        if (col == 0) bp[16 * h + 4 * g + r] = t;
+      }
+  }
+
+  // ---- G_3 = (G_4 W_4) * silu'(Z_3), K = 48
+  f32x4_t acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[j][kb], x4[kb], acc[j], 0, 0, 0);
+  }
+  bwd_rows(acc, zv[2], lds, 0, wave, g, col, lane, r0, live ? a.gb[2] + q * kH : nullptr,
+           a.bpart[2] + (int64_t)blockIdx.x * kH);
+  __syncthreads();
+
+  // ---- G_2 = (G_3 W_3) * silu'(Z_2), then G_1 = (G_2 W_2) * silu'(Z_1)
+  bf16x8_t x[8];
+#pragma unroll
+  for (int step = 0; step < 2; ++step) {
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, step, kb, lane);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
+    if (step == 0) {  // W_2^T, in flight while G_2 is finished
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb)
+          w[j][kb] = gfrag(a.packed, kPackT2 / kFrag + (4 * wave + j) * 8 + kb, lane);
+    }
+    const int l = 1 - step;  // G_2 (gb[1], Z_2) then G_1 (gb[0], Z_1)
+    bwd_rows(acc, zv[l], lds, step == 0 ? 1 : -1, wave, g, col, lane, r0,
+             live ? a.gb[l] + q * kH : nullptr, a.bpart[l] + (int64_t)blockIdx.x * kH);
+    if (step == 0) __syncthreads();
+  }
+}
+
 }  // namespace
 
-int64_t mlp_packed_elems() { return kPTotal; }
+int64_t mlp_packed_elems() { return kPackAll; }
 
 hipError_t mlp_pack(const uint16_t* wb, const MlpLayout& L, uint16_t* packed, hipStream_t s) {
-  hipLaunchKernelGGL(pack_weights, dim3((unsigned)((kPTotal + 255) / 256)), dim3(256), 0, s, wb,
+  hipLaunchKernelGGL(pack_weights, dim3((unsigned)((kPackAll + 255) / 256)), dim3(256), 0, s, wb,
                      L, packed);
   return hipGetLastError();
 }
@@ -666,6 +872,33 @@ hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLa
   const int64_t blocks = (B + 15) / 16;
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mlp_train_fwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// The training backward: one block per 16 items, as the forward.
+hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_t B,
+                              MlpActs& acts, const float* Y, const float* T, GradParts& parts,
+                              double* partial, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
+      L.dims[3] != kH || L.dims[4] != kNO)
+    return hipErrorInvalidValue;
+  const int64_t blocks = (B + 15) / 16;
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  parts.tiles = (int)blocks;
+  BwdArgs a{};
+  a.packed = packed;
+  a.Y = Y;
+  a.T = T;
+  for (int l = 0; l < 3; ++l) a.z[l] = acts.z[l];
+  for (int l = 0; l < 4; ++l) {
+    a.gb[l] = acts.gb[l];
+    a.bpart[l] = parts.b[l];
+  }
+  a.partial = partial;
+  a.n = B;
+  a.scale = (float)(2.0 / (double)(B * kNO));
+  hipLaunchKernelGGL(mlp_train_bwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -250,11 +250,12 @@ int64_t weight_count(const ens::MlpLayout& L) {
   return w;
 }
 
-// Where the step's gradient partials go inside the model's two buffers.
-ens::GradParts grad_parts(const ens_surrogate* s, int64_t B) {
+// Where the step's gradient partials go inside the model's two buffers; the
+// bias partials have one row per `tiles` block of the batch (64 items in the
+// tiled backward, 16 in the fused one).
+ens::GradParts grad_parts(const ens_surrogate* s, int64_t tiles) {
   ens::GradParts P{};
   int64_t wo = 0, bo = 0;
-  const int64_t tiles = (B + 63) / 64;
   for (int l = 0; l < s->L.layers; ++l) {
     P.w[l] = s->wparts + wo;
     P.b[l] = s->bparts + bo;
@@ -271,11 +272,11 @@ int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   for (void* p : old)
     if (p) (void)hipFree(p);
   const int H = kDims[1], O = kDims[4];
+  const int64_t blocks = (B + 15) / 16;  // the finer of the two backward passes' blockings
   bool ok = alloc(&s->a0, B * kDims[0]) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
-            alloc(&s->T, B * O) == hipSuccess &&
-            alloc(&s->partial, (B + 63) / 64) == hipSuccess &&
+            alloc(&s->T, B * O) == hipSuccess && alloc(&s->partial, blocks) == hipSuccess &&
             alloc(&s->wparts, (int64_t)ens::kSplits * weight_count(s->L)) == hipSuccess &&
-            alloc(&s->bparts, (B + 63) / 64 * (s->L.total - weight_count(s->L))) == hipSuccess;
+            alloc(&s->bparts, blocks * (s->L.total - weight_count(s->L))) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
     ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
   for (int l = 0; l < 4 && ok; ++l) ok = alloc(&s->gb[l], B * kDims[l + 1]) == hipSuccess;
@@ -351,17 +352,26 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
   }
   for (int l = 0; l < 4; ++l) acts.gb[l] = s->gb[l];
   hipError_t e;
-  if (c->mlp_tile != 0) {  // minibatch gather and forward in one launch
+  ens::GradParts parts;
+  if (c->mlp_tile != 0) {
+    // gather + forward, then loss + input gradients, one feature-split
+    // launch each; the weight gradients' grouped product; Adam
+    parts = grad_parts(s, (B + 15) / 16);
     e = ens::mlp_forward_train(s->packed, s->w, s->L, s->norm, params, u0, y, n, first, B, mult,
                                add, s->a0, acts, s->Y, s->T, st);
+    if (e == hipSuccess)
+      e = ens::mlp_backward_train(s->packed, s->L, B, acts, s->Y, s->T, parts, s->partial, st);
+    if (e == hipSuccess && loss)
+      e = ens::mlp_loss_sum(s->partial, parts.tiles, 1.0 / (double)(B * kDims[4]), loss, st);
+    if (e == hipSuccess) e = ens::mlp_weight_grads(s->L, s->a0, B, acts, parts, st);
   } else {
+    parts = grad_parts(s, (B + 63) / 64);
     e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T, kDims[4], st);
     if (e == hipSuccess)
       e = ens::mlp_forward(s->L, s->wb, s->w, s->norm, s->a0, B, acts, s->Y, nullptr, 0, 0, st);
+    if (e == hipSuccess)
+      e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, parts, s->partial, loss, st);
   }
-  ens::GradParts parts = grad_parts(s, B);
-  if (e == hipSuccess)
-    e = ens::mlp_backward(s->L, s->wb, s->a0, B, acts, s->Y, s->T, parts, s->partial, loss, st);
   if (e == hipSuccess) {
     s->step += 1;
     const double c1 = 1.0 / (1.0 - std::pow((double)kAdamB1, (double)s->step));
