@@ -94,13 +94,17 @@ hipError_t mlp_loss_sum(const double* partial, int64_t count, double factor, flo
 // Fused backward of a minibatch whose forward pass mlp_forward_train kept
 // in acts / Y / T (4-256-256-256-48 network, packed weights with the
 // transposed part): the output gradient, the loss partials (partial [nb],
-// nb = ceil(B / 16) blocks of 16 items) and the input gradients of layers
-// 3..1 into acts.gb, with the bias-gradient partials of every layer in
-// parts.b ([nb][width]; parts.tiles = nb).  The weight gradients follow with
-// mlp_weight_grads.
+// nb = 2 ceil(B / 32) blocks of 16 items) and every layer's bf16 output
+// gradient G_l into acts.gb in the item-fragment layout, with the
+// bias-gradient partials of every layer in parts.b ([nb][width];
+// parts.tiles = nb).  The weight gradients follow with mlp_weight_grads_if.
 hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_t B,
                               MlpActs& acts, const float* Y, const float* T, GradParts& parts,
                               double* partial, hipStream_t s);
+// The split-K weight-gradient partials (parts.w) from the item-fragment
+// G_l (acts.gb) and A_{l-1} (a0, acts.act) of the fused training path.
+hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, const uint16_t* a0,
+                               GradParts& parts, hipStream_t s);
 
 // Fragment-major weights of the fused kernels (mlp_fused.hip), for the
 // 4 -> 256 -> 256 -> 256 -> 48 network only.  A fragment is 64 lanes x 8
@@ -170,11 +174,23 @@ hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, co
                                   int64_t idx_step, const unsigned long long* n_dev,
                                   int out_compact, float* out, int64_t stride, int num_cu, int ns,
                                   hipStream_t s);
+// Item-fragment layout of a bf16 matrix X [item][feature] for the weight-
+// gradient products of the fused training path (items padded to whole
+// 32-item blocks, features to whole 16-feature blocks, padding zero): the
+// fragment of item block kb and feature block fb sits at
+// (kb * nfb + fb) * kPackFrag, lane 16 g + r holding feature 16 fb + r of
+// items 32 kb + 8 g .. 32 kb + 8 g + 7 -- for G_l^T the A operand and for
+// A_{l-1} the B operand of v_mfma_f32_16x16x32_bf16 with k = items.
+__host__ __device__ inline int64_t item_frag_pos(int64_t item, int f, int nfb) {
+  return ((item >> 5) * nfb + (f >> 4)) * kPackFrag + (16 * ((item & 31) >> 3) + (f & 15)) * 8 +
+         (item & 7);
+}
+
 // Training forward of a minibatch in one launch: item b < B is trajectory
 // (mult * (first + b) + add) mod n of params / u0 [3][n] and y [48][n]; keeps
-// the normalised inputs a0 [B][4] bf16, Z_l [B][256] FP32 and A_l [B][256]
-// bf16 of the hidden layers, the normalised outputs Y [B][48] and targets
-// T [B][48] in the layouts mlp_forward / mlp_gather leave them.
+// Z_l [B][256] FP32 of the hidden layers, the normalised outputs Y [B][48]
+// and targets T [B][48], and in the item-fragment layout the normalised
+// inputs a0 (16 feature slots, 4 used) and A_l of the hidden layers.
 hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
                              const float* norm, const float* params, const float* u0,
                              const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,

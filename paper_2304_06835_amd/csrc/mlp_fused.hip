@@ -393,9 +393,15 @@ mlp_fused_fwd(const FusedArgs a) {
 // hidden layers, Y and the normalised targets T.
 
 // LDS: two activation buffers [pair K][lane] of 16 bytes (layer outputs
-// alternate between them), then the biases and normalisation.
+// alternate between them); two transposition tiles [feature][16 items] of
+// bf16 (layer outputs alternate), through which a layer's output leaves in
+// the item-fragment layout; a small tile for the inputs / the output
+// gradient; then the biases and normalisation.
 constexpr int kTAct = 8 * 64 * 16;
-constexpr int kTBias = 2 * kTAct;
+constexpr int kTTile = 256 * 16 * 2;
+constexpr int kTTiles = 2 * kTAct;
+constexpr int kTSmall = kTTiles + 2 * kTTile;  // [48][16] bf16
+constexpr int kTBias = kTSmall + 48 * 16 * 2;
 constexpr int kTB1 = 0, kTB2 = 256, kTB3 = 512, kTB4 = 768, kTOutMean = 816, kTOutIStd = 864,
               kTInMean = 912, kTInIStd = 916, kTBCount = 920;
 constexpr int kTLdsBytes = kTBias + kTBCount * 4;
@@ -404,34 +410,51 @@ __device__ inline bf16x8_t* act_slot(uint8_t* lds, int buf, int K, int lane) {
   return reinterpret_cast<bf16x8_t*>(lds + buf * kTAct + (K * 64 + lane) * 16);
 }
 
+__device__ inline __bf16* ttile(uint8_t* lds, int t) {
+  return reinterpret_cast<__bf16*>(lds + kTTiles + t * kTTile);
+}
+
+// A block's 16 items (half h of item block kb) of a [feature][16 items]
+// transposition tile with nfb 16-feature blocks (`real` features, the rest
+// zero) into the item-fragment layout of mlp.h: entry (fb, g', r16) of the
+// fragment, g' = 2h or 2h + 1, holds 8 consecutive items of one feature,
+// 16 contiguous bytes in the tile.  32 nfb entries over the block's threads.
+__device__ inline void if_store(const __bf16* tile, uint16_t* dst, int64_t kb, int h, int nfb,
+                                int real, int tid) {
+  for (int E = tid; E < 32 * nfb; E += 256) {
+    const int fb = E >> 5, w = E & 31, r16 = w & 15, hi = w >> 4, f = 16 * fb + r16;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (f < real) v = *reinterpret_cast<const uint4*>(tile + f * 16 + 8 * hi);
+    *reinterpret_cast<uint4*>(dst + ((kb * nfb + fb) * kPackFrag + (16 * (2 * h + hi) + r16) * 8)) = v;
+  }
+}
+
 // One fragment of the packed weights, straight from global memory.
 __device__ inline bf16x8_t gfrag(const uint16_t* packed, int64_t frag_index, int lane) {
   return *reinterpret_cast<const bf16x8_t*>(packed + frag_index * kFrag + lane * 8);
 }
 
-// Z and A of pair K (features 32 K + 4 g + {0..3} and 32 K + 16 + 4 g + {0..3})
-// into this lane's item rows (null: an item past the end of the batch).
-__device__ inline void keep_pair(f32x4_t z0, f32x4_t z1, bf16x8_t v, int K, int g, float* zrow,
-                                 uint16_t* arow) {
-  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-  if (!zrow) return;
-  float* zp = zrow + 32 * K + 4 * g;
-  *reinterpret_cast<f32x4_t*>(zp) = z0;
-  *reinterpret_cast<f32x4_t*>(zp + 16) = z1;
-  uint16_t* ap = arow + 32 * K + 4 * g;
-  *reinterpret_cast<bf16x4_t*>(ap) = bf16x4_t{v[0], v[1], v[2], v[3]};
-  *reinterpret_cast<bf16x4_t*>(ap + 16) = bf16x4_t{v[4], v[5], v[6], v[7]};
-}
-
 // This wave's 64 rows of a layer: four 16-row blocks, their SiLU into the
-// output buffer (pairs 2w, 2w+1) and Z / A into the item's rows.
-__device__ inline void train_rows(f32x4_t (&acc)[4], uint8_t* lds, int out_buf, int wave, int g,
-                                  int lane, float* zrow, uint16_t* arow) {
+// output buffer (pairs K = 2w, 2w+1: features 32 K + 4 g + {0..3} and
+// 32 K + 16 + 4 g + {0..3}) and the transposition tile, Z into the item's
+// row (null: an item past the end of the batch).
+__device__ inline void train_rows(f32x4_t (&acc)[4], uint8_t* lds, int out_buf, __bf16* tile,
+                                  int wave, int g, int col, int lane, float* zrow) {
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
+    const int K = 2 * wave + pp;
     const bf16x8_t v = silu_pack(acc[2 * pp], acc[2 * pp + 1]);
-    *act_slot(lds, out_buf, 2 * wave + pp, lane) = v;
-    keep_pair(acc[2 * pp], acc[2 * pp + 1], v, 2 * wave + pp, g, zrow, arow);
+    *act_slot(lds, out_buf, K, lane) = v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tile[(32 * K + 4 * g + r) * 16 + col] = v[r];
+      tile[(32 * K + 16 + 4 * g + r) * 16 + col] = v[4 + r];
+    }
+    if (zrow) {
+      float* zp = zrow + 32 * K + 4 * g;
+      *reinterpret_cast<f32x4_t*>(zp) = acc[2 * pp];
+      *reinterpret_cast<f32x4_t*>(zp + 16) = acc[2 * pp + 1];
+    }
   }
 }
 
@@ -499,13 +522,12 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
   }
   __syncthreads();
   float* zrow[3];
-  uint16_t* arow[3];
 #pragma unroll
-  for (int l = 0; l < 3; ++l) {
-    zrow[l] = live ? a.z[l] + q * kH : nullptr;
-    arow[l] = live ? a.act[l] + q * kH : nullptr;
-  }
+  for (int l = 0; l < 3; ++l) zrow[l] = live ? a.z[l] + q * kH : nullptr;
   const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+  const int64_t kb = blockIdx.x >> 1;  // item block of the item-fragment outputs
+  const int h = blockIdx.x & 1;
+  __bf16* small = reinterpret_cast<__bf16*>(lds + kTSmall);
 
   // ---- layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane group 0
   {
@@ -516,18 +538,20 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
       xin[k] = (__bf16)v;
       xin[4 + k] = (__bf16)0.0f;
     }
-    if (wave == 0 && g == 0 && live) {
-      typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-      *reinterpret_cast<bf16x4_t*>(a.a0 + q * 4) = bf16x4_t{xin[0], xin[1], xin[2], xin[3]};
+    if (wave == 0 && g == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) small[k * 16 + col] = xin[k];
     }
     f32x4_t acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
           w1[j], xin, *reinterpret_cast<const f32x4_t*>(bw + kTB1 + r0 + 16 * j), 0, 0, 0);
-    train_rows(acc, lds, 0, wave, g, lane, zrow[0], arow[0]);
+    train_rows(acc, lds, 0, ttile(lds, 0), wave, g, col, lane, zrow[0]);
   }
   __syncthreads();
+  if_store(small, a.a0, kb, h, 1, 4, tid);
+  if_store(ttile(lds, 0), a.act[0], kb, h, 16, kH, tid);
 
   // ---- layers 2 and 3
   bf16x8_t x[8];
@@ -555,8 +579,9 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
 #pragma unroll
       for (int kb = 0; kb < 8; ++kb) w[0][kb] = gfrag(a.packed, kP4 / kFrag + wave * 8 + kb, lane);
     }
-    train_rows(acc, lds, out_buf, wave, g, lane, zrow[layer + 1], arow[layer + 1]);
+    train_rows(acc, lds, out_buf, ttile(lds, out_buf), wave, g, col, lane, zrow[layer + 1]);
     __syncthreads();
+    if_store(ttile(lds, out_buf), a.act[layer + 1], kb, h, 16, kH, tid);
   }
 
   // ---- layer 4: waves 0..2 take output rows 16 w .. 16 w + 15: normalised
@@ -607,32 +632,45 @@ __device__ inline float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-// Sum over the 16 lanes of a lane group (the block's 16 items), butterfly.
+// Sum over the 16 lanes of a lane group (the block's 16 items): rotations
+// by 8, 4, 2, 1 within each 16-lane DPP row, plain vector adds (a lane-
+// crossbar shuffle would cost an LDS round trip per step).  Every lane ends
+// with the group's total; callers take lane 0 of the group, whose order of
+// additions is fixed.
+__device__ inline float ror16(float v, int ctrl_sel) {
+  const int x = __builtin_bit_cast(int, v);
+  int r;
+  switch (ctrl_sel) {  // row_ror:8 / :4 / :2 / :1
+    case 8: r = __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false); break;
+    case 4: r = __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false); break;
+    case 2: r = __builtin_amdgcn_update_dpp(0, x, 0x122, 0xF, 0xF, false); break;
+    default: r = __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false); break;
+  }
+  return __builtin_bit_cast(float, r);
+}
 __device__ inline float sum16(float v) {
-  v += __shfl_xor(v, 8, 16);
-  v += __shfl_xor(v, 4, 16);
-  v += __shfl_xor(v, 2, 16);
-  v += __shfl_xor(v, 1, 16);
+  v += ror16(v, 8);
+  v += ror16(v, 4);
+  v += ror16(v, 2);
+  v += ror16(v, 1);
   return v;
 }
 
 // G = acc * silu'(Z) for this wave's 64 features (row blocks 4w + j): bf16
-// pairs into LDS (out_buf >= 0), bf16 into the item's row of gb (null: an
-// item past the end), the FP32 column sums into the block's partial row.
+// pairs into LDS (out_buf >= 0), bf16 into the transposition tile, the FP32
+// column sums into the block's partial row.
 __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4], uint8_t* lds,
-                                int out_buf, int wave, int g, int col, int lane, int r0,
-                                uint16_t* grow, float* bp) {
-  typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+                                int out_buf, __bf16* tile, int wave, int g, int col, int lane,
+                                int r0, float* bp) {
   f32x4_t G[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) G[j][r] = acc[j][r] * dsilu(zv[j][r]);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const bf16x4_t h = bf16x4_t{(__bf16)G[j][0], (__bf16)G[j][1], (__bf16)G[j][2], (__bf16)G[j][3]};
-    if (grow) *reinterpret_cast<bf16x4_t*>(grow + r0 + 16 * j) = h;
-  }
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) tile[(r0 + 16 * j + r) * 16 + col] = (__bf16)G[j][r];
   if (out_buf >= 0) {
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
@@ -655,22 +693,25 @@ __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4],
 }
 
 __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kTAct];
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kTBias];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
   const bool live = q < a.n;
   const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+  const int64_t kb = blockIdx.x >> 1;  // item block of the item-fragment outputs
+  const int h = blockIdx.x & 1;
+  __bf16* small = reinterpret_cast<__bf16*>(lds + kTSmall);
 
   // the output gradient's operands (outputs 16 h + 4 g + r), the kept
   // pre-activations of this wave's features, the transposed weights of
   // layers 4 and 3
   f32x4_t yv[3], tv[3], zv[3][4];
 #pragma unroll
-  for (int h = 0; h < 3; ++h) {
-    yv[h] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    tv[h] = yv[h];
+  for (int hh = 0; hh < 3; ++hh) {
+    yv[hh] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    tv[hh] = yv[hh];
   }
 #pragma unroll
   for (int l = 0; l < 3; ++l)
@@ -678,9 +719,9 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
     for (int j = 0; j < 4; ++j) zv[l][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   if (live) {
 #pragma unroll
-    for (int h = 0; h < 3; ++h) {
-      yv[h] = *reinterpret_cast<const f32x4_t*>(a.Y + q * kNO + 16 * h + 4 * g);
-      tv[h] = *reinterpret_cast<const f32x4_t*>(a.T + q * kNO + 16 * h + 4 * g);
+    for (int hh = 0; hh < 3; ++hh) {
+      yv[hh] = *reinterpret_cast<const f32x4_t*>(a.Y + q * kNO + 16 * hh + 4 * g);
+      tv[hh] = *reinterpret_cast<const f32x4_t*>(a.T + q * kNO + 16 * hh + 4 * g);
     }
 #pragma unroll
     for (int l = 2; l >= 0; --l)
@@ -704,11 +745,11 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
   float gv[12];
   double d2 = 0.0;
 #pragma unroll
-  for (int h = 0; h < 3; ++h)
+  for (int hh = 0; hh < 3; ++hh)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float d = yv[h][r] - tv[h][r];
-      gv[4 * h + r] = a.scale * d;
+      const float d = yv[hh][r] - tv[hh][r];
+      gv[4 * hh + r] = a.scale * d;
       d2 += (double)d * d;
     }
   bf16x8_t x4[2];
@@ -718,24 +759,20 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
     x4[1][e] = e < 4 ? (__bf16)gv[8 + e] : (__bf16)0.0f;
   }
   if (wave == 0) {
-    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-    if (live) {
 #pragma unroll
-      for (int h = 0; h < 3; ++h)
-        *reinterpret_cast<bf16x4_t*>(a.gb[3] + q * kNO + 16 * h + 4 * g) =
-            bf16x4_t{(__bf16)gv[4 * h], (__bf16)gv[4 * h + 1], (__bf16)gv[4 * h + 2],
-                     (__bf16)gv[4 * h + 3]};
-    }
+    for (int hh = 0; hh < 3; ++hh)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) small[(16 * hh + 4 * g + r) * 16 + col] = (__bf16)gv[4 * hh + r];
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 += __shfl_xor(d2, m);
     if (lane == 0) a.partial[blockIdx.x] = d2;
     float* bp = a.bpart[3] + (int64_t)blockIdx.x * kNO;
 #pragma unroll
-    for (int h = 0; h < 3; ++h)
+    for (int hh = 0; hh < 3; ++hh)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float t = sum16(gv[4 * h + r]);
-        if (col == 0) bp[16 * h + 4 * g + r] = t;
+        const float t = sum16(gv[4 * hh + r]);
+        if (col == 0) bp[16 * hh + 4 * g + r] = t;
       }
   }
 
@@ -748,9 +785,11 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
     for (int kb = 0; kb < 2; ++kb)
       acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[j][kb], x4[kb], acc[j], 0, 0, 0);
   }
-  bwd_rows(acc, zv[2], lds, 0, wave, g, col, lane, r0, live ? a.gb[2] + q * kH : nullptr,
+  bwd_rows(acc, zv[2], lds, 0, ttile(lds, 0), wave, g, col, lane, r0,
            a.bpart[2] + (int64_t)blockIdx.x * kH);
   __syncthreads();
+  if_store(small, a.gb[3], kb, h, 3, kNO, tid);
+  if_store(ttile(lds, 0), a.gb[2], kb, h, 16, kH, tid);
 
   // ---- G_2 = (G_3 W_3) * silu'(Z_2), then G_1 = (G_2 W_2) * silu'(Z_1)
   bf16x8_t x[8];
@@ -772,11 +811,94 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
         for (int kb = 0; kb < 8; ++kb)
           w[j][kb] = gfrag(a.packed, kPackT2 / kFrag + (4 * wave + j) * 8 + kb, lane);
     }
-    const int l = 1 - step;  // G_2 (gb[1], Z_2) then G_1 (gb[0], Z_1)
-    bwd_rows(acc, zv[l], lds, step == 0 ? 1 : -1, wave, g, col, lane, r0,
-             live ? a.gb[l] + q * kH : nullptr, a.bpart[l] + (int64_t)blockIdx.x * kH);
-    if (step == 0) __syncthreads();
+    const int l = 1 - step;  // G_2 (gb[1], Z_2, tile 1) then G_1 (gb[0], Z_1, tile 0)
+    bwd_rows(acc, zv[l], lds, step == 0 ? 1 : -1, ttile(lds, 1 - step), wave, g, col, lane, r0,
+             a.bpart[l] + (int64_t)blockIdx.x * kH);
+    __syncthreads();
+    if_store(ttile(lds, 1 - step), a.gb[l], kb, h, 16, kH, tid);
   }
+}
+
+// ---- weight gradients ------------------------------------------------------
+// dW_l [o][i] = sum over items of G_l [item][o] A_{l-1} [item][i], both in the
+// item-fragment layout: a fragment of G_l is exactly the A operand of
+// v_mfma_f32_16x16x32_bf16 for 16 rows o and 32 items, a fragment of
+// A_{l-1} the B operand for 16 columns i, so every wave reads its operands
+// with 16-byte loads straight into registers and no LDS is involved.  A
+// block takes a 64 x 64 tile of one layer's dW (wave (wm, wn) a 32 x 32
+// quarter) over one of kSplits item ranges and writes that range's partial;
+// the Adam kernel sums the partials.
+struct DwProblem {
+  const uint16_t* G;  // item-fragment layout, nfo feature blocks
+  const uint16_t* A;  // item-fragment layout, nfi feature blocks
+  float* C;           // [kSplits][M][N]
+  int M, N, nfo, nfi, tiles_m, tiles_n;
+  int64_t block0;
+};
+struct DwGroup {
+  DwProblem p[4];
+  int count;
+  int64_t nkb, kc;  // item blocks, item blocks per split
+};
+
+__global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
+  int pi = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (i < D.count && (int64_t)blockIdx.x >= D.p[i].block0) pi = i;
+  const DwProblem& P = D.p[pi];
+  const int64_t b = (int64_t)blockIdx.x - P.block0;
+  const int per_split = P.tiles_m * P.tiles_n;
+  const int split = (int)(b / per_split), rem = (int)(b % per_split);
+  const int tm = rem / P.tiles_n, tn = rem % P.tiles_n;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int fo0 = 4 * tm + 2 * (wave >> 1), fi0 = 4 * tn + 2 * (wave & 1);
+  const int64_t kb0 = split * D.kc, kb1 = kb0 + D.kc < D.nkb ? kb0 + D.kc : D.nkb;
+  f32x4_t acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const bf16x8_t zero = bf16x8_t{};
+  for (int64_t k0 = kb0; k0 < kb1; k0 += 8) {  // eight item blocks' operands in flight
+    bf16x8_t ga[8][2], ab[8][2];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const bool kin = k0 + t < kb1;
+        ga[t][x] = kin && fo0 + x < P.nfo
+                       ? *reinterpret_cast<const bf16x8_t*>(
+                             P.G + (((k0 + t) * P.nfo + fo0 + x) * kPackFrag + lane * 8))
+                       : zero;
+        ab[t][x] = kin && fi0 + x < P.nfi
+                       ? *reinterpret_cast<const bf16x8_t*>(
+                             P.A + (((k0 + t) * P.nfi + fi0 + x) * kPackFrag + lane * 8))
+                       : zero;
+      }
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[t][x], ab[t][y], acc[x][y], 0, 0, 0);
+  }
+  // lane (g, c) holds rows 4 g + r, column c of each 16 x 16 block
+  float* C = P.C + (int64_t)split * P.M * P.N;
+  const int g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+      const int i = 16 * (fi0 + y) + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int o = 16 * (fo0 + x) + 4 * g + r;
+        if (o < P.M && i < P.N) C[(int64_t)o * P.N + i] = acc[x][y][r];
+      }
+    }
 }
 
 }  // namespace
@@ -869,7 +991,7 @@ hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLa
   a.Y = Y;
   a.T = T;
   for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
-  const int64_t blocks = (B + 15) / 16;
+  const int64_t blocks = 2 * ((B + 31) / 32);  // whole item blocks of the fragment outputs
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   hipLaunchKernelGGL(mlp_train_fwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
@@ -883,7 +1005,7 @@ hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_
   if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
       L.dims[3] != kH || L.dims[4] != kNO)
     return hipErrorInvalidValue;
-  const int64_t blocks = (B + 15) / 16;
+  const int64_t blocks = 2 * ((B + 31) / 32);  // whole item blocks of the fragment outputs
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
   parts.tiles = (int)blocks;
   BwdArgs a{};
@@ -899,6 +1021,35 @@ hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_
   a.n = B;
   a.scale = (float)(2.0 / (double)(B * kNO));
   hipLaunchKernelGGL(mlp_train_bwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Weight-gradient partials from the item-fragment operands the fused
+// forward and backward kernels leave (B items padded to whole 32-item
+// blocks with zero gradients).
+hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, const uint16_t* a0,
+                               GradParts& parts, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  DwGroup D{};
+  D.count = L.layers;
+  D.nkb = (B + 31) / 32;
+  D.kc = (D.nkb + kSplits - 1) / kSplits;
+  int64_t blocks = 0;
+  for (int l = 0; l < L.layers; ++l) {
+    DwProblem& P = D.p[l];
+    P.G = acts.gb[l];
+    P.A = l > 0 ? acts.act[l - 1] : a0;
+    P.C = parts.w[l];
+    P.M = L.dims[l + 1];
+    P.N = L.dims[l];
+    P.nfo = (P.M + 15) / 16;
+    P.nfi = (P.N + 15) / 16;
+    P.tiles_m = (P.M + 63) / 64;
+    P.tiles_n = (P.N + 63) / 64;
+    P.block0 = blocks;
+    blocks += (int64_t)P.tiles_m * P.tiles_n * kSplits;
+  }
+  hipLaunchKernelGGL(mlp_dw, dim3((unsigned)blocks), dim3(256), 0, s, D);
   return hipGetLastError();
 }
 

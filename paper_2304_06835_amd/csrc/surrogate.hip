@@ -272,14 +272,17 @@ int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   for (void* p : old)
     if (p) (void)hipFree(p);
   const int H = kDims[1], O = kDims[4];
-  const int64_t blocks = (B + 15) / 16;  // the finer of the two backward passes' blockings
-  bool ok = alloc(&s->a0, B * kDims[0]) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
+  // the fused path's blocks of 16 items and its item-fragment layouts
+  // (items padded to whole 32-item blocks, a0 to 16 feature slots) are the
+  // larger of the two paths' needs
+  const int64_t Bp = (B + 31) / 32 * 32, blocks = Bp / 16;
+  bool ok = alloc(&s->a0, Bp * 16) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
             alloc(&s->T, B * O) == hipSuccess && alloc(&s->partial, blocks) == hipSuccess &&
             alloc(&s->wparts, (int64_t)ens::kSplits * weight_count(s->L)) == hipSuccess &&
             alloc(&s->bparts, blocks * (s->L.total - weight_count(s->L))) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
-    ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], B * H) == hipSuccess;
-  for (int l = 0; l < 4 && ok; ++l) ok = alloc(&s->gb[l], B * kDims[l + 1]) == hipSuccess;
+    ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], Bp * H) == hipSuccess;
+  for (int l = 0; l < 4 && ok; ++l) ok = alloc(&s->gb[l], Bp * kDims[l + 1]) == hipSuccess;
   if (!ok) {
     s->cap_batch = 0;
     return fail(c, ENS_ENOMEM, "cannot allocate the training workspace for batch %lld",
@@ -356,14 +359,14 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
   if (c->mlp_tile != 0) {
     // gather + forward, then loss + input gradients, one feature-split
     // launch each; the weight gradients' grouped product; Adam
-    parts = grad_parts(s, (B + 15) / 16);
+    parts = grad_parts(s, 2 * ((B + 31) / 32));
     e = ens::mlp_forward_train(s->packed, s->w, s->L, s->norm, params, u0, y, n, first, B, mult,
                                add, s->a0, acts, s->Y, s->T, st);
     if (e == hipSuccess)
       e = ens::mlp_backward_train(s->packed, s->L, B, acts, s->Y, s->T, parts, s->partial, st);
     if (e == hipSuccess && loss)
       e = ens::mlp_loss_sum(s->partial, parts.tiles, 1.0 / (double)(B * kDims[4]), loss, st);
-    if (e == hipSuccess) e = ens::mlp_weight_grads(s->L, s->a0, B, acts, parts, st);
+    if (e == hipSuccess) e = ens::mlp_weight_grads_if(s->L, B, acts, s->a0, parts, st);
   } else {
     parts = grad_parts(s, (B + 63) / 64);
     e = ens::mlp_gather(params, u0, y, n, first, B, mult, add, s->norm, s->a0, s->T, kDims[4], st);
