@@ -405,7 +405,10 @@ int ens_surrogate_train_step(ens_ctx *ctx, ens_surrogate *s,
 /* `epochs` passes over floor(n / batch) minibatches, a fresh pseudo-random
  * permutation per epoch drawn from `seed`, learning rate decayed from lr_max
  * to lr_min on a cosine; epoch_loss (device float [epochs], may be NULL)
- * receives the loss of each epoch's last minibatch.                          */
+ * receives the loss of each epoch's last minibatch.  With the fused kernels
+ * (ENS_OPT_MLP_TILE != 0) the call first stages the set item-major and
+ * normalised in a workspace the model keeps (208 bytes per trajectory);
+ * the steps are identical to ens_surrogate_train_step calls.                 */
 int ens_surrogate_train(ens_ctx *ctx, ens_surrogate *s, const float *params,
                         const float *u0, const float *y, int64_t n, int epochs,
                         int64_t batch, double lr_max, double lr_min,

@@ -186,15 +186,23 @@ __host__ __device__ inline int64_t item_frag_pos(int64_t item, int f, int nfb) {
          (item & 7);
 }
 
+// Record width of a staged training set (mlp_stage_items): the normalised
+// inputs (rho, x0, y0, z0) and 48 normalised targets of one trajectory.
+constexpr int kStageW = 52;
+hipError_t mlp_stage_items(const float* params, const float* u0, const float* y, int64_t n,
+                           const float* norm, float* D, hipStream_t s);
+
 // Training forward of a minibatch in one launch: item b < B is trajectory
 // (mult * (first + b) + add) mod n of params / u0 [3][n] and y [48][n]; keeps
 // Z_l [B][256] FP32 of the hidden layers, the normalised outputs Y [B][48]
 // and targets T [B][48], and in the item-fragment layout the normalised
-// inputs a0 (16 feature slots, 4 used) and A_l of the hidden layers.
+// inputs a0 (16 feature slots, 4 used) and A_l of the hidden layers.  With
+// `staged` (the set staged by mlp_stage_items, n records) the items are read
+// from there and params / u0 / y are not used.
 hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
                              const float* norm, const float* params, const float* u0,
                              const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
                              uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
-                             hipStream_t s);
+                             const float* staged, hipStream_t s);
 
 }  // namespace ens

@@ -119,6 +119,10 @@ struct FusedArgs {
   uint16_t* act[3];
   float* Y;
   float* T;
+  // optional: the training set staged item-major and normalised,
+  // [in_stride][kStageW] (inputs 0..3, targets 4..51), read instead of
+  // params / u0 / y
+  const float* staged;
 };
 
 __device__ inline float silu(float z) {
@@ -488,15 +492,29 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
   float f[4] = {0.f, 0.f, 0.f, 0.f}, yt[4] = {0.f, 0.f, 0.f, 0.f};
   if (live) {
     row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
-    if (g == 0) {
-      f[0] = a.params[ns + row];
-      f[1] = a.u0[row];
-      f[2] = a.u0[ns + row];
-      f[3] = a.u0[2 * ns + row];
-    }
-    if (wave < 3) {
+    if (a.staged) {  // normalised already, one 208-byte record per item
+      const float* rec = a.staged + row * kStageW;
+      if (g == 0) {
+        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+        for (int k = 0; k < 4; ++k) f[k] = v[k];
+      }
+      if (wave < 3) {
+        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec + 4 + 16 * wave + 4 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yt[r] = v[r];
+      }
+    } else {
+      if (g == 0) {
+        f[0] = a.params[ns + row];
+        f[1] = a.u0[row];
+        f[2] = a.u0[ns + row];
+        f[3] = a.u0[2 * ns + row];
+      }
+      if (wave < 3) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+      }
     }
   }
   // this wave's weights of layers 1 and 2
@@ -534,7 +552,9 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
     bf16x8_t xin;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float v = (g == 0 && live) ? (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k] : 0.f;
+      const float v = !(g == 0 && live) ? 0.f
+                      : a.staged       ? f[k]
+                                       : (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k];
       xin[k] = (__bf16)v;
       xin[4 + k] = (__bf16)0.0f;
     }
@@ -598,7 +618,8 @@ __global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
       *reinterpret_cast<f32x4_t*>(a.Y + q * kNO + o0) = out;
       f32x4_t t;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) t[r] = (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
+      for (int r = 0; r < 4; ++r)
+        t[r] = a.staged ? yt[r] : (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
       *reinterpret_cast<f32x4_t*>(a.T + q * kNO + o0) = t;
     }
   }
@@ -819,6 +840,39 @@ __global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
   }
 }
 
+// ---- staged training set ---------------------------------------------------
+// Item-major, normalised copy of a training set for the epochs of one
+// training call: record i = (rho, x0, y0, z0) and the 48 targets of
+// trajectory i, each as the forward kernel would normalise it, so that a
+// minibatch gather reads 208 contiguous bytes per item instead of one
+// scattered line from each of 52 rows.  A block takes 64 items: coalesced
+// reads of the 52 rows into an LDS tile, then contiguous record writes.
+__global__ void __launch_bounds__(256) stage_items(const float* params, const float* u0,
+                                                   const float* y, int64_t n, const float* norm,
+                                                   float* D) {
+  __shared__ float tile[64][kStageW + 1];
+  const int tid = threadIdx.x;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  for (int e = tid; e < 64 * kStageW; e += 256) {
+    const int c = e >> 6, i = e & 63;
+    const int64_t it = i0 + i;
+    float v = 0.f;
+    if (it < n) {
+      if (c < 4) {
+        const float x = c == 0 ? params[n + it] : u0[(int64_t)(c - 1) * n + it];
+        v = (x - norm[kInMean + c]) * norm[kInIStd + c];
+      } else {
+        const int o = c - 4;
+        v = (y[(int64_t)o * n + it] - norm[kOutMean + o]) * norm[kOutIStd + o];
+      }
+    }
+    tile[i][c] = v;
+  }
+  __syncthreads();
+  const int64_t items = n - i0 < 64 ? n - i0 : 64;
+  for (int e = tid; e < items * kStageW; e += 256) D[i0 * kStageW + e] = tile[e / kStageW][e % kStageW];
+}
+
 // ---- weight gradients ------------------------------------------------------
 // dW_l [o][i] = sum over items of G_l [item][o] A_{l-1} [item][i], both in the
 // item-fragment layout: a fragment of G_l is exactly the A operand of
@@ -839,9 +893,52 @@ struct DwGroup {
   DwProblem p[4];
   int count;
   int64_t nkb, kc;  // item blocks, item blocks per split
+  // bias gradients: the blocks from bias_block0 on each sum the `rows`
+  // per-block partial rows of 64 biases (layer l: bias_n[l] of them at
+  // bias[l]) into row 0, so the Adam kernel reads one row
+  float* bias[4];
+  int bias_n[4];
+  int64_t bias_block0;
+  int rows;
 };
 
+// 64 biases per block, four threads per bias each summing a quarter of the
+// rows in order, the quarters then added in order: a fixed summation order.
+__device__ void bias_sums(const DwGroup& D, int64_t b) {
+  __shared__ float part[4][64];
+  int l = 0;  // layer l owns ceil(bias_n[l] / 64) consecutive blocks
+  while (l < D.count - 1 && b >= (D.bias_n[l] + 63) / 64) {
+    b -= (D.bias_n[l] + 63) / 64;
+    ++l;
+  }
+  const int64_t first = b * 64;
+  const int t = threadIdx.x, j = t & 63, quarter = t >> 6;
+  const int64_t f = first + j;
+  const int n = D.bias_n[l];
+  float sum = 0.f;
+  if (f < n) {
+    const int per = (D.rows + 3) / 4, r0 = quarter * per, r1 = r0 + per < D.rows ? r0 + per : D.rows;
+    const float* col = D.bias[l] + f;
+    int r = r0;
+    for (; r + 16 <= r1; r += 16) {
+      float u[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) u[k] = col[(int64_t)(r + k) * n];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sum += u[k];
+    }
+    for (; r < r1; ++r) sum += col[(int64_t)r * n];
+  }
+  part[quarter][j] = sum;
+  __syncthreads();
+  if (quarter == 0 && f < n) D.bias[l][f] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
+}
+
 __global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
+  if ((int64_t)blockIdx.x >= D.bias_block0) {
+    bias_sums(D, (int64_t)blockIdx.x - D.bias_block0);
+    return;
+  }
   int pi = 0;
 #pragma unroll
   for (int i = 1; i < 4; ++i)
@@ -966,7 +1063,7 @@ hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLa
                              const float* norm, const float* params, const float* u0,
                              const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
                              uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
-                             hipStream_t s) {
+                             const float* staged, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
       L.dims[3] != kH || L.dims[4] != kNO || n <= 0)
@@ -990,6 +1087,7 @@ hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLa
   }
   a.Y = Y;
   a.T = T;
+  a.staged = staged;
   for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
   const int64_t blocks = 2 * ((B + 31) / 32);  // whole item blocks of the fragment outputs
   if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
@@ -1049,7 +1147,25 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     P.block0 = blocks;
     blocks += (int64_t)P.tiles_m * P.tiles_n * kSplits;
   }
+  // bias blocks: each layer's biases in whole 64-bias blocks
+  D.bias_block0 = blocks;
+  D.rows = parts.tiles;
+  for (int l = 0; l < L.layers; ++l) {
+    D.bias[l] = parts.b[l];
+    D.bias_n[l] = L.dims[l + 1];
+    blocks += (L.dims[l + 1] + 63) / 64;
+  }
   hipLaunchKernelGGL(mlp_dw, dim3((unsigned)blocks), dim3(256), 0, s, D);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  parts.tiles = 1;  // the Adam kernel reads the summed row
+  return hipSuccess;
+}
+
+hipError_t mlp_stage_items(const float* params, const float* u0, const float* y, int64_t n,
+                           const float* norm, float* D, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_items, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, params, u0, y,
+                     n, norm, D);
   return hipGetLastError();
 }
 

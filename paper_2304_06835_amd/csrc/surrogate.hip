@@ -215,6 +215,8 @@ struct ens_surrogate {
   float* Y = nullptr;
   float* T = nullptr;
   uint16_t* gb[4] = {};  // bf16 output gradient of every layer
+  int64_t cap_staged = 0;
+  float* staged = nullptr;  // a training call's set, item-major and normalised
   double* partial = nullptr;  // per 64-row block loss sums
   float* wparts = nullptr;    // split-K partials of the weight gradients, every layer
   float* bparts = nullptr;    // 64-row block partials of the bias gradients, every layer
@@ -238,7 +240,7 @@ namespace {
 void free_all(ens_surrogate* s) {
   void* ps[] = {s->w, s->wb, s->packed, s->m, s->v, s->grad, s->norm, s->a0, s->z[0], s->z[1], s->z[2],
                 s->act[0], s->act[1], s->act[2], s->Y, s->T, s->gb[0], s->gb[1], s->gb[2],
-                s->gb[3], s->partial, s->wparts, s->bparts, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
+                s->gb[3], s->partial, s->wparts, s->bparts, s->staged, s->ia0, s->iact[0], s->iact[1], s->alist, s->flist,
                 s->scratch, s->netans, s->used, s->counts, s->words};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -342,9 +344,11 @@ int predict(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0, 
   return ENS_OK;
 }
 
+// staged: the training set staged item-major by mlp_stage_items (fused path
+// only), or null to gather from params / u0 / y.
 int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u0,
                const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult, uint64_t add,
-               double lr, float* loss, hipStream_t st) {
+               double lr, float* loss, hipStream_t st, const float* staged = nullptr) {
   int rc = ensure_batch(c, s, B);
   if (rc != ENS_OK) return rc;
   ens::MlpActs acts{};
@@ -361,7 +365,7 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
     // launch each; the weight gradients' grouped product; Adam
     parts = grad_parts(s, 2 * ((B + 31) / 32));
     e = ens::mlp_forward_train(s->packed, s->w, s->L, s->norm, params, u0, y, n, first, B, mult,
-                               add, s->a0, acts, s->Y, s->T, st);
+                               add, s->a0, acts, s->Y, s->T, staged, st);
     if (e == hipSuccess)
       e = ens::mlp_backward_train(s->packed, s->L, B, acts, s->Y, s->T, parts, s->partial, st);
     if (e == hipSuccess && loss)
@@ -836,6 +840,23 @@ int ens_surrogate_train(ens_ctx* c, ens_surrogate* s, const float* params, const
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int64_t steps = n / batch;
   const int64_t total = steps * epochs;
+  // the fused path reads the set staged once, item-major and normalised
+  // (kept by the model and grown on demand)
+  const float* staged = nullptr;
+  if (c->mlp_tile != 0) {
+    if (n > s->cap_staged) {
+      if (s->staged) (void)hipFree(s->staged);
+      s->staged = nullptr;
+      s->cap_staged = 0;
+      if (alloc(&s->staged, n * ens::kStageW) != hipSuccess)
+        return fail(c, ENS_ENOMEM, "cannot allocate the staged training set (%lld items)",
+                    (long long)n);
+      s->cap_staged = n;
+    }
+    hipError_t e = ens::mlp_stage_items(params, u0, y, n, s->norm, s->staged, st);
+    if (e != hipSuccess) return fail(c, ENS_EDEVICE, "staging the training set: %s", hipGetErrorString(e));
+    staged = s->staged;
+  }
   uint64_t sm = seed;
   int64_t k = 0;
   for (int ep = 0; ep < epochs; ++ep) {
@@ -847,7 +868,7 @@ int ens_surrogate_train(ens_ctx* c, ens_surrogate* s, const float* params, const
       const double lr =
           lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(M_PI * (double)k / (double)total));
       float* lp = (epoch_loss && b == steps - 1) ? epoch_loss + ep : nullptr;
-      rc = train_step(c, s, params, u0, y, n, b * batch, batch, mult, add, lr, lp, st);
+      rc = train_step(c, s, params, u0, y, n, b * batch, batch, mult, add, lr, lp, st, staged);
       if (rc != ENS_OK) return rc;
     }
   }

@@ -233,6 +233,61 @@ def test_packed_weights_follow_every_update(ens):
     torch.cuda.synchronize()
 
 
+def _splitmix(state):
+    m = (1 << 64) - 1
+    state = (state + 0x9E3779B97F4A7C15) & m
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return state, z ^ (z >> 31)
+
+
+def test_train_call_equals_its_steps(ens):
+    """ens_surrogate_train stages the set item-major and normalised once and
+    reads it in every step; the same epochs run as ens_surrogate_train_step
+    calls on the raw [3][n] / [48][n] arrays (the per-epoch permutations and
+    the cosine learning rate rebuilt here) give the same weights bit for bit.
+    n = 1000 is not a multiple of the batch (some items unused per epoch)."""
+    import math
+
+    import torch
+    banner("train call vs its steps")
+    e = W.lorenz_fp32(N=1000, seed=17)
+    y = np.random.default_rng(10).normal(0, 1, (48, e.n)).astype(np.float32)
+    P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
+    th = random_theta(8, scale=0.5)
+    s1, m1 = make_model(ens, th)
+    s2, m2 = make_model(ens, th)
+    for m in (m1, m2):
+        m.fit_norm(P, U, Y)
+    epochs, batch, lr_max, lr_min, seed = 3, 96, 3e-3, 1e-4, 77
+    losses = to_host(m1.train(P, U, Y, epochs=epochs, batch=batch, lr_max=lr_max, lr_min=lr_min,
+                              seed=seed))
+    n, steps = e.n, e.n // batch
+    total, k, st = steps * epochs, 0, seed
+    last = []
+    for ep in range(epochs):
+        st, r = _splitmix(st)
+        mult = r % n
+        while mult == 0 or math.gcd(mult, n) != 1:
+            mult = (mult + 1) % n
+        st, r = _splitmix(st)
+        add = r % n
+        for b in range(steps):
+            lr = lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * k / total))
+            loss = torch.zeros(1, device="cuda")
+            m2.train_step(P, U, Y, first=b * batch, batch=batch, mult=mult, add=add, lr=lr,
+                          loss=loss)
+            k += 1
+        last.append(loss.item())
+    assert m1.step == m2.step == total
+    for b in ("master", "adam_m", "adam_v", "weights_bf16"):
+        assert np.array_equal(to_host(m1.buffer(b)).view(np.uint8),
+                              to_host(m2.buffer(b)).view(np.uint8)), b
+    assert np.array_equal(losses, np.array(last, dtype=np.float32))
+    torch.cuda.synchronize()
+
+
 def test_affine_minibatch_selection(ens):
     """Item b of a minibatch is trajectory (mult*(first+b) + add) mod n."""
     th = random_theta(4, scale=0.5)
