@@ -91,16 +91,6 @@ hipError_t mlp_weight_grads(const MlpLayout& L, const uint16_t* a0, int64_t B, M
 // *loss = factor * sum(partial[0 .. count)), one block, fixed order.
 hipError_t mlp_loss_sum(const double* partial, int64_t count, double factor, float* loss,
                         hipStream_t s);
-// Fused backward of a minibatch whose forward pass mlp_forward_train kept
-// in acts / Y / T (4-256-256-256-48 network, packed weights with the
-// transposed part): the output gradient, the loss partials (partial [nb],
-// nb = 2 ceil(B / 32) blocks of 16 items) and every layer's bf16 output
-// gradient G_l into acts.gb in the item-fragment layout, with the
-// bias-gradient partials of every layer in parts.b ([nb][width];
-// parts.tiles = nb).  The weight gradients follow with mlp_weight_grads_if.
-hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_t B,
-                              MlpActs& acts, const float* Y, const float* T, GradParts& parts,
-                              double* partial, hipStream_t s);
 // The split-K weight-gradient partials (parts.w) from the item-fragment
 // G_l (acts.gb) and A_{l-1} (a0, acts.act) of the fused training path.
 hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, const uint16_t* a0,
@@ -192,17 +182,21 @@ constexpr int kStageW = 52;
 hipError_t mlp_stage_items(const float* params, const float* u0, const float* y, int64_t n,
                            const float* norm, float* D, hipStream_t s);
 
-// Training forward of a minibatch in one launch: item b < B is trajectory
-// (mult * (first + b) + add) mod n of params / u0 [3][n] and y [48][n]; keeps
-// Z_l [B][256] FP32 of the hidden layers, the normalised outputs Y [B][48]
-// and targets T [B][48], and in the item-fragment layout the normalised
-// inputs a0 (16 feature slots, 4 used) and A_l of the hidden layers.  With
-// `staged` (the set staged by mlp_stage_items, n records) the items are read
-// from there and params / u0 / y are not used.
-hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
-                             const float* norm, const float* params, const float* u0,
-                             const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
-                             uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
-                             const float* staged, hipStream_t s);
+// The fused training step's forward and backward passes in one launch
+// (4-256-256-256-48 network, packed weights with the transposed part): item
+// b < B is trajectory (mult * (first + b) + add) mod n of params / u0 [3][n]
+// and y [48][n], or of the set staged by mlp_stage_items (`staged`, n
+// records; params / u0 / y then unused).  Leaves, in the item-fragment
+// layout, the normalised inputs (a0: 16 feature slots, 4 used), A_l of the
+// hidden layers (acts.act) and every layer's bf16 output gradient G_l
+// (acts.gb); the loss partials (partial [nb], nb = 2 ceil(B / 32) blocks of
+// 16 items) and the bias-gradient partials of every layer (parts.b,
+// [nb][width]; parts.tiles = nb).  The weight gradients follow with
+// mlp_weight_grads_if.
+hipError_t mlp_train_fused(const uint16_t* packed, const float* w, const MlpLayout& L,
+                           const float* norm, const float* params, const float* u0,
+                           const float* y, const float* staged, int64_t n, int64_t first,
+                           int64_t B, uint64_t mult, uint64_t add, uint16_t* a0, MlpActs& acts,
+                           GradParts& parts, double* partial, hipStream_t s);
 
 }  // namespace ens

@@ -107,22 +107,6 @@ struct FusedArgs {
   const unsigned long long* n_dev;
   int out_compact;
   int64_t b_off[4];
-  // training launches: item q is row (mult * (first + q) + add) mod
-  // in_stride; they keep the inputs a0 [n][4], Z_l and A_l [n][256] of the
-  // hidden layers, Y [n][48] (normalised) and the targets T [n][48]
-  // normalised from y [48][in_stride]
-  const float* y;
-  uint64_t mult, add;
-  int64_t first;
-  uint16_t* a0;
-  float* z[3];
-  uint16_t* act[3];
-  float* Y;
-  float* T;
-  // optional: the training set staged item-major and normalised,
-  // [in_stride][kStageW] (inputs 0..3, targets 4..51), read instead of
-  // params / u0 / y
-  const float* staged;
 };
 
 __device__ inline float silu(float z) {
@@ -379,36 +363,61 @@ mlp_fused_fwd(const FusedArgs a) {
   wait_vm();  // no global->LDS load may land after the block has left
 }
 
-// ---- training forward ------------------------------------------------------
+// ---- training step ---------------------------------------------------------
 // A training minibatch is small (a few thousand items), so the inference
 // kernel's decomposition -- each wave takes whole queries through all 256
-// features, the weights staged once per block in LDS -- leaves most CUs idle
-// and each busy wave with a long serial chain of SiLU evaluations
+// features, the weights staged once per block in LDS -- would leave most
+// CUs idle and each busy wave with a long serial chain of SiLU evaluations
 // (transcendentals at a quarter of the vector rate, one wave per SIMD).
-// Here a block takes 16 items and its four waves split every layer's
-// features: wave w computes rows 64 w .. 64 w + 63 (row blocks 4w .. 4w+3),
-// reading exactly those weight fragments (32 KiB of a hidden layer,
-// contiguous in the packed layout) straight from global memory into
-// registers, each fragment used once.  The activations are exchanged through
-// LDS, one barrier per layer; lane (g, col) writes the pair it produced and
-// reads back the eight pairs that are its next operands.  So a 4096-item
-// batch makes 256 blocks and each wave does a quarter of the serial work.
-// The kernel keeps what the backward pass reads: a0, Z_l and A_l of the
-// hidden layers, Y and the normalised targets T.
+// Here a block takes 16 items through the forward pass, the loss and the
+// backward pass, and its four waves split every layer's features: wave w
+// computes rows 64 w .. 64 w + 63 (row blocks 4w .. 4w+3) of each hidden
+// layer, and of each input gradient, reading exactly those fragments of W_l
+// (or W_l^T, from the transposed packed copy) -- 32 KiB of a hidden layer,
+// contiguous -- straight from global memory into registers, each used once.
+// The activations and gradients are exchanged through LDS, one barrier per
+// layer: lane (g, col) writes the pair of accumulator tiles it produced and
+// reads back the eight pairs that are its next operands.  A 4096-item batch
+// makes 256 blocks.  The pre-activations Z_l of the wave's features stay in
+// registers for SiLU' in the backward pass; each layer's A_l and G_l leave
+// through a transposition tile in the item-fragment layout of the weight-
+// gradient product, and every G_l's sum over the block's items goes to the
+// block's bias-gradient partial row.
 
-// LDS: two activation buffers [pair K][lane] of 16 bytes (layer outputs
-// alternate between them); two transposition tiles [feature][16 items] of
-// bf16 (layer outputs alternate), through which a layer's output leaves in
-// the item-fragment layout; a small tile for the inputs / the output
-// gradient; then the biases and normalisation.
+// LDS: two pair buffers [pair K][lane] of 16 bytes (layer outputs alternate
+// between them); two transposition tiles [feature][16 items] of bf16; a
+// small tile [48][16] for the inputs / the output gradient; the output
+// gradient's operand pieces [3][64 lanes] of 8 bytes; three loss partials;
+// the biases and normalisation.
 constexpr int kTAct = 8 * 64 * 16;
 constexpr int kTTile = 256 * 16 * 2;
 constexpr int kTTiles = 2 * kTAct;
-constexpr int kTSmall = kTTiles + 2 * kTTile;  // [48][16] bf16
-constexpr int kTBias = kTSmall + 48 * 16 * 2;
+constexpr int kTSmall = kTTiles + 2 * kTTile;
+constexpr int kTG4 = kTSmall + 48 * 16 * 2;
+constexpr int kTLoss = kTG4 + 3 * 64 * 8;
+constexpr int kTBias = kTLoss + 4 * 8;
 constexpr int kTB1 = 0, kTB2 = 256, kTB3 = 512, kTB4 = 768, kTOutMean = 816, kTOutIStd = 864,
               kTInMean = 912, kTInIStd = 916, kTBCount = 920;
 constexpr int kTLdsBytes = kTBias + kTBCount * 4;
+
+struct StepArgs {
+  const uint16_t* packed;  // forward and transposed fragments
+  const float* w;          // FP32 master parameters (biases)
+  const float* norm;
+  const float* params;  // [3][in_stride]
+  const float* u0;      // [3][in_stride]
+  const float* y;       // [48][in_stride]
+  const float* staged;  // or the set staged item-major ([in_stride][kStageW]), null
+  int64_t n, in_stride, first;
+  uint64_t mult, add;   // item q is row (mult (first + q) + add) mod in_stride
+  int64_t b_off[4];
+  uint16_t* a0;         // item-fragment outputs: inputs, A_1..A_3, G_1..G_4
+  uint16_t* act[3];
+  uint16_t* gb[4];
+  float* bpart[4];      // [blocks][width] bias-gradient partials
+  double* partial;      // [blocks] sums of (Y - T)^2
+  float scale;          // dLoss / dY = scale (Y - T)
+};
 
 __device__ inline bf16x8_t* act_slot(uint8_t* lds, int buf, int K, int lane) {
   return reinterpret_cast<bf16x8_t*>(lds + buf * kTAct + (K * 64 + lane) * 16);
@@ -438,12 +447,11 @@ __device__ inline bf16x8_t gfrag(const uint16_t* packed, int64_t frag_index, int
   return *reinterpret_cast<const bf16x8_t*>(packed + frag_index * kFrag + lane * 8);
 }
 
-// This wave's 64 rows of a layer: four 16-row blocks, their SiLU into the
-// output buffer (pairs K = 2w, 2w+1: features 32 K + 4 g + {0..3} and
-// 32 K + 16 + 4 g + {0..3}) and the transposition tile, Z into the item's
-// row (null: an item past the end of the batch).
-__device__ inline void train_rows(f32x4_t (&acc)[4], uint8_t* lds, int out_buf, __bf16* tile,
-                                  int wave, int g, int col, int lane, float* zrow) {
+// Forward: this wave's 64 rows of a layer, their SiLU into the pair buffer
+// (pairs K = 2w, 2w+1: features 32 K + 4 g + {0..3} and 32 K + 16 + 4 g +
+// {0..3}) and into the transposition tile.
+__device__ inline void train_rows(const f32x4_t (&acc)[4], uint8_t* lds, int out_buf,
+                                  __bf16* tile, int wave, int g, int col, int lane) {
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int K = 2 * wave + pp;
@@ -454,199 +462,8 @@ __device__ inline void train_rows(f32x4_t (&acc)[4], uint8_t* lds, int out_buf, 
       tile[(32 * K + 4 * g + r) * 16 + col] = v[r];
       tile[(32 * K + 16 + 4 * g + r) * 16 + col] = v[4 + r];
     }
-    if (zrow) {
-      float* zp = zrow + 32 * K + 4 * g;
-      *reinterpret_cast<f32x4_t*>(zp) = acc[2 * pp];
-      *reinterpret_cast<f32x4_t*>(zp + 16) = acc[2 * pp + 1];
-    }
   }
 }
-
-__global__ void __launch_bounds__(256) mlp_train_fwd(const FusedArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kTLdsBytes];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int g = lane >> 4, col = lane & 15;
-  const int64_t ns = a.in_stride;
-  const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
-  const bool live = q < a.n;
-  float* bw = reinterpret_cast<float*>(lds + kTBias);
-
-  // biases and normalisation first, so that their wait before the LDS
-  // stores does not wait for the loads issued after them
-  const float bh0 = a.w[a.b_off[0] + tid], bh1 = a.w[a.b_off[1] + tid],
-              bh2 = a.w[a.b_off[2] + tid];
-  float b4 = 0.f, om = 0.f, ois = 0.f, im = 0.f, iis = 0.f;
-  if (tid < kNO) {
-    b4 = a.w[a.b_off[3] + tid];
-    om = a.norm[kOutMean + tid];
-    ois = a.norm[kOutIStd + tid];
-  }
-  if (tid < 4) {
-    im = a.norm[kInMean + tid];
-    iis = a.norm[kInIStd + tid];
-  }
-  // the item's row, raw inputs (lane group 0) and, in waves 0..2, the four
-  // targets of outputs 16 w + 4 g + r this lane writes
-  int64_t row = 0;
-  float f[4] = {0.f, 0.f, 0.f, 0.f}, yt[4] = {0.f, 0.f, 0.f, 0.f};
-  if (live) {
-    row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
-    if (a.staged) {  // normalised already, one 208-byte record per item
-      const float* rec = a.staged + row * kStageW;
-      if (g == 0) {
-        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) f[k] = v[k];
-      }
-      if (wave < 3) {
-        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec + 4 + 16 * wave + 4 * g);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yt[r] = v[r];
-      }
-    } else {
-      if (g == 0) {
-        f[0] = a.params[ns + row];
-        f[1] = a.u0[row];
-        f[2] = a.u0[ns + row];
-        f[3] = a.u0[2 * ns + row];
-      }
-      if (wave < 3) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
-      }
-    }
-  }
-  // this wave's weights of layers 1 and 2
-  bf16x8_t w1[4], w[4][8];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) w1[j] = gfrag(a.packed, kP1 / kFrag + 4 * wave + j, lane);
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-      w[j][kb] = gfrag(a.packed, kP2 / kFrag + (4 * wave + j) * 8 + kb, lane);
-  bw[kTB1 + tid] = bh0;
-  bw[kTB2 + tid] = bh1;
-  bw[kTB3 + tid] = bh2;
-  if (tid < kNO) {
-    bw[kTB4 + tid] = b4;
-    bw[kTOutMean + tid] = om;
-    bw[kTOutIStd + tid] = ois;
-  }
-  if (tid < 4) {
-    bw[kTInMean + tid] = im;
-    bw[kTInIStd + tid] = iis;
-  }
-  __syncthreads();
-  float* zrow[3];
-#pragma unroll
-  for (int l = 0; l < 3; ++l) zrow[l] = live ? a.z[l] + q * kH : nullptr;
-  const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
-  const int64_t kb = blockIdx.x >> 1;  // item block of the item-fragment outputs
-  const int h = blockIdx.x & 1;
-  __bf16* small = reinterpret_cast<__bf16*>(lds + kTSmall);
-
-  // ---- layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane group 0
-  {
-    bf16x8_t xin;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float v = !(g == 0 && live) ? 0.f
-                      : a.staged       ? f[k]
-                                       : (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k];
-      xin[k] = (__bf16)v;
-      xin[4 + k] = (__bf16)0.0f;
-    }
-    if (wave == 0 && g == 0) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) small[k * 16 + col] = xin[k];
-    }
-    f32x4_t acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          w1[j], xin, *reinterpret_cast<const f32x4_t*>(bw + kTB1 + r0 + 16 * j), 0, 0, 0);
-    train_rows(acc, lds, 0, ttile(lds, 0), wave, g, col, lane, zrow[0]);
-  }
-  __syncthreads();
-  if_store(small, a.a0, kb, h, 1, 4, tid);
-  if_store(ttile(lds, 0), a.act[0], kb, h, 16, kH, tid);
-
-  // ---- layers 2 and 3
-  bf16x8_t x[8];
-#pragma unroll
-  for (int layer = 0; layer < 2; ++layer) {
-    const int in_buf = layer, out_buf = layer ^ 1;
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, in_buf, kb, lane);
-    f32x4_t acc[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      acc[j] = *reinterpret_cast<const f32x4_t*>(bw + (layer ? kTB3 : kTB2) + r0 + 16 * j);
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
-    if (layer == 0) {  // layer 3's rows, in flight while layer 2 finishes
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
-          w[j][kb] = gfrag(a.packed, kP3 / kFrag + (4 * wave + j) * 8 + kb, lane);
-    } else if (wave < 3) {  // layer 4's row block `wave`
-#pragma unroll
-      for (int kb = 0; kb < 8; ++kb) w[0][kb] = gfrag(a.packed, kP4 / kFrag + wave * 8 + kb, lane);
-    }
-    train_rows(acc, lds, out_buf, ttile(lds, out_buf), wave, g, col, lane, zrow[layer + 1]);
-    __syncthreads();
-    if_store(ttile(lds, out_buf), a.act[layer + 1], kb, h, 16, kH, tid);
-  }
-
-  // ---- layer 4: waves 0..2 take output rows 16 w .. 16 w + 15: normalised
-  // outputs Y and targets T, [item][48]
-  if (wave < 3) {
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, 0, kb, lane);
-    const int o0 = 16 * wave + 4 * g;
-    f32x4_t out = *reinterpret_cast<const f32x4_t*>(bw + kTB4 + o0);
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][kb], x[kb], out, 0, 0, 0);
-    if (live) {
-      *reinterpret_cast<f32x4_t*>(a.Y + q * kNO + o0) = out;
-      f32x4_t t;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        t[r] = a.staged ? yt[r] : (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
-      *reinterpret_cast<f32x4_t*>(a.T + q * kNO + o0) = t;
-    }
-  }
-}
-
-// ---- training backward -----------------------------------------------------
-// The same decomposition for the input gradients: a block takes 16 items,
-// wave w computes features 64 w .. 64 w + 63 of G_3, G_2 and G_1 from the
-// transposed weights (its 64 rows of W_l^T, contiguous in the packed copy,
-// straight into registers) and the previous gradient's eight k-blocks, read
-// back from LDS after one barrier per layer.  Each G is scaled by SiLU' of
-// the kept pre-activation, rounded to bf16 for the weight-gradient products
-// and the next layer, and summed over the block's 16 items (butterfly over
-// the lane group, FP32) into the bias-gradient partial of the block.  The
-// output gradient G_4 = scale (Y - T) and the loss partial (FP64) come from
-// the kept Y and T.
-struct BwdArgs {
-  const uint16_t* packed;
-  const float* Y;  // [n][48]
-  const float* T;  // [n][48]
-  const float* z[3];
-  uint16_t* gb[4];     // G_l [n][width] bf16
-  float* bpart[4];     // [blocks][width]
-  double* partial;     // [blocks]
-  int64_t n;
-  float scale;
-};
 
 __device__ inline float dsilu(float z) {
   const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
@@ -677,9 +494,9 @@ __device__ inline float sum16(float v) {
   return v;
 }
 
-// G = acc * silu'(Z) for this wave's 64 features (row blocks 4w + j): bf16
-// pairs into LDS (out_buf >= 0), bf16 into the transposition tile, the FP32
-// column sums into the block's partial row.
+// Backward: G = acc * silu'(Z) for this wave's 64 features (row blocks
+// 4w + j): bf16 pairs into the pair buffer (out_buf >= 0) and the
+// transposition tile, the FP32 column sums into the block's partial row.
 __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4], uint8_t* lds,
                                 int out_buf, __bf16* tile, int wave, int g, int col, int lane,
                                 int r0, float* bp) {
@@ -713,131 +530,255 @@ __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4],
     }
 }
 
-__global__ void __launch_bounds__(256) mlp_train_bwd(const BwdArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kTBias];
+// A hidden layer's products for this wave's four row blocks over the eight
+// k-blocks of the pair buffer in_buf, the accumulators starting from acc.
+__device__ inline void rows_mfma(f32x4_t (&acc)[4], const bf16x8_t (&w)[4][8], uint8_t* lds,
+                                 int in_buf, int lane) {
+  bf16x8_t x[8];
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, in_buf, kb, lane);
+#pragma unroll
+  for (int kb = 0; kb < 8; ++kb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
+}
+
+__device__ inline void load_rows(bf16x8_t (&w)[4][8], const uint16_t* packed, int64_t base_frag,
+                                 int wave, int lane) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) w[j][kb] = gfrag(packed, base_frag + (4 * wave + j) * 8 + kb, lane);
+}
+
+__global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
+  __shared__ __attribute__((aligned(16))) uint8_t lds[kTLdsBytes];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
+  const int64_t ns = a.in_stride;
   const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
   const bool live = q < a.n;
-  const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+  const int r0 = 64 * wave + 4 * g;    // this lane's first feature of its row blocks
   const int64_t kb = blockIdx.x >> 1;  // item block of the item-fragment outputs
   const int h = blockIdx.x & 1;
+  float* bw = reinterpret_cast<float*>(lds + kTBias);
   __bf16* small = reinterpret_cast<__bf16*>(lds + kTSmall);
 
-  // the output gradient's operands (outputs 16 h + 4 g + r), the kept
-  // pre-activations of this wave's features, the transposed weights of
-  // layers 4 and 3
-  f32x4_t yv[3], tv[3], zv[3][4];
-#pragma unroll
-  for (int hh = 0; hh < 3; ++hh) {
-    yv[hh] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    tv[hh] = yv[hh];
+  // biases and normalisation first, so that their wait before the LDS
+  // stores does not wait for the loads issued after them
+  const float bh0 = a.w[a.b_off[0] + tid], bh1 = a.w[a.b_off[1] + tid],
+              bh2 = a.w[a.b_off[2] + tid];
+  float b4 = 0.f, om = 0.f, ois = 0.f, im = 0.f, iis = 0.f;
+  if (tid < kNO) {
+    b4 = a.w[a.b_off[3] + tid];
+    om = a.norm[kOutMean + tid];
+    ois = a.norm[kOutIStd + tid];
   }
-#pragma unroll
-  for (int l = 0; l < 3; ++l)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) zv[l][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  if (tid < 4) {
+    im = a.norm[kInMean + tid];
+    iis = a.norm[kInIStd + tid];
+  }
+  // the item's row, inputs (lane group 0) and, in waves 0..2, the four
+  // targets of outputs 16 w + 4 g + r that this lane's output gradient uses
+  int64_t row = 0;
+  float f[4] = {0.f, 0.f, 0.f, 0.f}, yt[4] = {0.f, 0.f, 0.f, 0.f};
   if (live) {
+    row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
+    if (a.staged) {  // normalised already, one 208-byte record per item
+      const float* rec = a.staged + row * kStageW;
+      if (g == 0) {
+        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec);
 #pragma unroll
-    for (int hh = 0; hh < 3; ++hh) {
-      yv[hh] = *reinterpret_cast<const f32x4_t*>(a.Y + q * kNO + 16 * hh + 4 * g);
-      tv[hh] = *reinterpret_cast<const f32x4_t*>(a.T + q * kNO + 16 * hh + 4 * g);
+        for (int k = 0; k < 4; ++k) f[k] = v[k];
+      }
+      if (wave < 3) {
+        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec + 4 + 16 * wave + 4 * g);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yt[r] = v[r];
+      }
+    } else {
+      if (g == 0) {
+        f[0] = a.params[ns + row];
+        f[1] = a.u0[row];
+        f[2] = a.u0[ns + row];
+        f[3] = a.u0[2 * ns + row];
+      }
+      if (wave < 3) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+      }
+    }
+  }
+  // this wave's weights of layers 1 and 2
+  bf16x8_t w1[4], w[4][8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) w1[j] = gfrag(a.packed, kP1 / kFrag + 4 * wave + j, lane);
+  load_rows(w, a.packed, kP2 / kFrag, wave, lane);
+  bw[kTB1 + tid] = bh0;
+  bw[kTB2 + tid] = bh1;
+  bw[kTB3 + tid] = bh2;
+  if (tid < kNO) {
+    bw[kTB4 + tid] = b4;
+    bw[kTOutMean + tid] = om;
+    bw[kTOutIStd + tid] = ois;
+  }
+  if (tid < 4) {
+    bw[kTInMean + tid] = im;
+    bw[kTInIStd + tid] = iis;
+  }
+  __syncthreads();
+  f32x4_t z[3][4];  // pre-activations of this wave's features, kept for SiLU'
+  f32x4_t acc[4];
+
+  // ---- forward, layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane
+  // group 0
+  {
+    bf16x8_t xin;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float v = !(g == 0 && live) ? 0.f
+                      : a.staged       ? f[k]
+                                       : (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k];
+      xin[k] = (__bf16)v;
+      xin[4 + k] = (__bf16)0.0f;
+    }
+    if (wave == 0 && g == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) small[k * 16 + col] = xin[k];
     }
 #pragma unroll
-    for (int l = 2; l >= 0; --l)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        zv[l][j] = *reinterpret_cast<const f32x4_t*>(a.z[l] + q * kH + r0 + 16 * j);
+    for (int j = 0; j < 4; ++j)
+      z[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          w1[j], xin, *reinterpret_cast<const f32x4_t*>(bw + kTB1 + r0 + 16 * j), 0, 0, 0);
+    train_rows(z[0], lds, 0, ttile(lds, 0), wave, g, col, lane);
   }
-  bf16x8_t w4[4][2], w[4][8];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb) w4[j][kb] = gfrag(a.packed, kPackT4 / kFrag + (4 * wave + j) * 2 + kb, lane);
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-      w[j][kb] = gfrag(a.packed, kPackT3 / kFrag + (4 * wave + j) * 8 + kb, lane);
+  __syncthreads();
+  if_store(small, a.a0, kb, h, 1, 4, tid);
+  if_store(ttile(lds, 0), a.act[0], kb, h, 16, kH, tid);
 
-  // ---- G_4 = scale (Y - T): k-blocks 0 (outputs 0..31) and 1 (32..47, zero
-  // padded) of the first product, the loss and the output bias partial
-  float gv[12];
-  double d2 = 0.0;
+  // ---- layer 2
 #pragma unroll
-  for (int hh = 0; hh < 3; ++hh)
+  for (int j = 0; j < 4; ++j) z[1][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB2 + r0 + 16 * j);
+  rows_mfma(z[1], w, lds, 0, lane);
+  load_rows(w, a.packed, kP3 / kFrag, wave, lane);  // layer 3, in flight meanwhile
+  train_rows(z[1], lds, 1, ttile(lds, 1), wave, g, col, lane);
+  __syncthreads();
+  if_store(ttile(lds, 1), a.act[1], kb, h, 16, kH, tid);
+
+  // ---- layer 3
+#pragma unroll
+  for (int j = 0; j < 4; ++j) z[2][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB3 + r0 + 16 * j);
+  rows_mfma(z[2], w, lds, 1, lane);
+  bf16x8_t w4[8], w4t[4][2];  // layer 4's row block `wave` (waves 0..2), W_4^T rows
+  if (wave < 3) {
+#pragma unroll
+    for (int kb4 = 0; kb4 < 8; ++kb4) w4[kb4] = gfrag(a.packed, kP4 / kFrag + wave * 8 + kb4, lane);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int k2 = 0; k2 < 2; ++k2)
+      w4t[j][k2] = gfrag(a.packed, kPackT4 / kFrag + (4 * wave + j) * 2 + k2, lane);
+  train_rows(z[2], lds, 0, ttile(lds, 0), wave, g, col, lane);
+  __syncthreads();
+  if_store(ttile(lds, 0), a.act[2], kb, h, 16, kH, tid);
+
+  // ---- layer 4 and the loss (waves 0..2: outputs 16 w .. 16 w + 15):
+  // G_4 = scale (Y - T) into the small tile, the operand pieces, the output
+  // bias partial and the block's loss partial
+  if (wave < 3) {
+    bf16x8_t x[8];
+#pragma unroll
+    for (int k8 = 0; k8 < 8; ++k8) x[k8] = *act_slot(lds, 0, k8, lane);
+    const int o0 = 16 * wave + 4 * g;
+    f32x4_t out = *reinterpret_cast<const f32x4_t*>(bw + kTB4 + o0);
+#pragma unroll
+    for (int k8 = 0; k8 < 8; ++k8)
+      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[k8], x[k8], out, 0, 0, 0);
+    load_rows(w, a.packed, kPackT3 / kFrag, wave, lane);  // W_3^T for G_2, in flight
+    float gg[4];
+    double d2 = 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float d = yv[hh][r] - tv[hh][r];
-      gv[4 * hh + r] = a.scale * d;
+      const float t = !live ? 0.f
+                      : a.staged ? yt[r]
+                                 : (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
+      const float d = live ? out[r] - t : 0.f;
+      gg[r] = a.scale * d;
       d2 += (double)d * d;
+      small[(o0 + r) * 16 + col] = (__bf16)gg[r];
     }
-  bf16x8_t x4[2];
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    x4[0][e] = (__bf16)gv[e];
-    x4[1][e] = e < 4 ? (__bf16)gv[8 + e] : (__bf16)0.0f;
-  }
-  if (wave == 0) {
-#pragma unroll
-    for (int hh = 0; hh < 3; ++hh)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) small[(16 * hh + 4 * g + r) * 16 + col] = (__bf16)gv[4 * hh + r];
+    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<bf16x4_t*>(lds + kTG4 + (wave * 64 + lane) * 8) =
+        bf16x4_t{(__bf16)gg[0], (__bf16)gg[1], (__bf16)gg[2], (__bf16)gg[3]};
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 += __shfl_xor(d2, m);
-    if (lane == 0) a.partial[blockIdx.x] = d2;
+    if (lane == 0) reinterpret_cast<double*>(lds + kTLoss)[wave] = d2;
     float* bp = a.bpart[3] + (int64_t)blockIdx.x * kNO;
 #pragma unroll
-    for (int hh = 0; hh < 3; ++hh)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float t = sum16(gv[4 * hh + r]);
-        if (col == 0) bp[16 * hh + 4 * g + r] = t;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const float t = sum16(gg[r]);
+      if (col == 0) bp[o0 + r] = t;
+    }
+  } else {
+    load_rows(w, a.packed, kPackT3 / kFrag, wave, lane);
   }
+  __syncthreads();
+  if (tid == 0) {
+    const double* lp = reinterpret_cast<const double*>(lds + kTLoss);
+    a.partial[blockIdx.x] = (lp[0] + lp[1]) + lp[2];
+  }
+  if_store(small, a.gb[3], kb, h, 3, kNO, tid);
 
-  // ---- G_3 = (G_4 W_4) * silu'(Z_3), K = 48
-  f32x4_t acc[4];
+  // ---- backward: G_3 = (G_4 W_4) * silu'(Z_3), K = 48 (k-block 1 half
+  // zero): lane (g, col) takes outputs 4g.., 16+4g.. and 32+4g.. from the
+  // pieces of waves 0, 1, 2
+  {
+    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+    const bf16x4_t p0 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (0 * 64 + lane) * 8);
+    const bf16x4_t p1 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (1 * 64 + lane) * 8);
+    const bf16x4_t p2 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (2 * 64 + lane) * 8);
+    bf16x8_t x4[2];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < 4; ++e) {
+      x4[0][e] = p0[e];
+      x4[0][4 + e] = p1[e];
+      x4[1][e] = p2[e];
+      x4[1][4 + e] = (__bf16)0.0f;
+    }
 #pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[j][kb], x4[kb], acc[j], 0, 0, 0);
+    for (int j = 0; j < 4; ++j) {
+      acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k2 = 0; k2 < 2; ++k2)
+        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4t[j][k2], x4[k2], acc[j], 0, 0, 0);
+    }
   }
-  bwd_rows(acc, zv[2], lds, 0, ttile(lds, 0), wave, g, col, lane, r0,
+  bwd_rows(acc, z[2], lds, 1, ttile(lds, 1), wave, g, col, lane, r0,
            a.bpart[2] + (int64_t)blockIdx.x * kH);
   __syncthreads();
-  if_store(small, a.gb[3], kb, h, 3, kNO, tid);
-  if_store(ttile(lds, 0), a.gb[2], kb, h, 16, kH, tid);
+  if_store(ttile(lds, 1), a.gb[2], kb, h, 16, kH, tid);
 
-  // ---- G_2 = (G_3 W_3) * silu'(Z_2), then G_1 = (G_2 W_2) * silu'(Z_1)
-  bf16x8_t x[8];
+  // ---- G_2 = (G_3 W_3) * silu'(Z_2)
 #pragma unroll
-  for (int step = 0; step < 2; ++step) {
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  rows_mfma(acc, w, lds, 1, lane);
+  load_rows(w, a.packed, kPackT2 / kFrag, wave, lane);  // W_2^T, in flight meanwhile
+  bwd_rows(acc, z[1], lds, 0, ttile(lds, 0), wave, g, col, lane, r0,
+           a.bpart[1] + (int64_t)blockIdx.x * kH);
+  __syncthreads();
+  if_store(ttile(lds, 0), a.gb[1], kb, h, 16, kH, tid);
+
+  // ---- G_1 = (G_2 W_2) * silu'(Z_1)
 #pragma unroll
-    for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, step, kb, lane);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 8; ++kb)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
-    if (step == 0) {  // W_2^T, in flight while G_2 is finished
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-#pragma unroll
-        for (int kb = 0; kb < 8; ++kb)
-          w[j][kb] = gfrag(a.packed, kPackT2 / kFrag + (4 * wave + j) * 8 + kb, lane);
-    }
-    const int l = 1 - step;  // G_2 (gb[1], Z_2, tile 1) then G_1 (gb[0], Z_1, tile 0)
-    bwd_rows(acc, zv[l], lds, step == 0 ? 1 : -1, ttile(lds, 1 - step), wave, g, col, lane, r0,
-             a.bpart[l] + (int64_t)blockIdx.x * kH);
-    __syncthreads();
-    if_store(ttile(lds, 1 - step), a.gb[l], kb, h, 16, kH, tid);
-  }
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  rows_mfma(acc, w, lds, 0, lane);
+  bwd_rows(acc, z[0], lds, -1, ttile(lds, 1), wave, g, col, lane, r0,
+           a.bpart[0] + (int64_t)blockIdx.x * kH);
+  __syncthreads();
+  if_store(ttile(lds, 1), a.gb[0], kb, h, 16, kH, tid);
 }
 
 // ---- staged training set ---------------------------------------------------
@@ -1058,67 +999,43 @@ hipError_t mlp_forward_fused_list(const MlpLayout& L, const uint16_t* packed, co
   return hipGetLastError();
 }
 
-// The training forward: one block per 16 items.
-hipError_t mlp_forward_train(const uint16_t* packed, const float* w, const MlpLayout& L,
-                             const float* norm, const float* params, const float* u0,
-                             const float* y, int64_t n, int64_t first, int64_t B, uint64_t mult,
-                             uint64_t add, uint16_t* a0, MlpActs& acts, float* Y, float* T,
-                             const float* staged, hipStream_t s) {
+// The training step's fused launch: one block per 16 items, whole 32-item
+// blocks of the item-fragment outputs.
+hipError_t mlp_train_fused(const uint16_t* packed, const float* w, const MlpLayout& L,
+                           const float* norm, const float* params, const float* u0,
+                           const float* y, const float* staged, int64_t n, int64_t first,
+                           int64_t B, uint64_t mult, uint64_t add, uint16_t* a0, MlpActs& acts,
+                           GradParts& parts, double* partial, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
       L.dims[3] != kH || L.dims[4] != kNO || n <= 0)
     return hipErrorInvalidValue;
-  FusedArgs a{};
+  const int64_t blocks = 2 * ((B + 31) / 32);
+  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  StepArgs a{};
   a.packed = packed;
   a.w = w;
   a.norm = norm;
   a.params = params;
   a.u0 = u0;
+  a.y = y;
+  a.staged = staged;
   a.n = B;
   a.in_stride = n;
-  a.y = y;
+  a.first = first;
   a.mult = mult % (uint64_t)n;
   a.add = add % (uint64_t)n;
-  a.first = first;
-  a.a0 = a0;
-  for (int l = 0; l < 3; ++l) {
-    a.z[l] = acts.z[l];
-    a.act[l] = acts.act[l];
-  }
-  a.Y = Y;
-  a.T = T;
-  a.staged = staged;
   for (int l = 0; l < 4; ++l) a.b_off[l] = L.b_off[l];
-  const int64_t blocks = 2 * ((B + 31) / 32);  // whole item blocks of the fragment outputs
-  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(mlp_train_fwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-// The training backward: one block per 16 items, as the forward.
-hipError_t mlp_backward_train(const uint16_t* packed, const MlpLayout& L, int64_t B,
-                              MlpActs& acts, const float* Y, const float* T, GradParts& parts,
-                              double* partial, hipStream_t s) {
-  if (B <= 0) return hipSuccess;
-  if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
-      L.dims[3] != kH || L.dims[4] != kNO)
-    return hipErrorInvalidValue;
-  const int64_t blocks = 2 * ((B + 31) / 32);  // whole item blocks of the fragment outputs
-  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-  parts.tiles = (int)blocks;
-  BwdArgs a{};
-  a.packed = packed;
-  a.Y = Y;
-  a.T = T;
-  for (int l = 0; l < 3; ++l) a.z[l] = acts.z[l];
+  a.a0 = a0;
+  for (int l = 0; l < 3; ++l) a.act[l] = acts.act[l];
   for (int l = 0; l < 4; ++l) {
     a.gb[l] = acts.gb[l];
     a.bpart[l] = parts.b[l];
   }
   a.partial = partial;
-  a.n = B;
   a.scale = (float)(2.0 / (double)(B * kNO));
-  hipLaunchKernelGGL(mlp_train_bwd, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  parts.tiles = (int)blocks;
+  hipLaunchKernelGGL(mlp_train_step, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

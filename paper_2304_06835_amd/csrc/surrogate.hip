@@ -361,13 +361,11 @@ int train_step(ens_ctx* c, ens_surrogate* s, const float* params, const float* u
   hipError_t e;
   ens::GradParts parts;
   if (c->mlp_tile != 0) {
-    // gather + forward, then loss + input gradients, one feature-split
-    // launch each; the weight gradients' grouped product; Adam
+    // gather, forward, loss and input gradients in one feature-split
+    // launch; the weight gradients (and bias sums) in one more; Adam
     parts = grad_parts(s, 2 * ((B + 31) / 32));
-    e = ens::mlp_forward_train(s->packed, s->w, s->L, s->norm, params, u0, y, n, first, B, mult,
-                               add, s->a0, acts, s->Y, s->T, staged, st);
-    if (e == hipSuccess)
-      e = ens::mlp_backward_train(s->packed, s->L, B, acts, s->Y, s->T, parts, s->partial, st);
+    e = ens::mlp_train_fused(s->packed, s->w, s->L, s->norm, params, u0, y, staged, n, first,
+                             B, mult, add, s->a0, acts, parts, s->partial, st);
     if (e == hipSuccess && loss)
       e = ens::mlp_loss_sum(s->partial, parts.tiles, 1.0 / (double)(B * kDims[4]), loss, st);
     if (e == hipSuccess) e = ens::mlp_weight_grads_if(s->L, B, acts, s->a0, parts, st);
