@@ -49,16 +49,22 @@ struct MlpActs {
   uint16_t* gb[kMlpMaxLayers];  // training: bf16 output gradient G_l of every layer
 };
 
-// Split-K factor of the weight-gradient products (K = batch).
+// Split-K factors of the weight-gradient products (K = batch): the tiled
+// path's and the fused path's (whose direct-load kernel has the shorter K
+// loop per block and so takes fewer, longer ranges); buffers are sized for
+// the larger.
 constexpr int kSplits = 16;
+constexpr int kSplitsFused = 8;
+static_assert(kSplitsFused <= kSplits, "partial buffers hold kSplits ranges");
 
 // Gradient partials of one training step, summed by the Adam kernel:
-// w[l] [kSplits][dims[l+1] * dims[l]] split-K partials of dW_l, b[l]
-// [tiles][dims[l+1]] partials of db_l over 64-row blocks of the batch.
+// w[l] [splits][dims[l+1] * dims[l]] split-K partials of dW_l, b[l]
+// [tiles][dims[l+1]] partials of db_l over blocks of the batch.
 struct GradParts {
   float* w[kMlpMaxLayers];
   float* b[kMlpMaxLayers];
   int tiles;
+  int splits;
 };
 
 struct RowSet {

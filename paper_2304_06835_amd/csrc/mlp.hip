@@ -367,10 +367,11 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
       const float* q = P.w[l] + (p - L.w_off[l]);
       float t[kSplits];  // all loads in flight, then the fixed-order sum
 #pragma unroll
-      for (int z = 0; z < kSplits; ++z) t[z] = q[(int64_t)z * nw];
+      for (int z = 0; z < kSplits; ++z) t[z] = z < P.splits ? q[(int64_t)z * nw] : 0.0f;
       gg = t[0];
 #pragma unroll
-      for (int z = 1; z < kSplits; ++z) gg += t[z];
+      for (int z = 1; z < kSplits; ++z)
+        if (z < P.splits) gg += t[z];
     } else if (p >= L.b_off[l] && p < L.b_off[l] + nb) {
       const float* q = P.b[l] + (p - L.b_off[l]);
       int t = 0;
@@ -633,6 +634,7 @@ hipError_t mlp_loss_sum(const double* partial, int64_t count, double factor, flo
 hipError_t mlp_weight_grads(const MlpLayout& L, const uint16_t* a0, int64_t B, MlpActs& acts,
                             GradParts& parts, hipStream_t s) {
   const int nl = L.layers;
+  parts.splits = kSplits;
   GemmGroup G{};
   G.count = nl;
   int64_t blocks = 0;

@@ -821,12 +821,12 @@ __global__ void __launch_bounds__(256) stage_items(const float* params, const fl
 // A_{l-1} the B operand for 16 columns i, so every wave reads its operands
 // with 16-byte loads straight into registers and no LDS is involved.  A
 // block takes a 64 x 64 tile of one layer's dW (wave (wm, wn) a 32 x 32
-// quarter) over one of kSplits item ranges and writes that range's partial;
+// quarter) over one of kSplitsFused item ranges and writes that range's partial;
 // the Adam kernel sums the partials.
 struct DwProblem {
   const uint16_t* G;  // item-fragment layout, nfo feature blocks
   const uint16_t* A;  // item-fragment layout, nfi feature blocks
-  float* C;           // [kSplits][M][N]
+  float* C;           // [kSplitsFused][M][N]
   int M, N, nfo, nfi, tiles_m, tiles_n;
   int64_t block0;
 };
@@ -1048,7 +1048,8 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
   DwGroup D{};
   D.count = L.layers;
   D.nkb = (B + 31) / 32;
-  D.kc = (D.nkb + kSplits - 1) / kSplits;
+  D.kc = (D.nkb + kSplitsFused - 1) / kSplitsFused;
+  parts.splits = kSplitsFused;
   int64_t blocks = 0;
   for (int l = 0; l < L.layers; ++l) {
     DwProblem& P = D.p[l];
@@ -1062,7 +1063,7 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     P.tiles_m = (P.M + 63) / 64;
     P.tiles_n = (P.N + 63) / 64;
     P.block0 = blocks;
-    blocks += (int64_t)P.tiles_m * P.tiles_n * kSplits;
+    blocks += (int64_t)P.tiles_m * P.tiles_n * kSplitsFused;
   }
   // bias blocks: each layer's biases in whole 64-bias blocks
   D.bias_block0 = blocks;
