@@ -17,8 +17,10 @@
 // epilogues (bias, SiLU, bf16 rounding, SiLU', de-normalisation into the
 // structure-of-arrays output, the bias gradient's column sums) are fused into
 // the tile's store; the weight gradients' split-K partials and the bias
-// partials are summed inside the Adam kernel, so a training step is eleven
-// products and three small kernels (gather, loss, Adam).
+// partials are summed inside the Adam kernel, so a training step on this
+// layer-by-layer path is eleven products and three small kernels (gather,
+// loss, Adam).  The default training path is the fused one in
+// mlp_fused.hip, which shares the Adam kernel.
 #include "../../include/ens.h"
 #include "ens_internal.h"
 #include "mlp.h"

@@ -1,5 +1,7 @@
-// mlp_fused.hip -- inference of the surrogate MLP (rho, x0, y0, z0) -> 256 ->
-// 256 -> 256 -> 48 in one persistent kernel.
+// mlp_fused.hip -- the fused kernels of the surrogate MLP (rho, x0, y0, z0)
+// -> 256 -> 256 -> 256 -> 48: inference in one persistent kernel (below), and
+// the training step (forward, loss and input gradients of a minibatch in one
+// kernel, the weight gradients in another; see "training step").
 //
 // Layer l computes Z_l = W_l A_{l-1} + b_l for a tile of queries on the
 // matrix cores (v_mfma_f32_16x16x32_bf16: bf16 operands, FP32 accumulation)
