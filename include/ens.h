@@ -395,7 +395,9 @@ int ens_surrogate_fit_norm(ens_ctx *ctx, ens_surrogate *s, const float *params,
  * minibatch of items first .. first+batch-1, item b being trajectory
  * (mult * b + add) mod n (mult coprime with n: a permutation of the set).
  * Loss = mean squared error of the normalised outputs; written to *loss
- * (device float) when loss is not NULL.                                      */
+ * (device float) when loss is not NULL.  batch <= ENS_SURR_MAX_BATCH, else
+ * ENS_EINVAL (here and in ens_surrogate_train).                              */
+#define ENS_SURR_MAX_BATCH 268435456LL /* 2^28 */
 int ens_surrogate_train_step(ens_ctx *ctx, ens_surrogate *s,
                              const float *params, const float *u0,
                              const float *y, int64_t n, int64_t first,

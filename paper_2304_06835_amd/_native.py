@@ -28,6 +28,7 @@ EXPORTS = ("ens_create", "ens_destroy", "ens_last_error", "ens_set_option",
            "ens_surrogate_load", "ens_surrogate_solve_static")
 SURR_BUFFERS = {"master": 1, "weights_bf16": 2, "grad": 3, "adam_m": 4, "adam_v": 5, "norm": 6}
 SURR_NPARAM = 145200
+SURR_MAX_BATCH = 1 << 28  # ENS_SURR_MAX_BATCH
 
 
 class EnsError(RuntimeError):

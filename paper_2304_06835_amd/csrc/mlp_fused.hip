@@ -790,12 +790,10 @@ __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
 // minibatch gather reads 208 contiguous bytes per item instead of one
 // scattered line from each of 52 rows.  A block takes 64 items: coalesced
 // reads of the 52 rows into an LDS tile, then contiguous record writes.
-__global__ void __launch_bounds__(256) stage_items(const float* params, const float* u0,
-                                                   const float* y, int64_t n, const float* norm,
-                                                   float* D) {
-  __shared__ float tile[64][kStageW + 1];
-  const int tid = threadIdx.x;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
+// One 64-item tile of stage_items (the grid strides over tiles).
+__device__ inline void stage_tile(const float* params, const float* u0, const float* y,
+                                  int64_t n, const float* norm, float* D,
+                                  float (&tile)[64][kStageW + 1], int64_t i0, int tid) {
   for (int e = tid; e < 64 * kStageW; e += 256) {
     const int c = e >> 6, i = e & 63;
     const int64_t it = i0 + i;
@@ -814,6 +812,17 @@ __global__ void __launch_bounds__(256) stage_items(const float* params, const fl
   __syncthreads();
   const int64_t items = n - i0 < 64 ? n - i0 : 64;
   for (int e = tid; e < items * kStageW; e += 256) D[i0 * kStageW + e] = tile[e / kStageW][e % kStageW];
+  __syncthreads();  // the tile is refilled by the next iteration
+}
+
+__global__ void __launch_bounds__(256) stage_items(const float* params, const float* u0,
+                                                   const float* y, int64_t n, const float* norm,
+                                                   float* D) {
+  __shared__ float tile[64][kStageW + 1];
+  const int tid = threadIdx.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * 64; i0 < n; i0 += (int64_t)gridDim.x * 64) {
+    stage_tile(params, u0, y, n, norm, D, tile, i0, tid);
+  }
 }
 
 // ---- weight gradients ------------------------------------------------------
@@ -1013,7 +1022,7 @@ hipError_t mlp_train_fused(const uint16_t* packed, const float* w, const MlpLayo
       L.dims[3] != kH || L.dims[4] != kNO || n <= 0)
     return hipErrorInvalidValue;
   const int64_t blocks = 2 * ((B + 31) / 32);
-  if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+  if (blocks > (1LL << 24)) return hipErrorInvalidValue;  // blocks x 256 work-items fit 32 bits
   StepArgs a{};
   a.packed = packed;
   a.w = w;
@@ -1084,8 +1093,9 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
 hipError_t mlp_stage_items(const float* params, const float* u0, const float* y, int64_t n,
                            const float* norm, float* D, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(stage_items, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, params, u0, y,
-                     n, norm, D);
+  const int64_t tiles = (n + 63) / 64;
+  hipLaunchKernelGGL(stage_items, dim3((unsigned)(tiles < 65536 ? tiles : 65536)), dim3(256), 0, s,
+                     params, u0, y, n, norm, D);
   return hipGetLastError();
 }
 

@@ -816,8 +816,8 @@ int ens_surrogate_train_step(ens_ctx* c, ens_surrogate* s, const float* params, 
                              uint64_t mult, uint64_t add, double lr, float* loss, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > ENS_MAX_TRAJ || !params || !u0 || !y ||
-      !(lr >= 0.0))
+  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > ENS_SURR_MAX_BATCH || !params || !u0 ||
+      !y || !(lr >= 0.0))
     return fail(c, ENS_EINVAL, "bad training arguments");
   if (gcd(mult % (uint64_t)n, (uint64_t)n) != 1 && n > 1)
     return fail(c, ENS_EINVAL, "mult must be coprime with n (a permutation of the set)");
@@ -831,7 +831,8 @@ int ens_surrogate_train(ens_ctx* c, ens_surrogate* s, const float* params, const
                         double lr_min, uint64_t seed, float* epoch_loss, void* stream) {
   int rc = check_model(c, s);
   if (rc != ENS_OK) return rc;
-  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > n || epochs < 1 || !params || !u0 || !y ||
+  if (n < 1 || n > ENS_MAX_TRAJ || batch < 1 || batch > n || batch > ENS_SURR_MAX_BATCH ||
+      epochs < 1 || !params || !u0 || !y ||
       !(lr_max >= lr_min) || !(lr_min >= 0.0))
     return fail(c, ENS_EINVAL, "bad training arguments");
   DeviceGuard g(c->device);

@@ -96,6 +96,7 @@ def test_binding_constants_match_header():
     surr = header_constants("ENS_SURR_")
     assert {k: surr[k] for k in _native.SURR_BUFFERS} == _native.SURR_BUFFERS
     assert surr["nparam"] == _native.SURR_NPARAM
+    assert surr["max_batch"] == _native.SURR_MAX_BATCH == 2**28
 
 
 

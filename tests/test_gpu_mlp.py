@@ -288,6 +288,23 @@ def test_train_call_equals_its_steps(ens):
     torch.cuda.synchronize()
 
 
+def test_training_argument_limits(ens):
+    """A batch beyond ENS_SURR_MAX_BATCH (one fused block per 16 items must
+    keep the launch's work-items within 32 bits) and a batch larger than the
+    set in ens_surrogate_train are refused before anything runs."""
+    from paper_2304_06835_amd import _native
+    e = W.lorenz_fp32(N=64, seed=19)
+    y = np.zeros((48, e.n), dtype=np.float32)
+    P, U, Y = to_dev(e.params), to_dev(e.u0), to_dev(y)
+    s, m = make_model(ens, random_theta(9))
+    before = to_host(m.buffer("master"))
+    with pytest.raises(ens.EnsError, match="bad training arguments"):
+        m.train_step(P, U, Y, first=0, batch=_native.SURR_MAX_BATCH + 1)
+    with pytest.raises(ens.EnsError, match="bad training arguments"):
+        m.train(P, U, Y, epochs=1, batch=e.n + 1)
+    assert np.array_equal(to_host(m.buffer("master")), before) and m.step == 0
+
+
 def test_affine_minibatch_selection(ens):
     """Item b of a minibatch is trajectory (mult*(first+b) + add) mod n."""
     th = random_theta(4, scale=0.5)
