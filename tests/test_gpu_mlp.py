@@ -129,15 +129,19 @@ def test_fused_forward_matches_tiled_path_across_many_tiles(ens, tile):
 
 @pytest.mark.parametrize("tile", [13, 0])
 @pytest.mark.parametrize("B,N,mult,add", [(777, 1500, 1, 0), (65, 1500, 1, 0),
-                                          (4096, 1 << 18, 100003, 12345)])
+                                          (4096, 1 << 18, 100003, 12345),
+                                          (20011, 1 << 18, 7, 3)])
 def test_gradient_and_adam_match_oracle(ens, B, N, mult, add, tile):
     """One training step: loss, every gradient element (B = 777: twelve
     64-sample tiles and a 9-sample tail; B = 65: one tile and a 1-sample
     tail, so the edge handling of the products and of the split-K weight
     gradients is pinned; B = 4096: the training minibatch, drawn by an
-    affine permutation of 2^18 trajectories), and Adam's update from the
-    GPU's own gradient.  tile 13: the minibatch gather and forward pass in
-    one fused launch; 0: the gather kernel and layer-by-layer products."""
+    affine permutation of 2^18 trajectories; B = 20,011: more fused blocks
+    than CUs, several operand rounds per weight-gradient wave and a ragged
+    last item block), and Adam's update from the GPU's own gradient.
+    tile 13: the fused path (one launch for the gather, forward, loss and
+    input gradients, one for the weight gradients); 0: the gather kernel
+    and layer-by-layer products."""
     th = random_theta(2, scale=0.5)
     e = W.lorenz_fp32(N=N, seed=12)
     rng = np.random.default_rng(3)
