@@ -150,7 +150,9 @@ typedef struct ens_ctx ens_ctx;
                                16-query subtiles per wave and one wave per SIMD
                                (2, 3, 4), or 2 or 3 subtiles and two waves per
                                SIMD (12, 13; default 13); 0: the layer-by-layer
-                               tiled-product path                             */
+                               tiled-product path.  Training: any non-zero value
+                               selects the fused training kernels, 0 the tiled
+                               products                                       */
 #define ENS_OPT_SAVE_MODE 13 /* 0 (default): steps land on every save time;
                                 1 (ENS_ALG_TSIT5 only, else ENS_EUNSUPPORTED):
                                 steps land on the last save time only and the
