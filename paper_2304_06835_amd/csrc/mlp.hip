@@ -362,8 +362,8 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
   for (int l = 0; l < L.layers; ++l) {
     const int64_t nw = (int64_t)L.dims[l] * L.dims[l + 1], nb = L.dims[l + 1];
     if (p >= L.w_off[l] && p < L.w_off[l] + nw) {
-      const int64_t e = p - L.w_off[l];
-      const int row = (int)(e / L.dims[l]), col = (int)(e % L.dims[l]);
+      const int e = (int)(p - L.w_off[l]);  // < dims[l] * dims[l+1]: 32-bit division
+      const int row = e / L.dims[l], col = e - row * L.dims[l];
       pk = packed_pos(l, row, col);
       if (l > 0) pt = packed_pos_t(l, row, col);
       const float* q = P.w[l] + (p - L.w_off[l]);
