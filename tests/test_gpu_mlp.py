@@ -127,6 +127,31 @@ def test_fused_forward_matches_tiled_path_across_many_tiles(ens, tile):
     assert np.abs(g - Y).max() / np.abs(Y).max() <= FWD_BAR
 
 
+def test_fused_forward_at_the_benchmarked_size(ens):
+    """Inference in the launch the benchmark times: the default fused
+    kernel <3, 8> on 2^24 queries (43,691 tiles of 384 over 256 persistent
+    blocks, a ragged last tile), checked against the bf16-emulating oracle
+    on 4096 queries spread over every block's tiles, and every output
+    finite."""
+    import torch
+    banner("fused forward 2^24 queries <3,8>")
+    th = random_theta(5)
+    e = W.lorenz_fp32(seed=W.SEEDS["surr_query"])
+    assert e.n == 1 << 24
+    s, m = make_model(ens, th)
+    assert s.get("mlp_tile") == 13
+    out = m.predict(to_dev(e.params), to_dev(e.u0))
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(out).all())
+    idx = np.unique(np.concatenate([np.linspace(0, e.n - 1, 4000).astype(np.int64),
+                                    np.arange(e.n - 96, e.n)]))
+    got = to_host(out.view(48, -1)[:, torch.from_numpy(idx).cuda()]).T
+    Y, _ = mlp.forward(th, features(e.params[:, idx], e.u0[:, idx]), bf16=True)
+    err = np.abs(got - Y).max() / np.abs(Y).max()
+    print("2^24 queries: max rel %.3e on %d sampled" % (err, len(idx)))
+    assert err <= FWD_BAR
+
+
 @pytest.mark.parametrize("tile", [13, 0])
 @pytest.mark.parametrize("B,N,mult,add", [(777, 1500, 1, 0), (65, 1500, 1, 0),
                                           (4096, 1 << 18, 100003, 12345),
