@@ -434,13 +434,20 @@ __device__ inline __bf16* ttile(uint8_t* lds, int t) {
 // zero) into the item-fragment layout of mlp.h: entry (fb, g', r16) of the
 // fragment, g' = 2h or 2h + 1, holds 8 consecutive items of one feature,
 // 16 contiguous bytes in the tile.  32 nfb entries over the block's threads.
+// Non-temporal stores: the next kernel reads these from other XCDs anyway,
+// and lines left dirty in this XCD's L2 would have to be written back when
+// the kernel ends (measured: the step kernel 18.9 -> 16.4 us, the weight-
+// gradient kernel that reads them 9.3 -> 10.3 us).
 __device__ inline void if_store(const __bf16* tile, uint16_t* dst, int64_t kb, int h, int nfb,
                                 int real, int tid) {
+  typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
   for (int E = tid; E < 32 * nfb; E += 256) {
     const int fb = E >> 5, w = E & 31, r16 = w & 15, hi = w >> 4, f = 16 * fb + r16;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (f < real) v = *reinterpret_cast<const uint4*>(tile + f * 16 + 8 * hi);
-    *reinterpret_cast<uint4*>(dst + ((kb * nfb + fb) * kPackFrag + (16 * (2 * h + hi) + r16) * 8)) = v;
+    u32x4_t v = u32x4_t{0u, 0u, 0u, 0u};
+    if (f < real) v = *reinterpret_cast<const u32x4_t*>(tile + f * 16 + 8 * hi);
+    __builtin_nontemporal_store(
+        v, reinterpret_cast<u32x4_t*>(
+               dst + ((kb * nfb + fb) * kPackFrag + (16 * (2 * h + hi) + r16) * 8)));
   }
 }
 
