@@ -50,16 +50,17 @@ struct MlpActs {
 };
 
 // Split-K factors of the weight-gradient products (K = batch): the tiled
-// path's and the fused path's (whose direct-load kernel has the shorter K
-// loop per block and so takes fewer, longer ranges); buffers are sized for
-// the larger.
+// path's, and the fused path's range of them -- about 16 item blocks of 32
+// per range, so a small batch takes few, longer ranges and a large one
+// enough blocks to hide its loads; buffers are sized for the largest.
 constexpr int kSplits = 16;
-constexpr int kSplitsFused = 8;
-static_assert(kSplitsFused <= kSplits, "partial buffers hold kSplits ranges");
+constexpr int kSplitsFusedMin = 8, kSplitsMax = 64;  // multiples of 8 (XCD-aware order)
+static_assert(kSplits <= kSplitsMax, "partial buffers hold kSplitsMax ranges");
 
 // Gradient partials of one training step, summed by the Adam kernel:
-// w[l] [splits][dims[l+1] * dims[l]] split-K partials of dW_l, b[l]
-// [tiles][dims[l+1]] partials of db_l over blocks of the batch.
+// w[l] [splits][dims[l+1] * dims[l]] split-K partials of dW_l (room for
+// kSplitsMax), b[l] [tiles][dims[l+1]] partials of db_l over blocks of the
+// batch.
 struct GradParts {
   float* w[kMlpMaxLayers];
   float* b[kMlpMaxLayers];

@@ -367,13 +367,20 @@ __global__ void adam_step(float* w, float* m, float* v, float* g, uint16_t* wb,
       pk = packed_pos(l, row, col);
       if (l > 0) pt = packed_pos_t(l, row, col);
       const float* q = P.w[l] + (p - L.w_off[l]);
-      float t[kSplits];  // all loads in flight, then the fixed-order sum
+      float t[16];  // 16 loads in flight per round, summed in split order
 #pragma unroll
-      for (int z = 0; z < kSplits; ++z) t[z] = z < P.splits ? q[(int64_t)z * nw] : 0.0f;
+      for (int z = 0; z < 16; ++z) t[z] = z < P.splits ? q[(int64_t)z * nw] : 0.0f;
       gg = t[0];
 #pragma unroll
-      for (int z = 1; z < kSplits; ++z)
+      for (int z = 1; z < 16; ++z)
         if (z < P.splits) gg += t[z];
+      for (int z0 = 16; z0 < P.splits; z0 += 16) {
+#pragma unroll
+        for (int z = 0; z < 16; ++z) t[z] = z0 + z < P.splits ? q[(int64_t)(z0 + z) * nw] : 0.0f;
+#pragma unroll
+        for (int z = 0; z < 16; ++z)
+          if (z0 + z < P.splits) gg += t[z];
+      }
     } else if (p >= L.b_off[l] && p < L.b_off[l] + nb) {
       const float* q = P.b[l] + (p - L.b_off[l]);
       int t = 0;

@@ -839,12 +839,12 @@ __global__ void __launch_bounds__(256) stage_items(const float* params, const fl
 // A_{l-1} the B operand for 16 columns i, so every wave reads its operands
 // with 16-byte loads straight into registers and no LDS is involved.  A
 // block takes a 64 x 64 tile of one layer's dW (wave (wm, wn) a 32 x 32
-// quarter) over one of kSplitsFused item ranges and writes that range's partial;
+// quarter) over one of the step's item ranges and writes that range's partial;
 // the Adam kernel sums the partials.
 struct DwProblem {
   const uint16_t* G;  // item-fragment layout, nfo feature blocks
   const uint16_t* A;  // item-fragment layout, nfi feature blocks
-  float* C;           // [kSplitsFused][M][N]
+  float* C;           // [splits][M][N]
   int M, N, nfo, nfi, tiles_m, tiles_n;
   int64_t block0;
 };
@@ -903,9 +903,14 @@ __global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
   for (int i = 1; i < 4; ++i)
     if (i < D.count && (int64_t)blockIdx.x >= D.p[i].block0) pi = i;
   const DwProblem& P = D.p[pi];
+  // Blocks go to the eight XCDs round robin (block0 and the block count of
+  // every problem are multiples of 8): every tile of item range z runs on
+  // XCD z mod 8, so the range's operands are fetched into that XCD's L2
+  // once and re-read from there by the range's other tiles
   const int64_t b = (int64_t)blockIdx.x - P.block0;
   const int per_split = P.tiles_m * P.tiles_n;
-  const int split = (int)(b / per_split), rem = (int)(b % per_split);
+  const int64_t slot = b >> 3;
+  const int split = (int)((b & 7) + 8 * (slot / per_split)), rem = (int)(slot % per_split);
   const int tm = rem / P.tiles_n, tn = rem % P.tiles_n;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1066,8 +1071,11 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
   DwGroup D{};
   D.count = L.layers;
   D.nkb = (B + 31) / 32;
-  D.kc = (D.nkb + kSplitsFused - 1) / kSplitsFused;
-  parts.splits = kSplitsFused;
+  // about 16 item blocks per range, a multiple of the 8 XCDs
+  int64_t splits = ((D.nkb + 15) / 16 + 7) / 8 * 8;
+  splits = splits < kSplitsFusedMin ? kSplitsFusedMin : (splits > kSplitsMax ? kSplitsMax : splits);
+  D.kc = (D.nkb + splits - 1) / splits;
+  parts.splits = (int)splits;
   int64_t blocks = 0;
   for (int l = 0; l < L.layers; ++l) {
     DwProblem& P = D.p[l];
@@ -1081,7 +1089,7 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     P.tiles_m = (P.M + 63) / 64;
     P.tiles_n = (P.N + 63) / 64;
     P.block0 = blocks;
-    blocks += (int64_t)P.tiles_m * P.tiles_n * kSplitsFused;
+    blocks += (int64_t)P.tiles_m * P.tiles_n * splits;
   }
   // bias blocks: each layer's biases in whole 64-bias blocks
   D.bias_block0 = blocks;

@@ -261,7 +261,7 @@ ens::GradParts grad_parts(const ens_surrogate* s, int64_t tiles) {
   for (int l = 0; l < s->L.layers; ++l) {
     P.w[l] = s->wparts + wo;
     P.b[l] = s->bparts + bo;
-    wo += (int64_t)ens::kSplits * s->L.dims[l] * s->L.dims[l + 1];
+    wo += (int64_t)ens::kSplitsMax * s->L.dims[l] * s->L.dims[l + 1];
     bo += tiles * s->L.dims[l + 1];
   }
   return P;
@@ -280,7 +280,7 @@ int ensure_batch(ens_ctx* c, ens_surrogate* s, int64_t B) {
   const int64_t Bp = (B + 31) / 32 * 32, blocks = Bp / 16;
   bool ok = alloc(&s->a0, Bp * 16) == hipSuccess && alloc(&s->Y, B * O) == hipSuccess &&
             alloc(&s->T, B * O) == hipSuccess && alloc(&s->partial, blocks) == hipSuccess &&
-            alloc(&s->wparts, (int64_t)ens::kSplits * weight_count(s->L)) == hipSuccess &&
+            alloc(&s->wparts, (int64_t)ens::kSplitsMax * weight_count(s->L)) == hipSuccess &&
             alloc(&s->bparts, blocks * (s->L.total - weight_count(s->L))) == hipSuccess;
   for (int l = 0; l < 3 && ok; ++l)
     ok = alloc(&s->z[l], B * H) == hipSuccess && alloc(&s->act[l], Bp * H) == hipSuccess;
