@@ -386,21 +386,27 @@ mlp_fused_fwd(const FusedArgs a) {
 // gradient product, and every G_l's sum over the block's items goes to the
 // block's bias-gradient partial row.
 
-// LDS: two pair buffers [pair K][lane] of 16 bytes (layer outputs alternate
-// between them); two transposition tiles [feature][16 items] of bf16; a
-// small tile [48][16] for the inputs / the output gradient; the output
-// gradient's operand pieces [3][64 lanes] of 8 bytes; three loss partials;
-// the biases and normalisation.
-constexpr int kTAct = 8 * 64 * 16;
-constexpr int kTTile = 256 * 16 * 2;
-constexpr int kTTiles = 2 * kTAct;
-constexpr int kTSmall = kTTiles + 2 * kTTile;
-constexpr int kTG4 = kTSmall + 48 * 16 * 2;
-constexpr int kTLoss = kTG4 + 3 * 64 * 8;
-constexpr int kTBias = kTLoss + 4 * 8;
+// A block takes NS subtiles of 16 items (NS = 1 below a batch of 8192 items,
+// else 2: each weight fragment then feeds two products).  LDS, per NS: two
+// pair buffers [subtile][pair K][lane] of 16 bytes (layer outputs alternate
+// between them); two transposition tiles [feature][16 NS items] of bf16; a
+// small tile [48][16 NS] for the inputs / the output gradient; the output
+// gradient's operand pieces [subtile][3][64 lanes] of 8 bytes; three loss
+// partials; the biases and normalisation.
 constexpr int kTB1 = 0, kTB2 = 256, kTB3 = 512, kTB4 = 768, kTOutMean = 816, kTOutIStd = 864,
               kTInMean = 912, kTInIStd = 916, kTBCount = 920;
-constexpr int kTLdsBytes = kTBias + kTBCount * 4;
+template <int NS>
+struct TLds {
+  static constexpr int kItems = 16 * NS;
+  static constexpr int kAct = NS * 8 * 64 * 16;
+  static constexpr int kTile = 256 * kItems * 2;
+  static constexpr int kTiles = 2 * kAct;
+  static constexpr int kSmall = kTiles + 2 * kTile;
+  static constexpr int kG4 = kSmall + 48 * kItems * 2;
+  static constexpr int kLoss = kG4 + NS * 3 * 64 * 8;
+  static constexpr int kBias = kLoss + 4 * 8;
+  static constexpr int kBytes = kBias + kTBCount * 4;
+};
 
 struct StepArgs {
   const uint16_t* packed;  // forward and transposed fragments
@@ -421,33 +427,39 @@ struct StepArgs {
   float scale;          // dLoss / dY = scale (Y - T)
 };
 
-__device__ inline bf16x8_t* act_slot(uint8_t* lds, int buf, int K, int lane) {
-  return reinterpret_cast<bf16x8_t*>(lds + buf * kTAct + (K * 64 + lane) * 16);
+template <int NS>
+__device__ inline bf16x8_t* act_slot(uint8_t* lds, int buf, int s, int K, int lane) {
+  return reinterpret_cast<bf16x8_t*>(lds + buf * TLds<NS>::kAct + ((s * 8 + K) * 64 + lane) * 16);
 }
 
+template <int NS>
 __device__ inline __bf16* ttile(uint8_t* lds, int t) {
-  return reinterpret_cast<__bf16*>(lds + kTTiles + t * kTTile);
+  return reinterpret_cast<__bf16*>(lds + TLds<NS>::kTiles + t * TLds<NS>::kTile);
 }
 
-// A block's 16 items (half h of item block kb) of a [feature][16 items]
+// A block's 16 NS items, from item `first`, of a [feature][16 NS items]
 // transposition tile with nfb 16-feature blocks (`real` features, the rest
-// zero) into the item-fragment layout of mlp.h: entry (fb, g', r16) of the
-// fragment, g' = 2h or 2h + 1, holds 8 consecutive items of one feature,
-// 16 contiguous bytes in the tile.  32 nfb entries over the block's threads.
+// zero) into the item-fragment layout of mlp.h: entry (fb, g', r16) of item
+// block first / 32 holds 8 consecutive items of one feature, 16 contiguous
+// bytes in the tile; the block fills lane groups g' = g0 .. g0 + 2 NS - 1.
 // Non-temporal stores: the next kernel reads these from other XCDs anyway,
 // and lines left dirty in this XCD's L2 would have to be written back when
 // the kernel ends (measured: the step kernel 18.9 -> 16.4 us, the weight-
 // gradient kernel that reads them 9.3 -> 10.3 us).
-__device__ inline void if_store(const __bf16* tile, uint16_t* dst, int64_t kb, int h, int nfb,
+template <int NS>
+__device__ inline void if_store(const __bf16* tile, uint16_t* dst, int64_t first, int nfb,
                                 int real, int tid) {
   typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-  for (int E = tid; E < 32 * nfb; E += 256) {
-    const int fb = E >> 5, w = E & 31, r16 = w & 15, hi = w >> 4, f = 16 * fb + r16;
+  const int64_t kb = first >> 5;
+  const int g0 = (int)((first & 31) >> 3);
+  for (int E = tid; E < 32 * NS * nfb; E += 256) {
+    const int fb = E / (32 * NS), w = E % (32 * NS), r16 = w & 15, gi = w >> 4;
+    const int f = 16 * fb + r16;
     u32x4_t v = u32x4_t{0u, 0u, 0u, 0u};
-    if (f < real) v = *reinterpret_cast<const u32x4_t*>(tile + f * 16 + 8 * hi);
+    if (f < real) v = *reinterpret_cast<const u32x4_t*>(tile + f * (16 * NS) + 8 * gi);
     __builtin_nontemporal_store(
         v, reinterpret_cast<u32x4_t*>(
-               dst + ((kb * nfb + fb) * kPackFrag + (16 * (2 * h + hi) + r16) * 8)));
+               dst + ((kb * nfb + fb) * kPackFrag + (16 * (g0 + gi) + r16) * 8)));
   }
 }
 
@@ -456,20 +468,21 @@ __device__ inline bf16x8_t gfrag(const uint16_t* packed, int64_t frag_index, int
   return *reinterpret_cast<const bf16x8_t*>(packed + frag_index * kFrag + lane * 8);
 }
 
-// Forward: this wave's 64 rows of a layer, their SiLU into the pair buffer
-// (pairs K = 2w, 2w+1: features 32 K + 4 g + {0..3} and 32 K + 16 + 4 g +
-// {0..3}) and into the transposition tile.
+// Forward: this wave's 64 rows of a layer for subtile s, their SiLU into
+// the pair buffer (pairs K = 2w, 2w+1: features 32 K + 4 g + {0..3} and
+// 32 K + 16 + 4 g + {0..3}) and into the transposition tile.
+template <int NS>
 __device__ inline void train_rows(const f32x4_t (&acc)[4], uint8_t* lds, int out_buf,
-                                  __bf16* tile, int wave, int g, int col, int lane) {
+                                  __bf16* tile, int s, int wave, int g, int col, int lane) {
 #pragma unroll
   for (int pp = 0; pp < 2; ++pp) {
     const int K = 2 * wave + pp;
     const bf16x8_t v = silu_pack(acc[2 * pp], acc[2 * pp + 1]);
-    *act_slot(lds, out_buf, K, lane) = v;
+    *act_slot<NS>(lds, out_buf, s, K, lane) = v;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      tile[(32 * K + 4 * g + r) * 16 + col] = v[r];
-      tile[(32 * K + 16 + 4 * g + r) * 16 + col] = v[4 + r];
+      tile[(32 * K + 4 * g + r) * (16 * NS) + 16 * s + col] = v[r];
+      tile[(32 * K + 16 + 4 * g + r) * (16 * NS) + 16 * s + col] = v[4 + r];
     }
   }
 }
@@ -479,7 +492,7 @@ __device__ inline float dsilu(float z) {
   return s * (1.0f + z * (1.0f - s));
 }
 
-// Sum over the 16 lanes of a lane group (the block's 16 items): rotations
+// Sum over the 16 lanes of a lane group (a subtile's 16 items): rotations
 // by 8, 4, 2, 1 within each 16-lane DPP row, plain vector adds (a lane-
 // crossbar shuffle would cost an LDS round trip per step).  Every lane ends
 // with the group's total; callers take lane 0 of the group, whose order of
@@ -504,11 +517,13 @@ __device__ inline float sum16(float v) {
 }
 
 // Backward: G = acc * silu'(Z) for this wave's 64 features (row blocks
-// 4w + j): bf16 pairs into the pair buffer (out_buf >= 0) and the
-// transposition tile, the FP32 column sums into the block's partial row.
+// 4w + j) of subtile s: bf16 pairs into the pair buffer (out_buf >= 0) and
+// the transposition tile; each value's sum over the subtile's 16 items is
+// added to bs (lane 0 of a group holds the group's sums).
+template <int NS>
 __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4], uint8_t* lds,
-                                int out_buf, __bf16* tile, int wave, int g, int col, int lane,
-                                int r0, float* bp) {
+                                int out_buf, __bf16* tile, int s, int wave, int g, int col,
+                                int lane, int r0, float (&bs)[16]) {
   f32x4_t G[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -517,7 +532,7 @@ __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4],
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) tile[(r0 + 16 * j + r) * 16 + col] = (__bf16)G[j][r];
+    for (int r = 0; r < 4; ++r) tile[(r0 + 16 * j + r) * (16 * NS) + 16 * s + col] = (__bf16)G[j][r];
   if (out_buf >= 0) {
 #pragma unroll
     for (int pp = 0; pp < 2; ++pp) {
@@ -527,30 +542,43 @@ __device__ inline void bwd_rows(const f32x4_t (&acc)[4], const f32x4_t (&zv)[4],
         v[r] = (__bf16)G[2 * pp][r];
         v[4 + r] = (__bf16)G[2 * pp + 1][r];
       }
-      *act_slot(lds, out_buf, 2 * wave + pp, lane) = v;
+      *act_slot<NS>(lds, out_buf, s, 2 * wave + pp, lane) = v;
     }
   }
 #pragma unroll
   for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float t = sum16(G[j][r]);
-      if (col == 0) bp[r0 + 16 * j + r] = t;
-    }
+    for (int r = 0; r < 4; ++r) bs[4 * j + r] = s == 0 ? sum16(G[j][r]) : bs[4 * j + r] + sum16(G[j][r]);
+}
+
+// The block's bias-gradient partial row: lane 0 of each group writes its 16.
+__device__ inline void write_bias_row(const float (&bs)[16], int col, int r0, float* bp) {
+  if (col == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bp[r0 + 16 * j + r] = bs[4 * j + r];
+  }
 }
 
 // A hidden layer's products for this wave's four row blocks over the eight
-// k-blocks of the pair buffer in_buf, the accumulators starting from acc.
-__device__ inline void rows_mfma(f32x4_t (&acc)[4], const bf16x8_t (&w)[4][8], uint8_t* lds,
+// k-blocks of the pair buffer in_buf, every subtile; accumulators start
+// from acc.
+template <int NS>
+__device__ inline void rows_mfma(f32x4_t (&acc)[NS][4], const bf16x8_t (&w)[4][8], uint8_t* lds,
                                  int in_buf, int lane) {
-  bf16x8_t x[8];
+  bf16x8_t x[NS][8];
 #pragma unroll
-  for (int kb = 0; kb < 8; ++kb) x[kb] = *act_slot(lds, in_buf, kb, lane);
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) x[s][kb] = *act_slot<NS>(lds, in_buf, s, kb, lane);
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[kb], acc[j], 0, 0, 0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s)
+        acc[s][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[j][kb], x[s][kb], acc[s][j], 0, 0, 0);
 }
 
 __device__ inline void load_rows(bf16x8_t (&w)[4][8], const uint16_t* packed, int64_t base_frag,
@@ -561,19 +589,19 @@ __device__ inline void load_rows(bf16x8_t (&w)[4][8], const uint16_t* packed, in
     for (int kb = 0; kb < 8; ++kb) w[j][kb] = gfrag(packed, base_frag + (4 * wave + j) * 8 + kb, lane);
 }
 
+template <int NS>
 __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
-  __shared__ __attribute__((aligned(16))) uint8_t lds[kTLdsBytes];
+  using T = TLds<NS>;
+  constexpr int IT = 16 * NS;  // items per block
+  __shared__ __attribute__((aligned(16))) uint8_t lds[T::kBytes];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, col = lane & 15;
   const int64_t ns = a.in_stride;
-  const int64_t q = (int64_t)blockIdx.x * 16 + col;  // this lane's item
-  const bool live = q < a.n;
-  const int r0 = 64 * wave + 4 * g;    // this lane's first feature of its row blocks
-  const int64_t kb = blockIdx.x >> 1;  // item block of the item-fragment outputs
-  const int h = blockIdx.x & 1;
-  float* bw = reinterpret_cast<float*>(lds + kTBias);
-  __bf16* small = reinterpret_cast<__bf16*>(lds + kTSmall);
+  const int64_t first = (int64_t)blockIdx.x * IT;  // the block's first item
+  const int r0 = 64 * wave + 4 * g;  // this lane's first feature of its row blocks
+  float* bw = reinterpret_cast<float*>(lds + T::kBias);
+  __bf16* small = reinterpret_cast<__bf16*>(lds + T::kSmall);
 
   // biases and normalisation first, so that their wait before the LDS
   // stores does not wait for the loads issued after them
@@ -589,34 +617,43 @@ __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
     im = a.norm[kInMean + tid];
     iis = a.norm[kInIStd + tid];
   }
-  // the item's row, inputs (lane group 0) and, in waves 0..2, the four
-  // targets of outputs 16 w + 4 g + r that this lane's output gradient uses
-  int64_t row = 0;
-  float f[4] = {0.f, 0.f, 0.f, 0.f}, yt[4] = {0.f, 0.f, 0.f, 0.f};
-  if (live) {
-    row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
-    if (a.staged) {  // normalised already, one 208-byte record per item
-      const float* rec = a.staged + row * kStageW;
-      if (g == 0) {
-        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec);
+  // each subtile's item (lane col), its row, inputs (lane group 0) and, in
+  // waves 0..2, the four targets of outputs 16 w + 4 g + r its output
+  // gradient uses
+  bool live[NS];
+  float f[NS][4], yt[NS][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) f[k] = v[k];
-      }
-      if (wave < 3) {
-        const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec + 4 + 16 * wave + 4 * g);
+  for (int s = 0; s < NS; ++s) {
+    const int64_t q = first + 16 * s + col;
+    live[s] = q < a.n;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) yt[r] = v[r];
-      }
-    } else {
-      if (g == 0) {
-        f[0] = a.params[ns + row];
-        f[1] = a.u0[row];
-        f[2] = a.u0[ns + row];
-        f[3] = a.u0[2 * ns + row];
-      }
-      if (wave < 3) {
+    for (int k = 0; k < 4; ++k) f[s][k] = yt[s][k] = 0.f;
+    if (live[s]) {
+      const int64_t row = affine_row(a.mult, a.add, (uint64_t)(a.first + q), (uint64_t)ns);
+      if (a.staged) {  // normalised already, one 208-byte record per item
+        const float* rec = a.staged + row * kStageW;
+        if (g == 0) {
+          const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) yt[r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+          for (int k = 0; k < 4; ++k) f[s][k] = v[k];
+        }
+        if (wave < 3) {
+          const f32x4_t v = *reinterpret_cast<const f32x4_t*>(rec + 4 + 16 * wave + 4 * g);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) yt[s][r] = v[r];
+        }
+      } else {
+        if (g == 0) {
+          f[s][0] = a.params[ns + row];
+          f[s][1] = a.u0[row];
+          f[s][2] = a.u0[ns + row];
+          f[s][3] = a.u0[2 * ns + row];
+        }
+        if (wave < 3) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            yt[s][r] = a.y[(int64_t)(16 * wave + 4 * g + r) * ns + row];
+        }
       }
     }
   }
@@ -638,48 +675,56 @@ __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
     bw[kTInIStd + tid] = iis;
   }
   __syncthreads();
-  f32x4_t z[3][4];  // pre-activations of this wave's features, kept for SiLU'
-  f32x4_t acc[4];
+  f32x4_t z[3][NS][4];  // pre-activations of this wave's features, kept for SiLU'
+  f32x4_t acc[NS][4];
 
   // ---- forward, layer 1: normalised (rho, x0, y0, z0) in k = 0..3 of lane
   // group 0
-  {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     bf16x8_t xin;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const float v = !(g == 0 && live) ? 0.f
-                      : a.staged       ? f[k]
-                                       : (f[k] - bw[kTInMean + k]) * bw[kTInIStd + k];
+      const float v = !(g == 0 && live[s]) ? 0.f
+                      : a.staged          ? f[s][k]
+                                          : (f[s][k] - bw[kTInMean + k]) * bw[kTInIStd + k];
       xin[k] = (__bf16)v;
       xin[4 + k] = (__bf16)0.0f;
     }
     if (wave == 0 && g == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) small[k * 16 + col] = xin[k];
+      for (int k = 0; k < 4; ++k) small[k * IT + 16 * s + col] = xin[k];
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      z[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+      z[0][s][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
           w1[j], xin, *reinterpret_cast<const f32x4_t*>(bw + kTB1 + r0 + 16 * j), 0, 0, 0);
-    train_rows(z[0], lds, 0, ttile(lds, 0), wave, g, col, lane);
+    train_rows<NS>(z[0][s], lds, 0, ttile<NS>(lds, 0), s, wave, g, col, lane);
   }
   __syncthreads();
-  if_store(small, a.a0, kb, h, 1, 4, tid);
-  if_store(ttile(lds, 0), a.act[0], kb, h, 16, kH, tid);
+  if_store<NS>(small, a.a0, first, 1, 4, tid);
+  if_store<NS>(ttile<NS>(lds, 0), a.act[0], first, 16, kH, tid);
 
   // ---- layer 2
 #pragma unroll
-  for (int j = 0; j < 4; ++j) z[1][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB2 + r0 + 16 * j);
-  rows_mfma(z[1], w, lds, 0, lane);
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      z[1][s][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB2 + r0 + 16 * j);
+  rows_mfma<NS>(z[1], w, lds, 0, lane);
   load_rows(w, a.packed, kP3 / kFrag, wave, lane);  // layer 3, in flight meanwhile
-  train_rows(z[1], lds, 1, ttile(lds, 1), wave, g, col, lane);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) train_rows<NS>(z[1][s], lds, 1, ttile<NS>(lds, 1), s, wave, g, col, lane);
   __syncthreads();
-  if_store(ttile(lds, 1), a.act[1], kb, h, 16, kH, tid);
+  if_store<NS>(ttile<NS>(lds, 1), a.act[1], first, 16, kH, tid);
 
   // ---- layer 3
 #pragma unroll
-  for (int j = 0; j < 4; ++j) z[2][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB3 + r0 + 16 * j);
-  rows_mfma(z[2], w, lds, 1, lane);
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      z[2][s][j] = *reinterpret_cast<const f32x4_t*>(bw + kTB3 + r0 + 16 * j);
+  rows_mfma<NS>(z[2], w, lds, 1, lane);
   bf16x8_t w4[8], w4t[4][2];  // layer 4's row block `wave` (waves 0..2), W_4^T rows
   if (wave < 3) {
 #pragma unroll
@@ -690,65 +735,77 @@ __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
 #pragma unroll
     for (int k2 = 0; k2 < 2; ++k2)
       w4t[j][k2] = gfrag(a.packed, kPackT4 / kFrag + (4 * wave + j) * 2 + k2, lane);
-  train_rows(z[2], lds, 0, ttile(lds, 0), wave, g, col, lane);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) train_rows<NS>(z[2][s], lds, 0, ttile<NS>(lds, 0), s, wave, g, col, lane);
   __syncthreads();
-  if_store(ttile(lds, 0), a.act[2], kb, h, 16, kH, tid);
+  if_store<NS>(ttile<NS>(lds, 0), a.act[2], first, 16, kH, tid);
 
   // ---- layer 4 and the loss (waves 0..2: outputs 16 w .. 16 w + 15):
   // G_4 = scale (Y - T) into the small tile, the operand pieces, the output
   // bias partial and the block's loss partial
   if (wave < 3) {
-    bf16x8_t x[8];
-#pragma unroll
-    for (int k8 = 0; k8 < 8; ++k8) x[k8] = *act_slot(lds, 0, k8, lane);
     const int o0 = 16 * wave + 4 * g;
-    f32x4_t out = *reinterpret_cast<const f32x4_t*>(bw + kTB4 + o0);
+    f32x4_t out[NS];
 #pragma unroll
-    for (int k8 = 0; k8 < 8; ++k8)
-      out = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[k8], x[k8], out, 0, 0, 0);
+    for (int s = 0; s < NS; ++s) {
+      bf16x8_t x[8];
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8) x[k8] = *act_slot<NS>(lds, 0, s, k8, lane);
+      out[s] = *reinterpret_cast<const f32x4_t*>(bw + kTB4 + o0);
+#pragma unroll
+      for (int k8 = 0; k8 < 8; ++k8)
+        out[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4[k8], x[k8], out[s], 0, 0, 0);
+    }
     load_rows(w, a.packed, kPackT3 / kFrag, wave, lane);  // W_3^T for G_2, in flight
-    float gg[4];
+    float bs4[4];
     double d2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float t = !live ? 0.f
-                      : a.staged ? yt[r]
-                                 : (yt[r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
-      const float d = live ? out[r] - t : 0.f;
-      gg[r] = a.scale * d;
-      d2 += (double)d * d;
-      small[(o0 + r) * 16 + col] = (__bf16)gg[r];
+    for (int s = 0; s < NS; ++s) {
+      float gg[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float t = !live[s] ? 0.f
+                        : a.staged ? yt[s][r]
+                                   : (yt[s][r] - bw[kTOutMean + o0 + r]) * bw[kTOutIStd + o0 + r];
+        const float d = live[s] ? out[s][r] - t : 0.f;
+        gg[r] = a.scale * d;
+        d2 += (double)d * d;
+        small[(o0 + r) * IT + 16 * s + col] = (__bf16)gg[r];
+        bs4[r] = s == 0 ? sum16(gg[r]) : bs4[r] + sum16(gg[r]);
+      }
+      typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+      *reinterpret_cast<bf16x4_t*>(lds + T::kG4 + ((s * 3 + wave) * 64 + lane) * 8) =
+          bf16x4_t{(__bf16)gg[0], (__bf16)gg[1], (__bf16)gg[2], (__bf16)gg[3]};
     }
-    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-    *reinterpret_cast<bf16x4_t*>(lds + kTG4 + (wave * 64 + lane) * 8) =
-        bf16x4_t{(__bf16)gg[0], (__bf16)gg[1], (__bf16)gg[2], (__bf16)gg[3]};
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) d2 += __shfl_xor(d2, m);
-    if (lane == 0) reinterpret_cast<double*>(lds + kTLoss)[wave] = d2;
+    if (lane == 0) reinterpret_cast<double*>(lds + T::kLoss)[wave] = d2;
     float* bp = a.bpart[3] + (int64_t)blockIdx.x * kNO;
+    if (col == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float t = sum16(gg[r]);
-      if (col == 0) bp[o0 + r] = t;
+      for (int r = 0; r < 4; ++r) bp[o0 + r] = bs4[r];
     }
   } else {
     load_rows(w, a.packed, kPackT3 / kFrag, wave, lane);
   }
   __syncthreads();
   if (tid == 0) {
-    const double* lp = reinterpret_cast<const double*>(lds + kTLoss);
+    const double* lp = reinterpret_cast<const double*>(lds + T::kLoss);
     a.partial[blockIdx.x] = (lp[0] + lp[1]) + lp[2];
   }
-  if_store(small, a.gb[3], kb, h, 3, kNO, tid);
+  if_store<NS>(small, a.gb[3], first, 3, kNO, tid);
 
   // ---- backward: G_3 = (G_4 W_4) * silu'(Z_3), K = 48 (k-block 1 half
   // zero): lane (g, col) takes outputs 4g.., 16+4g.. and 32+4g.. from the
   // pieces of waves 0, 1, 2
-  {
+  float bs[16];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
     typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
-    const bf16x4_t p0 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (0 * 64 + lane) * 8);
-    const bf16x4_t p1 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (1 * 64 + lane) * 8);
-    const bf16x4_t p2 = *reinterpret_cast<const bf16x4_t*>(lds + kTG4 + (2 * 64 + lane) * 8);
+    const uint8_t* pc = lds + T::kG4 + (s * 3 * 64 + lane) * 8;
+    const bf16x4_t p0 = *reinterpret_cast<const bf16x4_t*>(pc);
+    const bf16x4_t p1 = *reinterpret_cast<const bf16x4_t*>(pc + 64 * 8);
+    const bf16x4_t p2 = *reinterpret_cast<const bf16x4_t*>(pc + 2 * 64 * 8);
     bf16x8_t x4[2];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -759,35 +816,43 @@ __global__ void __launch_bounds__(256) mlp_train_step(const StepArgs a) {
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      acc[s][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int k2 = 0; k2 < 2; ++k2)
-        acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4t[j][k2], x4[k2], acc[j], 0, 0, 0);
+        acc[s][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w4t[j][k2], x4[k2], acc[s][j], 0, 0, 0);
     }
+    bwd_rows<NS>(acc[s], z[2][s], lds, 1, ttile<NS>(lds, 1), s, wave, g, col, lane, r0, bs);
   }
-  bwd_rows(acc, z[2], lds, 1, ttile(lds, 1), wave, g, col, lane, r0,
-           a.bpart[2] + (int64_t)blockIdx.x * kH);
+  write_bias_row(bs, col, r0, a.bpart[2] + (int64_t)blockIdx.x * kH);
   __syncthreads();
-  if_store(ttile(lds, 1), a.gb[2], kb, h, 16, kH, tid);
+  if_store<NS>(ttile<NS>(lds, 1), a.gb[2], first, 16, kH, tid);
 
   // ---- G_2 = (G_3 W_3) * silu'(Z_2)
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  rows_mfma(acc, w, lds, 1, lane);
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[s][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  rows_mfma<NS>(acc, w, lds, 1, lane);
   load_rows(w, a.packed, kPackT2 / kFrag, wave, lane);  // W_2^T, in flight meanwhile
-  bwd_rows(acc, z[1], lds, 0, ttile(lds, 0), wave, g, col, lane, r0,
-           a.bpart[1] + (int64_t)blockIdx.x * kH);
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    bwd_rows<NS>(acc[s], z[1][s], lds, 0, ttile<NS>(lds, 0), s, wave, g, col, lane, r0, bs);
+  write_bias_row(bs, col, r0, a.bpart[1] + (int64_t)blockIdx.x * kH);
   __syncthreads();
-  if_store(ttile(lds, 0), a.gb[1], kb, h, 16, kH, tid);
+  if_store<NS>(ttile<NS>(lds, 0), a.gb[1], first, 16, kH, tid);
 
   // ---- G_1 = (G_2 W_2) * silu'(Z_1)
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  rows_mfma(acc, w, lds, 0, lane);
-  bwd_rows(acc, z[0], lds, -1, ttile(lds, 1), wave, g, col, lane, r0,
-           a.bpart[0] + (int64_t)blockIdx.x * kH);
+  for (int s = 0; s < NS; ++s)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[s][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  rows_mfma<NS>(acc, w, lds, 0, lane);
+#pragma unroll
+  for (int s = 0; s < NS; ++s)
+    bwd_rows<NS>(acc[s], z[0][s], lds, -1, ttile<NS>(lds, 1), s, wave, g, col, lane, r0, bs);
+  write_bias_row(bs, col, r0, a.bpart[0] + (int64_t)blockIdx.x * kH);
   __syncthreads();
-  if_store(ttile(lds, 1), a.gb[0], kb, h, 16, kH, tid);
+  if_store<NS>(ttile<NS>(lds, 1), a.gb[0], first, 16, kH, tid);
 }
 
 // ---- staged training set ---------------------------------------------------
@@ -1033,7 +1098,10 @@ hipError_t mlp_train_fused(const uint16_t* packed, const float* w, const MlpLayo
   if (L.layers != 4 || L.dims[0] != 4 || L.dims[1] != kH || L.dims[2] != kH ||
       L.dims[3] != kH || L.dims[4] != kNO || n <= 0)
     return hipErrorInvalidValue;
-  const int64_t blocks = 2 * ((B + 31) / 32);
+  // 16-item blocks for a small batch (so it still spreads over the CUs),
+  // 32-item ones from 8192 items on; whole 32-item blocks of outputs either way
+  const int NS = B >= 8192 ? 2 : 1;
+  const int64_t blocks = (2 / NS) * ((B + 31) / 32);
   if (blocks > (1LL << 24)) return hipErrorInvalidValue;  // blocks x 256 work-items fit 32 bits
   StepArgs a{};
   a.packed = packed;
@@ -1058,7 +1126,10 @@ hipError_t mlp_train_fused(const uint16_t* packed, const float* w, const MlpLayo
   a.partial = partial;
   a.scale = (float)(2.0 / (double)(B * kNO));
   parts.tiles = (int)blocks;
-  hipLaunchKernelGGL(mlp_train_step, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (NS == 2)
+    hipLaunchKernelGGL(mlp_train_step<2>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(mlp_train_step<1>, dim3((unsigned)blocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
