@@ -904,8 +904,9 @@ __global__ void __launch_bounds__(256) stage_items(const float* params, const fl
 // A_{l-1} the B operand for 16 columns i, so every wave reads its operands
 // with 16-byte loads straight into registers and no LDS is involved.  A
 // block takes a 64 x 64 tile of one layer's dW (wave (wm, wn) a 32 x 32
-// quarter) over one of the step's item ranges and writes that range's partial;
-// the Adam kernel sums the partials.
+// quarter), or from 16,384 items a 128 x 128 one (64 x 64 per wave), over
+// one of the step's item ranges and writes that range's partial; the Adam
+// kernel sums the partials.
 struct DwProblem {
   const uint16_t* G;  // item-fragment layout, nfo feature blocks
   const uint16_t* A;  // item-fragment layout, nfi feature blocks
@@ -958,7 +959,12 @@ __device__ void bias_sums(const DwGroup& D, int64_t b) {
   if (quarter == 0 && f < n) D.bias[l][f] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
 }
 
+// WT 16-row blocks per wave in each dimension: WT = 2, a 64 x 64 tile per
+// block (small batches: enough blocks); WT = 4, 128 x 128 (large batches:
+// each operand fragment is read by half as many blocks).
+template <int WT>
 __global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
+  constexpr int RT = 16 / WT;  // item blocks per round: 4 WT operand fragments each
   if ((int64_t)blockIdx.x >= D.bias_block0) {
     bias_sums(D, (int64_t)blockIdx.x - D.bias_block0);
     return;
@@ -979,20 +985,20 @@ __global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
   const int tm = rem / P.tiles_n, tn = rem % P.tiles_n;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int fo0 = 4 * tm + 2 * (wave >> 1), fi0 = 4 * tn + 2 * (wave & 1);
+  const int fo0 = 2 * WT * tm + WT * (wave >> 1), fi0 = 2 * WT * tn + WT * (wave & 1);
   const int64_t kb0 = split * D.kc, kb1 = kb0 + D.kc < D.nkb ? kb0 + D.kc : D.nkb;
-  f32x4_t acc[2][2];
+  f32x4_t acc[WT][WT];
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WT; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) acc[x][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int y = 0; y < WT; ++y) acc[x][y] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const bf16x8_t zero = bf16x8_t{};
-  for (int64_t k0 = kb0; k0 < kb1; k0 += 8) {  // eight item blocks' operands in flight
-    bf16x8_t ga[8][2], ab[8][2];
+  for (int64_t k0 = kb0; k0 < kb1; k0 += RT) {  // RT item blocks' operands in flight
+    bf16x8_t ga[RT][WT], ab[RT][WT];
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int x = 0; x < 2; ++x) {
+      for (int x = 0; x < WT; ++x) {
         const bool kin = k0 + t < kb1;
         ga[t][x] = kin && fo0 + x < P.nfo
                        ? *reinterpret_cast<const bf16x8_t*>(
@@ -1004,20 +1010,20 @@ __global__ void __launch_bounds__(256) mlp_dw(const DwGroup D) {
                        : zero;
       }
 #pragma unroll
-    for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int x = 0; x < 2; ++x)
+      for (int x = 0; x < WT; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < WT; ++y)
           acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[t][x], ab[t][y], acc[x][y], 0, 0, 0);
   }
   // lane (g, c) holds rows 4 g + r, column c of each 16 x 16 block
   float* C = P.C + (int64_t)split * P.M * P.N;
   const int g = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int x = 0; x < 2; ++x)
+  for (int x = 0; x < WT; ++x)
 #pragma unroll
-    for (int y = 0; y < 2; ++y) {
+    for (int y = 0; y < WT; ++y) {
       const int i = 16 * (fi0 + y) + c;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -1144,6 +1150,8 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
   D.nkb = (B + 31) / 32;
   // about 16 item blocks per range, a multiple of the 8 XCDs
   int64_t splits = ((D.nkb + 15) / 16 + 7) / 8 * 8;
+  const int WT = D.nkb >= 512 ? 4 : 2;  // 128 x 128 tiles from 16,384 items on
+  const int tile = 32 * WT;
   splits = splits < kSplitsFusedMin ? kSplitsFusedMin : (splits > kSplitsMax ? kSplitsMax : splits);
   D.kc = (D.nkb + splits - 1) / splits;
   parts.splits = (int)splits;
@@ -1157,8 +1165,8 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     P.N = L.dims[l];
     P.nfo = (P.M + 15) / 16;
     P.nfi = (P.N + 15) / 16;
-    P.tiles_m = (P.M + 63) / 64;
-    P.tiles_n = (P.N + 63) / 64;
+    P.tiles_m = (P.M + tile - 1) / tile;
+    P.tiles_n = (P.N + tile - 1) / tile;
     P.block0 = blocks;
     blocks += (int64_t)P.tiles_m * P.tiles_n * splits;
   }
@@ -1170,7 +1178,10 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     D.bias_n[l] = L.dims[l + 1];
     blocks += (L.dims[l + 1] + 63) / 64;
   }
-  hipLaunchKernelGGL(mlp_dw, dim3((unsigned)blocks), dim3(256), 0, s, D);
+  if (WT == 4)
+    hipLaunchKernelGGL(mlp_dw<4>, dim3((unsigned)blocks), dim3(256), 0, s, D);
+  else
+    hipLaunchKernelGGL(mlp_dw<2>, dim3((unsigned)blocks), dim3(256), 0, s, D);
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   parts.tiles = 1;  // the Adam kernel reads the summed row
   return hipSuccess;
