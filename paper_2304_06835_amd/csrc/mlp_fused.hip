@@ -927,22 +927,26 @@ struct DwGroup {
   int rows;
 };
 
-// 64 biases per block, four threads per bias each summing a quarter of the
-// rows in order, the quarters then added in order: a fixed summation order.
+// 16 biases per block, sixteen threads per bias each summing a sixteenth of
+// the rows in order (16 loads in flight), the sixteen parts then added in
+// order: a fixed summation order, and enough threads on the rows that a
+// large batch's thousands of block rows do not make these blocks the
+// launch's long pole.
+constexpr int kBiasPerBlock = 16;
 __device__ void bias_sums(const DwGroup& D, int64_t b) {
-  __shared__ float part[4][64];
-  int l = 0;  // layer l owns ceil(bias_n[l] / 64) consecutive blocks
-  while (l < D.count - 1 && b >= (D.bias_n[l] + 63) / 64) {
-    b -= (D.bias_n[l] + 63) / 64;
+  __shared__ float part[16][kBiasPerBlock];
+  int l = 0;  // layer l owns ceil(bias_n[l] / 16) consecutive blocks
+  while (l < D.count - 1 && b >= (D.bias_n[l] + kBiasPerBlock - 1) / kBiasPerBlock) {
+    b -= (D.bias_n[l] + kBiasPerBlock - 1) / kBiasPerBlock;
     ++l;
   }
-  const int64_t first = b * 64;
-  const int t = threadIdx.x, j = t & 63, quarter = t >> 6;
-  const int64_t f = first + j;
+  const int t = threadIdx.x, j = t & (kBiasPerBlock - 1), sixteenth = t >> 4;
+  const int64_t f = b * kBiasPerBlock + j;
   const int n = D.bias_n[l];
   float sum = 0.f;
   if (f < n) {
-    const int per = (D.rows + 3) / 4, r0 = quarter * per, r1 = r0 + per < D.rows ? r0 + per : D.rows;
+    const int per = (D.rows + 15) / 16, r0 = sixteenth * per,
+              r1 = r0 + per < D.rows ? r0 + per : D.rows;
     const float* col = D.bias[l] + f;
     int r = r0;
     for (; r + 16 <= r1; r += 16) {
@@ -954,9 +958,14 @@ __device__ void bias_sums(const DwGroup& D, int64_t b) {
     }
     for (; r < r1; ++r) sum += col[(int64_t)r * n];
   }
-  part[quarter][j] = sum;
+  part[sixteenth][j] = sum;
   __syncthreads();
-  if (quarter == 0 && f < n) D.bias[l][f] = (part[0][j] + part[1][j]) + (part[2][j] + part[3][j]);
+  if (sixteenth == 0 && f < n) {
+    float tot = part[0][j];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) tot += part[k][j];
+    D.bias[l][f] = tot;
+  }
 }
 
 // WT 16-row blocks per wave in each dimension: WT = 2, a 64 x 64 tile per
@@ -1170,13 +1179,13 @@ hipError_t mlp_weight_grads_if(const MlpLayout& L, int64_t B, MlpActs& acts, con
     P.block0 = blocks;
     blocks += (int64_t)P.tiles_m * P.tiles_n * splits;
   }
-  // bias blocks: each layer's biases in whole 64-bias blocks
+  // bias blocks: each layer's biases in whole blocks of kBiasPerBlock
   D.bias_block0 = blocks;
   D.rows = parts.tiles;
   for (int l = 0; l < L.layers; ++l) {
     D.bias[l] = parts.b[l];
     D.bias_n[l] = L.dims[l + 1];
-    blocks += (L.dims[l + 1] + 63) / 64;
+    blocks += (L.dims[l + 1] + kBiasPerBlock - 1) / kBiasPerBlock;
   }
   if (WT == 4)
     hipLaunchKernelGGL(mlp_dw<4>, dim3((unsigned)blocks), dim3(256), 0, s, D);
