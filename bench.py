@@ -333,6 +333,54 @@ def recorded_valu_mix(key, path=None):
     return r
 
 
+def mfma_mix_rates(device=0, iters=4096):
+    """Wave-iterations per second over the device of the matrix-core probe's
+    three kinds, measured now: 24 bf16 products, 12 SiLU rows, and both one
+    after the other in a wave (two waves per SIMD)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2304_06835_amd", "libvaluprobe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2304_06835_amd.build`")
+    L = ctypes.CDLL(path)
+    L.mfma_mix_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_double)]
+    out = {}
+    for name, kind in (("mfma", 0), ("silu", 1), ("mfma_then_silu", 2)):
+        r = ctypes.c_double(0.0)
+        rc = L.mfma_mix_rate(device, kind, iters, ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"mfma_mix_rate({name}) failed with {rc}")
+        out[name] = r.value
+    return out
+
+
+# One 16-query subtile of the fused inference kernel in the probe's units:
+# layers 2 and 3 together are 256 products and 128 SiLU rows (the 2 : 1 of
+# the mixed kind), layer 1 16 products (K = 4 padded to one k-block) and 64
+# SiLU rows, layer 4 24 products (48 outputs padded to 3 row blocks) and no
+# activation: 296 products and 192 rows in all.
+MIX_PRODUCTS, MIX_ROWS = 24, 12
+INFER_SUBTILE = {"mfma_then_silu": 256 / MIX_PRODUCTS, "mfma": (16 + 24) / MIX_PRODUCTS,
+                 "silu": 64 / MIX_ROWS}
+
+
+def coissue_ceiling(queries, kernel_ms, rates):
+    """The inference kernel against what its instruction stream can reach on
+    this chip: the device time the probe needs for the kernel's products and
+    SiLU rows (each layer priced by the probe kind with its mix), over the
+    measured kernel time.  Products alone run near the matrix-core peak, but
+    a wave's activation rows barely overlap its products, so this, not the
+    2.5 PFLOP/s, bounds a kernel whose every product is followed by SiLU."""
+    subtiles = queries / 16.0
+    ceil_s = subtiles * sum(n / rates[k] for k, n in INFER_SUBTILE.items())
+    mfma_frac = rates["mfma"] * MIX_PRODUCTS * 16 * 16 * 32 * 2 / (PEAK_BF16_MFMA * 1e12)
+    mix_frac = rates["mfma_then_silu"] * MIX_PRODUCTS * 16 * 16 * 32 * 2 / (PEAK_BF16_MFMA * 1e12)
+    return {"ceiling_ms": ceil_s * 1e3, "frac": ceil_s * 1e3 / kernel_ms,
+            "probe_products_frac_of_peak": mfma_frac,
+            "probe_products_then_silu_frac_of_peak": mix_frac,
+            "probe_wave_iters_per_s": rates}
+
+
 _RATES = {}
 
 
@@ -715,7 +763,8 @@ def surrogate_variant(epochs, plain_ms_2p24, headline_ms_2p24=None):
                      "batch_scaling": scaling},
         "predict_ms": pred_ms,
         "predict_mfma": {"achieved": mfma, "peak": PEAK_BF16_MFMA, "unit": "TFLOP/s",
-                         "frac": mfma / PEAK_BF16_MFMA},
+                         "frac": mfma / PEAK_BF16_MFMA,
+                         "coissue": coissue_ceiling(q.n, pred_ms, mfma_mix_rates())},
         "queries": q.n, "plain_solver_ms": plain_ms_2p24,
         "predict_only_speedup_vs_plain": plain_ms_2p24 / pred_ms,
     }
@@ -780,6 +829,7 @@ def surrogate_only(epochs, scaling=False):
         "train_epochs": epochs, "train_samples": 1 << 20, "train_seconds": train_s,
         "train_tflops": train_tf, "predict_ms": pred_ms, "queries": q.n,
         "predict_tflops": MLP_FLOPS_PER_QUERY * q.n / (pred_ms * 1e-3) / 1e12,
+        "predict_coissue": coissue_ceiling(q.n, pred_ms, mfma_mix_rates()),
         "train_batch_scaling": train_batch_scaling(s, P, U, y) if scaling else None}}),
         flush=True)
 

@@ -101,9 +101,10 @@ def test_binding_constants_match_header():
 
 
 def test_valu_probe_library_loads_and_rejects_bad_kinds():
-    """The issue-rate probe the benchmark prices instruction streams with is a
-    separate shared object; it loads, exports its one entry point and rejects
-    an unknown kind or a null result pointer before touching a device."""
+    """The issue-rate probes the benchmark prices instruction streams with are
+    a separate shared object; it loads, exports its two entry points and each
+    rejects an unknown kind or a null result pointer before touching a
+    device."""
     path = os.path.join(ROOT, "paper_2304_06835_amd", "libvaluprobe.so")
     if not os.path.exists(path):
         pytest.skip("libvaluprobe.so not built")
@@ -115,3 +116,9 @@ def test_valu_probe_library_loads_and_rejects_bad_kinds():
     assert f(0, -1, 16, ctypes.byref(r)) == -1
     assert f(0, 0, 0, ctypes.byref(r)) == -1
     assert f(0, 0, 16, None) == -1
+    g = L.mfma_mix_rate
+    g.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    assert g(0, 3, 16, ctypes.byref(r)) == -1
+    assert g(0, -1, 16, ctypes.byref(r)) == -1
+    assert g(0, 0, 0, ctypes.byref(r)) == -1
+    assert g(0, 0, 16, None) == -1

@@ -83,3 +83,21 @@ def test_training_flops_per_sample():
     fwd = 2 * (4 * 256 + 2 * 256 * 256 + 256 * 48)
     assert bench.MLP_FLOPS_PER_QUERY == fwd == 288768
     assert bench.MLP_TRAIN_FLOPS_PER_SAMPLE == 2 * fwd + 2 * (2 * 256 * 256 + 256 * 48) == 864256
+
+
+def test_coissue_ceiling_counts_the_inference_kernels_work():
+    """The probe units of one 16-query subtile add up to the fused kernel's
+    296 products (16 + 128 + 128 + 24 row-block x k-block tiles) and 192 SiLU
+    rows (768 activations x 16 queries / 64 lanes), and the ceiling is the
+    probe time of those units over the kernel time."""
+    prod = (bench.INFER_SUBTILE["mfma_then_silu"] + bench.INFER_SUBTILE["mfma"]) * bench.MIX_PRODUCTS
+    rows = (bench.INFER_SUBTILE["mfma_then_silu"] + bench.INFER_SUBTILE["silu"]) * bench.MIX_ROWS
+    assert abs(prod - 296) < 1e-9 and abs(rows - 192) < 1e-9
+    rates = {"mfma": 2e9, "silu": 1e9, "mfma_then_silu": 5e8}
+    q = 1 << 20
+    r = bench.coissue_ceiling(q, 10.0, rates)
+    want_s = q / 16 * (256 / 24 / 5e8 + 40 / 24 / 2e9 + 64 / 12 / 1e9)
+    assert abs(r["ceiling_ms"] - want_s * 1e3) < 1e-9
+    assert abs(r["frac"] - want_s * 1e3 / 10.0) < 1e-12
+    # 24 products of 16 x 16 x 32 per wave-iteration against the bf16 peak
+    assert abs(r["probe_products_frac_of_peak"] - 2e9 * 24 * 16384 / 2.5e15) < 1e-12
