@@ -123,6 +123,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (the "
                          "reference kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--record-counters", metavar="DIR", default="",
+                    help="no GPU: write profiles/valu_mix.json and profiles/traffic.json from "
+                         "the rocprofv3 --pmc output directories under DIR (the commands in "
+                         "profiles/valu_issue_rates.md and tsit5_sorted_f32_lorenz_2p24.md)")
     return ap.parse_args()
 
 
@@ -286,6 +290,121 @@ def recorded_traffic(name, form, launches_units):
     if not r or r.get("source_hash") != kernel_source_hash(r.get("sources")):
         return None
     return r.get("hbm_bytes_per_launch")
+
+
+# ---- counter records (rocprofv3 --pmc output -> profiles/*.json) ----------
+TSIT5_SOURCES = ["tsit5.hip", "driver.h", "systems.h", "ens_internal.h"]
+SDE_SOURCES = ["em.hip", "driver.h", "philox.h", "ens_internal.h"]
+ROS_SOURCES = ["rodas4.hip", "rodas.h", "rosenbrock.h", "pollu.h", "systems.h", "driver.h",
+               "ens_internal.h"]
+# record key: (directory suffix of the mixA_/mixC_ passes, kernel-name match,
+# sources, description)
+MIX_RUNS = {
+    "lorenz_fp32/tsit5/sorted/dense": (
+        "lorenz_fp32", "tsit5_sorted<float, ens::Lorenz, 256, 1, false>", TSIT5_SOURCES,
+        "tsit5_sorted<float, Lorenz, 256, 1, false>, save mode 1 (dense output), 2^24 trajectories"),
+    "gbm/em/plain": ("gbm", "em_gbm4", SDE_SOURCES, "em_gbm4, 2^22 trajectories x 256 steps"),
+    "gbm/siea/plain": ("gbm_siea", "Gbm4Siea", SDE_SOURCES,
+                       "sde_fixed<Gbm4Siea>, 2^22 trajectories x 256 steps"),
+    "crn/em/plain": ("crn", "Crn>", SDE_SOURCES, "sde_fixed<Crn>, 10^6 trajectories x 10^4 steps"),
+    "robertson/rodas4/sorted": (
+        "robertson", "ros_sorted<float, ens::Robertson", ROS_SOURCES,
+        "ros_sorted<float, Robertson, Rodas4, 256, 1>, 2^20 trajectories"),
+}
+# record key: (directory tag of the pmc_<tag>_FETCH / _WRITE passes, description)
+TRAFFIC_RUNS = {
+    "lorenz_fp32/sorted/dense": (
+        "h", "tsit5_sorted<float, Lorenz, 256, 1, false>, save mode 1 (dense output), saves "
+             "stored directly"),
+    "lorenz_fp32/sorted_staged/dense": (
+        "st", "tsit5_sorted<float, Lorenz, 256, 1, true>, save mode 1 (dense output), saves "
+              "staged in LDS"),
+}
+HEADLINE_ALG_BYTES = (40 + 192) * (1 << 24)  # inputs + 16 saves of 3 FP32, per trajectory
+
+
+def pmc_dispatches(path, match):
+    """Per-dispatch counter sums {counter: value} of the kernels whose name
+    contains `match`, in dispatch order, from a rocprofv3 counter CSV."""
+    import collections
+    import csv
+    agg = collections.OrderedDict()
+    with open(os.path.join(path, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if match in r["Kernel_Name"]:
+                e = agg.setdefault(r["Dispatch_Id"], collections.Counter())
+                e[r["Counter_Name"]] += float(r["Counter_Value"])
+    return list(agg.values())
+
+
+def record_counters(root, out_dir=None):
+    """Write the VALU-mix and HBM-traffic records that bench.py replays (by
+    source hash) from the --pmc output directories under `root`."""
+    out_dir = out_dir or os.path.join(ROOT, "profiles")
+
+    def mean(ds, k):
+        return sum(d[k] for d in ds) / len(ds)
+
+    mix = {"_doc": (
+        "Wave-level VALU instructions per launch by class, from two rocprofv3 --pmc passes "
+        "(SQ_INSTS_VALU and its FMA/MUL/ADD/TRANS_F32, INT32, INT64, CVT classes; the F64 "
+        "classes with SQ_ACTIVE_INST_VALU and SQ_THREAD_CYCLES_VALU), written by bench.py "
+        "--record-counters. OTHER = SQ_INSTS_VALU minus the counted classes (moves, compares, "
+        "selects, logic, permutes). bench.py prices each class at the issue rate the VALU probe "
+        "measures in the same run; source_hash identifies the kernel's sources and bench.py "
+        "ignores a record taken on other sources.")}
+    for key, (tag, match, src, kern) in MIX_RUNS.items():
+        A = pmc_dispatches(os.path.join(root, f"mixA_{tag}"), match)
+        C = pmc_dispatches(os.path.join(root, f"mixC_{tag}"), match)
+        if not A or not C:
+            raise ValueError(f"{key}: no '{match}' dispatches under {root}/mix[AC]_{tag}")
+        tot = mean(A, "SQ_INSTS_VALU")
+        cls = {c: mean(A, f"SQ_INSTS_VALU_{c}") for c in
+               ("FMA_F32", "MUL_F32", "ADD_F32", "TRANS_F32", "INT32", "INT64", "CVT")}
+        cls["F64"] = sum(mean(C, f"SQ_INSTS_VALU_{k}_F64") for k in ("FMA", "ADD", "MUL", "TRANS"))
+        cls["OTHER"] = max(0.0, tot - sum(cls.values()))
+        mix[key] = {"kernel": kern, "sources": src, "source_hash": kernel_source_hash(src),
+                    "dispatches": [len(A), len(C)], "per_launch": cls,
+                    "sq_insts_valu_raw": [d["SQ_INSTS_VALU"] for d in A],
+                    "lanes_active_per_instr": (mean(C, "SQ_THREAD_CYCLES_VALU")
+                                               / (64 * mean(C, "SQ_ACTIVE_INST_VALU"))),
+                    "sq_waves": mean(C, "SQ_WAVES"),
+                    "sq_busy_cycles": [d["SQ_BUSY_CYCLES"] for d in C]}
+
+    def sums(d, match):
+        return [sum(c.values()) for c in pmc_dispatches(os.path.join(root, d), match)]
+
+    # the runtime's blit copy of 1 GiB (--copy-calibration); smaller
+    # dispatches of the same kernel are torch's own set-up copies
+    cf = [v for v in sums("pmc_copy_FETCH", "copyBuffer") if v > 1e5]
+    cw = [v for v in sums("pmc_copy_WRITE", "copyBuffer") if v > 1e5]
+    if not cf or not cw:
+        raise ValueError(f"no 1 GiB copy dispatches under {root}/pmc_copy_*")
+    fs, ws = 1048576 / (sum(cf) / len(cf)), 1048576 / (sum(cw) / len(cw))
+    tr = {"_doc": (
+        "HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per dispatch), "
+        f"each scaled by the ratio the same counter reads for a 1 GiB device copy (bench.py "
+        f"--copy-calibration): fetch x{fs:.3f}, write x{ws:.3f}; written by bench.py "
+        "--record-counters. source_hash identifies the kernel's translation-unit sources "
+        "(bench.kernel_source_hash over `sources`); bench.py reports null once they change.")}
+    for key, (tag, kern) in TRAFFIC_RUNS.items():
+        f = sums(f"pmc_{tag}_FETCH", "tsit5_sorted")
+        w = sums(f"pmc_{tag}_WRITE", "tsit5_sorted")
+        if not f or len(w) < 2:
+            raise ValueError(f"{key}: need the kernel's dispatches under {root}/pmc_{tag}_*")
+        rd = sum(f) / len(f) * 1024 * fs
+        wr = sum(w[1:]) / len(w[1:]) * 1024 * ws  # the first dispatch is cold
+        tr[key] = {"kernel": kern, "sources": TSIT5_SOURCES,
+                   "source_hash": kernel_source_hash(TSIT5_SOURCES),
+                   "fetch_kib_raw": [round(v) for v in f], "write_kib_raw": [round(v) for v in w],
+                   "hbm_read_bytes_per_launch": rd, "hbm_write_bytes_per_launch": wr,
+                   "hbm_bytes_per_launch": rd + wr,
+                   "algorithmic_bytes_per_launch": HEADLINE_ALG_BYTES,
+                   "traffic_over_algorithmic": (rd + wr) / HEADLINE_ALG_BYTES}
+    for name, rec in (("valu_mix.json", mix), ("traffic.json", tr)):
+        with open(os.path.join(out_dir, name), "w") as fh:
+            json.dump(rec, fh, indent=1)
+    return mix, tr
 
 
 # Vector-ALU instruction classes of the rocprofv3 SQ_INSTS_VALU_* counters and
@@ -862,6 +981,12 @@ def train_batch_scaling(s, P, U, y, batches=(4096, 16384, 65536), epochs=2):
 
 def main():
     args = parse()
+    if args.record_counters:
+        mix, tr = record_counters(args.record_counters)
+        print(json.dumps({"recorded": {
+            "valu_mix": {k: v["per_launch"] for k, v in mix.items() if k != "_doc"},
+            "traffic": {k: v["traffic_over_algorithmic"] for k, v in tr.items() if k != "_doc"}}}))
+        return
     if args.copy_calibration:
         copy_calibration()
         return

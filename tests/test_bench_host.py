@@ -101,3 +101,62 @@ def test_coissue_ceiling_counts_the_inference_kernels_work():
     assert abs(r["frac"] - want_s * 1e3 / 10.0) < 1e-12
     # 24 products of 16 x 16 x 32 per wave-iteration against the bf16 peak
     assert abs(r["probe_products_frac_of_peak"] - 2e9 * 24 * 16384 / 2.5e15) < 1e-12
+
+
+def _write_pmc(d, rows):
+    """A rocprofv3 counter CSV with the columns record_counters reads."""
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "run_counter_collection.csv"), "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for disp, kern, name, val in rows:
+            fh.write(f'{disp},"{kern}",{name},{val}\n')
+
+
+def test_record_counters_from_pmc_csvs(tmp_path):
+    """bench.py --record-counters: per-dispatch sums of each counter over the
+    CSV's rows (one row per XCD here), means over the kernel's dispatches,
+    OTHER as the uncounted remainder, lane activity from the F64 pass, and
+    HBM bytes scaled by the 1 GiB copy's counter reading (first write
+    dispatch dropped as cold); other kernels' rows are ignored."""
+    root = tmp_path / "pmc"
+    cls = {"FMA_F32": 40, "MUL_F32": 20, "ADD_F32": 5, "TRANS_F32": 3, "INT32": 2, "INT64": 1,
+           "CVT": 1}
+    for key, (tag, match, _src, _k) in bench.MIX_RUNS.items():
+        kern = f"void ens::{match}(ens::LaunchArgs)"
+        a, c = [], []
+        for disp, scale in ((1, 1.0), (2, 3.0)):
+            for xcd in range(2):  # each counter read on two XCDs, half each
+                a.append((disp, kern, "SQ_INSTS_VALU", 50 * scale))
+                for k, v in cls.items():
+                    a.append((disp, kern, f"SQ_INSTS_VALU_{k}", v / 2 * scale))
+                for k in ("FMA", "ADD", "MUL", "TRANS"):
+                    c.append((disp, kern, f"SQ_INSTS_VALU_{k}_F64", 1 / 2 * scale))
+                c += [(disp, kern, "SQ_ACTIVE_INST_VALU", 100 / 2), (disp, kern, "SQ_THREAD_CYCLES_VALU",
+                      0.75 * 64 * 100 / 2), (disp, kern, "SQ_WAVES", 8 / 2),
+                      (disp, kern, "SQ_BUSY_CYCLES", 1000 / 2)]
+            a.append((disp + 10, "other_kernel", "SQ_INSTS_VALU", 1e9))
+        _write_pmc(str(root / f"mixA_{tag}"), a)
+        _write_pmc(str(root / f"mixC_{tag}"), c)
+    copy = "__amd_rocclr_copyBuffer"
+    _write_pmc(str(root / "pmc_copy_FETCH"), [(1, copy, "FETCH_SIZE", 524288), (2, copy, "FETCH_SIZE", 12)])
+    _write_pmc(str(root / "pmc_copy_WRITE"), [(1, copy, "WRITE_SIZE", 1048576)])
+    for tag in ("h", "st"):
+        k = "void ens::tsit5_sorted<float, ens::Lorenz, 256, 1, false>(ens::LaunchArgs)"
+        _write_pmc(str(root / f"pmc_{tag}_FETCH"), [(1, k, "FETCH_SIZE", 1000), (2, k, "FETCH_SIZE", 3000)])
+        _write_pmc(str(root / f"pmc_{tag}_WRITE"), [(1, k, "WRITE_SIZE", 9e9), (2, k, "WRITE_SIZE", 4000)])
+    out = tmp_path / "out"
+    out.mkdir()
+    mix, tr = bench.record_counters(str(root), str(out))
+    r = mix["lorenz_fp32/tsit5/sorted/dense"]
+    assert r["dispatches"] == [2, 2]
+    # means over dispatches of scale 1 and 3: twice the base counts
+    assert r["per_launch"]["FMA_F32"] == 80 and r["per_launch"]["F64"] == 8
+    # SQ_INSTS_VALU averages 200; the counted classes 144, F64 8
+    assert r["per_launch"]["OTHER"] == 200 - 2 * sum(cls.values()) - 8
+    assert abs(r["lanes_active_per_instr"] - 0.75) < 1e-12
+    assert r["source_hash"] == bench.kernel_source_hash(bench.TSIT5_SOURCES)
+    t = tr["lorenz_fp32/sorted/dense"]
+    assert t["hbm_read_bytes_per_launch"] == 2000 * 1024 * 2.0   # fetch scale 1 GiB / 512 MiB read
+    assert t["hbm_write_bytes_per_launch"] == 4000 * 1024 * 1.0  # first dispatch dropped
+    assert json.load(open(out / "valu_mix.json"))["gbm/em/plain"]["per_launch"]["MUL_F32"] == 40
+    assert json.load(open(out / "traffic.json"))["lorenz_fp32/sorted_staged/dense"]["fetch_kib_raw"] == [1000, 3000]
