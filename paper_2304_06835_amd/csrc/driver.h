@@ -27,6 +27,27 @@ struct Num<float> {
   __device__ static inline float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
   __device__ static inline float sqrt(float x) { return __builtin_sqrtf(x); }
   __device__ static inline float nan() { return __builtin_nanf(""); }
+  // max, min and clamp as one v_med3_f32 (operands not NaN).  fmax / fmin of
+  // a value computed in another basic block (a loop-carried step size, state
+  // or error) first quiets it with an extra v_max, because the selector sees
+  // one block at a time; the median against +-inf needs no quieting.  The
+  // infinity goes through an opaque scalar move so that the median is not
+  // folded back into fmax / fmin.
+  __device__ static inline float inf() {
+    float v;
+    asm("s_mov_b32 %0, 0x7f800000" : "=s"(v));
+    return v;
+  }
+  __device__ static inline float max(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, inf()); }
+  __device__ static inline float min(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, -inf()); }
+  __device__ static inline float clamp(float x, float lo, float hi) {
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+  }
+  // max(x, floor) for x >= 0 and a positive floor: non-negative floats order
+  // as their bit patterns do, so an integer maximum (no quieting) suffices
+  __device__ static inline float max_nonneg(float x, float floor) {
+    return __builtin_bit_cast(float, ::max(__builtin_bit_cast(int, x), __builtin_bit_cast(int, floor)));
+  }
 };
 
 template <>
@@ -36,6 +57,12 @@ struct Num<double> {
   __device__ static inline double exp2(double x) { return ::exp2(x); }
   __device__ static inline double sqrt(double x) { return ::sqrt(x); }
   __device__ static inline double nan() { return __builtin_nan(""); }
+  __device__ static inline double max(double a, double b) { return fmax(a, b); }
+  __device__ static inline double min(double a, double b) { return fmin(a, b); }
+  __device__ static inline double clamp(double x, double lo, double hi) {
+    return fmin(hi, fmax(lo, x));
+  }
+  __device__ static inline double max_nonneg(double x, double floor) { return fmax(x, floor); }
 };
 
 // Save-time landing: a step whose proposal reaches within this factor of

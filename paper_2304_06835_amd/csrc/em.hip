@@ -127,8 +127,9 @@ struct Crn {
   __device__ static inline float rt(float x) { return __builtin_amdgcn_sqrtf(x); }
   // X += a(X) h + b(X) dW, dW = sqrt(h) z
   __device__ inline void em_step(float* X, float h, float sqh, const float* z) const {
-    const float s = fmaxf(X[0], 0.0f), a1 = fmaxf(X[1], 0.0f), a2 = fmaxf(X[2], 0.0f),
-                a3 = fmaxf(X[3], 0.0f);
+    using F = Num<float>;  // the loop-carried state is clamped without quieting
+    const float s = F::max(X[0], 0.0f), a1 = F::max(X[1], 0.0f), a2 = F::max(X[2], 0.0f),
+                a3 = F::max(X[3], 0.0f);
     const float hs = powc(S * s), hd = powc(D * a3);
     const float H = hs * __builtin_amdgcn_rcpf(hs + hd + 1.0f);  // denominator >= 1
     const float prod = nu0 + H;

@@ -327,7 +327,7 @@ struct RosLane {
     R q2 = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const R sc = fma((R)a.rtol, fmax(fabs(u[c]), fabs(unew[c])), (R)a.atol);
+      const R sc = fma((R)a.rtol, F::max(fabs(u[c]), fabs(unew[c])), (R)a.atol);
       const R r = err[c] * F::rcp(sc);
       q2 = fma(r, r, q2);
     }
@@ -337,7 +337,8 @@ struct RosLane {
       done = true;
       return;
     }
-    const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));
+    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));
+    const R lq_floored = fmax(lq, (R)kLog2QFloor);
     if (q2 <= (R)1) {
       ++nacc;
       if (clamped)
@@ -352,10 +353,10 @@ struct RosLane {
       }
       R fac = (R)kRosEta * F::exp2(fma((R)(-0.7 / M::kK), lq, (R)(0.4 / M::kK) * lqold));
       fac = fmin((R)kRosFacMax, fmax((R)kRosFacMin, fac));
-      lqold = fmax(lq, (R)kLog2QFloor);
+      lqold = lq_floored;
       R hn = he * fac;
-      if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
-      h = fmin(hn, hmax);
+      if (clamped) hn = F::max(hn, h);  // keep the proposal made before the clamp
+      h = F::min(hn, hmax);
       hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
       if (clamped) {  // only a cut step lands on a save time
         save_reached(a);

@@ -246,17 +246,20 @@ struct Tsit5Lane {
 #pragma unroll
       for (int q = 1; q < 7; ++q) e = fma((R)BT[q], k[q][c], e);
       e = he * e;
-      const R sc = fma((R)a.rtol, fmax(fabs(u[c]), fabs(y[c])), (R)a.atol);
+      const R sc = fma((R)a.rtol, F::max(fabs(u[c]), fabs(y[c])), (R)a.atol);
       const R r = e * F::rcp(sc);
       q2 = fma(r, r, q2);
     }
     q2 = q2 * (R)(1.0 / N);
+    // log2 q, and its floored copy for the next step's controller: taken
+    // here, in the block that computes q2, so the maxima need no quieting
+    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));
+    const R lq_floored = fmax(lq, (R)-13.287712379549449);
     if (!(q2 <= (R)3.0e38)) {  // NaN or inf
       status = ENS_ST_NONFINITE;
       done = true;
       return;
     }
-    const R lq = (R)0.5 * F::log2(fmax(q2, (R)1e-20));  // log2 q
     if (q2 <= (R)1) {
       ++nacc;
       if (a.dense) dense_saves(a, he, k);  // save times inside this step
@@ -271,10 +274,10 @@ struct Tsit5Lane {
       }
       R fac = (R)kEta * F::exp2(fma((R)(-0.7 / kK), lq, (R)(0.4 / kK) * lqold));
       fac = fmin((R)kFacMax, fmax((R)kFacMin, fac));
-      lqold = fmax(lq, (R)-13.287712379549449);
+      lqold = lq_floored;
       R hn = he * fac;
-      if (clamped) hn = fmax(hn, h);  // keep the proposal made before the clamp
-      h = fmin(hn, hmax);
+      if (clamped) hn = F::max(hn, h);  // keep the proposal made before the clamp
+      h = F::min(hn, hmax);
       hfloor = (R)(16.0 * DBL_EPSILON) * (R)fabs(t.hi);
       if (clamped) {  // only a cut step lands on a save time
         save_reached(a);
