@@ -228,29 +228,41 @@ struct Tsit5Lane {
     for (int c = 0; c < N; ++c) k[0][c] = k1[c];
 #pragma unroll
     for (int s = 1; s < 7; ++s) {
+      if (s <= 2) {  // one or two terms: he a_sq once per lane, then one FMA per term
+        R ha[2];
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        R acc = (R)TA[s][0] * k[0][c];
+        for (int q = 0; q < s; ++q) ha[q] = he * (R)TA[s][q];
 #pragma unroll
-        for (int q = 1; q < s; ++q) acc = fma((R)TA[s][q], k[q][c], acc);
-        y[c] = fma(he, acc, u[c]);
+        for (int c = 0; c < N; ++c) {
+          y[c] = fma(ha[0], k[0][c], u[c]);
+#pragma unroll
+          for (int q = 1; q < s; ++q) y[c] = fma(ha[q], k[q][c], y[c]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          R acc = (R)TA[s][0] * k[0][c];
+#pragma unroll
+          for (int q = 1; q < s; ++q) acc = fma((R)TA[s][q], k[q][c], acc);
+          y[c] = fma(he, acc, u[c]);
+        }
       }
       S::f(p, y, k[s]);
     }
 
-    // scaled error proportion, squared (avoids a square root)
+    // scaled error proportion, squared (avoids a square root); the step size
+    // and the mean's 1/N scale the sum once
     R q2 = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
       R e = (R)BT[0] * k[0][c];
 #pragma unroll
       for (int q = 1; q < 7; ++q) e = fma((R)BT[q], k[q][c], e);
-      e = he * e;
       const R sc = fma((R)a.rtol, F::max(fabs(u[c]), fabs(y[c])), (R)a.atol);
       const R r = e * F::rcp(sc);
       q2 = fma(r, r, q2);
     }
-    q2 = q2 * (R)(1.0 / N);
+    q2 = q2 * (he * (he * (R)(1.0 / N)));
     // log2 q, and its floored copy for the next step's controller: taken
     // here, in the block that computes q2, so the maxima need no quieting
     const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));
