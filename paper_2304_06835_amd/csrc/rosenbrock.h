@@ -337,8 +337,7 @@ struct RosLane {
       done = true;
       return;
     }
-    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));
-    const R lq_floored = fmax(lq, (R)kLog2QFloor);
+    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));  // q2 >= 0
     if (q2 <= (R)1) {
       ++nacc;
       if (clamped)
@@ -353,7 +352,7 @@ struct RosLane {
       }
       R fac = (R)kRosEta * F::exp2(fma((R)(-0.7 / M::kK), lq, (R)(0.4 / M::kK) * lqold));
       fac = fmin((R)kRosFacMax, fmax((R)kRosFacMin, fac));
-      lqold = lq_floored;
+      lqold = fmax(lq, (R)kLog2QFloor);
       R hn = he * fac;
       if (clamped) hn = F::max(hn, h);  // keep the proposal made before the clamp
       h = F::min(hn, hmax);

@@ -263,15 +263,12 @@ struct Tsit5Lane {
       q2 = fma(r, r, q2);
     }
     q2 = q2 * (he * (he * (R)(1.0 / N)));
-    // log2 q, and its floored copy for the next step's controller: taken
-    // here, in the block that computes q2, so the maxima need no quieting
-    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));
-    const R lq_floored = fmax(lq, (R)-13.287712379549449);
     if (!(q2 <= (R)3.0e38)) {  // NaN or inf
       status = ENS_ST_NONFINITE;
       done = true;
       return;
     }
+    const R lq = (R)0.5 * F::log2(F::max_nonneg(q2, (R)1e-20));  // log2 q (q2 >= 0)
     if (q2 <= (R)1) {
       ++nacc;
       if (a.dense) dense_saves(a, he, k);  // save times inside this step
@@ -286,7 +283,7 @@ struct Tsit5Lane {
       }
       R fac = (R)kEta * F::exp2(fma((R)(-0.7 / kK), lq, (R)(0.4 / kK) * lqold));
       fac = fmin((R)kFacMax, fmax((R)kFacMin, fac));
-      lqold = lq_floored;
+      lqold = fmax(lq, (R)-13.287712379549449);
       R hn = he * fac;
       if (clamped) hn = F::max(hn, h);  // keep the proposal made before the clamp
       h = F::min(hn, hmax);
