@@ -67,6 +67,13 @@ __device__ inline T group_max(T x) {
   for (int m = kGroup / 2; m >= 1; m >>= 1) x = fmax(x, __shfl_xor(x, m, kGroup));
   return x;
 }
+// The same for FP32 values that are not NaN: one shuffle and one median per
+// level (an fmax of a shuffled value would first quiet it)
+__device__ inline float group_max_f(float x) {
+#pragma unroll
+  for (int m = kGroup / 2; m >= 1; m >>= 1) x = Num<float>::max(x, __shfl_xor(x, m, kGroup));
+  return x;
+}
 __device__ inline int group_lane() { return (int)(threadIdx.x & (kGroup - 1)); }
 // The group's bits of a wave-wide ballot.
 __device__ inline uint32_t group_bits(unsigned long long ballot) {
@@ -124,8 +131,19 @@ struct GroupW {
       // yet used (kr is a permutation of 0..D-1) and the NaN reaches x
       const double v = fabs(a[k]);
       const double cand = used ? -1.0 : (v == v ? v : __builtin_inf());
-      const double m = group_max(cand);
-      const int pk = __ffs(group_bits(__ballot(cand == m))) - 1;
+      // the maximum of the candidates rounded to FP32 first: rounding keeps
+      // order, so the lane of the exact maximum holds it, and when no other
+      // lane does, that lane is the pivot; otherwise (ties after rounding)
+      // the exact FP64 reduction decides, lowest lane first as before
+      const float cf = (float)cand;
+      const uint32_t top = group_bits(__ballot(cf == group_max_f(cf)));
+      int pk;
+      if (__popc(top) == 1) {
+        pk = __ffs(top) - 1;
+      } else {
+        const double m = group_max(cand);
+        pk = __ffs(group_bits(__ballot(cand == m))) - 1;
+      }
       const bool piv = r == pk;
       if (piv) {  // the pivot row goes to the group's LDS row unscaled
 #pragma unroll
